@@ -1,0 +1,143 @@
+"""Pins of the oracle's ordering (Alg. 1 with Eq. 3) against independent facts."""
+import itertools
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import varlingam as O
+
+
+def _order_violations(order, B0):
+    pos = {int(v): k for k, v in enumerate(order)}
+    eff, cau = np.nonzero(B0)
+    return int(sum(pos[int(i)] < pos[int(j)] for i, j in zip(eff, cau)))
+
+
+def test_hand_built_total_order_is_recovered():
+    rng = np.random.default_rng(0)
+    for m in (1, 2, 3, 7, 20):
+        true = rng.permutation(m)
+        pos = np.empty(m, int)
+        pos[true] = np.arange(m)
+        S = np.where(pos[:, None] < pos[None, :], 1.0, -1.0) * rng.uniform(0.1, 1, (m, m))
+        S = np.triu(S, 1) - np.triu(S, 1).T          # antisymmetric, sign from the order
+        S[np.tril_indices(m, -1)] = -S.T[np.tril_indices(m, -1)]
+        order, margin = O.approx_order(S)
+        assert list(order) == list(true)
+        assert margin[-1] == np.inf and np.all(margin[:-1] > 0)
+
+
+def test_ties_go_to_lowest_index_and_margin_zero():
+    order, margin = O.approx_order(np.zeros((4, 4)))
+    assert list(order) == [0, 1, 2, 3]
+    assert np.all(margin[:-1] == 0.0)
+
+
+def test_pure_python_loop_form_small():
+    """Alg. 1 written as explicit loops over U (tiny m), compared element by element."""
+    rng = np.random.default_rng(4)
+    for m in (2, 3, 5, 8):
+        A = rng.normal(size=(m, m))
+        S = A - A.T
+        U = list(range(m))
+        ref = []
+        for _ in range(m):
+            best, best_val = None, None
+            for i in U:
+                tot = 0.0
+                for j in U:
+                    if j != i and S[i, j] < 0:
+                        tot += S[i, j] * S[i, j]
+                if best_val is None or tot < best_val:
+                    best, best_val = i, tot
+            ref.append(best)
+            U.remove(best)
+        order, _ = O.approx_order(S)
+        assert list(order) == ref
+
+
+def test_m2_heuristic_equals_iterative_and_first_pick_equal():
+    for seed in range(5):
+        inst = synth.make_custom(2, 2000, 1, "uniform", seed)
+        _, _, E = O.fit_var(inst.X_parity, 1)
+        _, _, S = O.pairwise_stats(E)
+        order, _ = O.approx_order(S)
+        assert list(order) == list(O.directlingam_iterative(E))
+    for seed in range(3):
+        inst = synth.make_custom(6, 2000, 1, "laplace", seed)
+        _, _, E = O.fit_var(inst.X_parity, 1)
+        _, _, S = O.pairwise_stats(E)
+        order, _ = O.approx_order(S)
+        assert order[0] == O.directlingam_iterative(E)[0]
+
+
+@pytest.mark.slow
+def test_tiny_m_agreement_with_iterative():
+    """Brute force on tiny inputs: for strongly non-Gaussian (uniform) data with m <= 5 the
+    heuristic and the full iterative DirectLiNGAM recover orders that are both consistent with
+    the true DAG in most seeds (statistical; the heuristic has no guarantee)."""
+    agree = 0
+    seeds = range(30)
+    for seed in seeds:
+        m = 3 + seed % 3
+        inst = synth.make_custom(m, 5000, 1, "uniform", seed, edge_prob=0.5, w_lo=0.4, w_hi=0.9)
+        _, _, E = O.fit_var(inst.X_parity, 1)
+        _, _, S = O.pairwise_stats(E)
+        h, _ = O.approx_order(S)
+        it = O.directlingam_iterative(E)
+        if _order_violations(h, inst.B0) == _order_violations(it, inst.B0) == 0:
+            agree += 1
+    assert agree >= 0.9 * len(seeds)
+
+
+@pytest.mark.slow
+def test_recovery_of_generating_order_small_workload():
+    viol = []
+    for seed in range(10):
+        inst = synth.make_instance(synth.SMALL, seed)
+        res = O.fit(inst.X_parity, 1)
+        viol.append(_order_violations(res["order"], inst.B0))
+    assert np.median(viol) == 0
+
+
+def test_aggregate_scores_over_current_set():
+    S = np.array([[0.0, -1.0, 2.0], [1.0, 0.0, -3.0], [-2.0, 3.0, 0.0]])
+    np.testing.assert_array_equal(O.aggregate_scores(S, [0, 1, 2]), [1.0, 9.0, 4.0])
+    np.testing.assert_array_equal(O.aggregate_scores(S, [0, 2]), [0.0, 4.0])
+
+
+def test_order_is_a_permutation():
+    A = np.random.default_rng(1).normal(size=(30, 30))
+    order, _ = O.approx_order(A - A.T)
+    assert sorted(order) == list(range(30))
+
+
+def test_incremental_update_equals_recompute():
+    """Removing c from U lowers every M_i by min(0, S[i, c])^2 (the O(m^2) form a GPU pass can
+    use) -- checked against the oracle's from-scratch O(m^3) recompute."""
+    rng = np.random.default_rng(8)
+    A = rng.normal(size=(25, 25))
+    S = A - A.T
+    order, _ = O.approx_order(S)
+    U = list(range(25))
+    M = O.aggregate_scores(S, U)
+    Md = dict(zip(U, M))
+    for c in order[:-1]:
+        U.remove(int(c))
+        for i in U:
+            Md[i] -= min(0.0, S[i, c]) ** 2
+        ref = O.aggregate_scores(S, U)
+        np.testing.assert_allclose([Md[i] for i in U], ref, atol=1e-12)
+
+
+def test_exhaustive_tiny_permutations():
+    """For m = 4, every relabelling of the variables relabels the order (equivariance)."""
+    A = np.random.default_rng(2).normal(size=(4, 4))
+    S = A - A.T
+    order, _ = O.approx_order(S)
+    for P in itertools.permutations(range(4)):
+        P = np.array(P)
+        oP, _ = O.approx_order(S[np.ix_(P, P)])
+        # variable k of the permuted problem is variable P[k] of the original one
+        assert list(P[oP]) == list(order)
