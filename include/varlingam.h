@@ -1,0 +1,153 @@
+/*
+ * varlingam.h -- C ABI of the MI355X (gfx950) heuristic VarLiNGAM library.
+ *
+ * The library computes the hot path of the heuristic VarLiNGAM of Jiao, Guo and Luk,
+ * "Scalable Time-Series Causal Discovery with Approximate Causal Ordering":
+ *   VAR fit (Sec. 2.1)  ->  one-time precompute of every pairwise entropy statistic
+ *   (Sec. 3 steps 1-3, Eqs. 1-2; Sec. 4.2 steps 1-2)  ->  lookup-only ordering
+ *   (Alg. 1 with Eq. 3)  ->  B0 and lag matrices B_tau (Sec. 4, Sec. 2.1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All array arguments are DEVICE pointers owned by the caller.  Matrices are row-major
+ *   with an explicit leading dimension (in elements).  Nothing is allocated inside the
+ *   library: scratch memory comes from the caller's workspace `ws` of `ws_bytes` bytes,
+ *   sized by the matching *_workspace_bytes() query and aligned to 256 bytes.
+ * - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL = default stream).
+ *   No entry point synchronises the stream.
+ * - Errors a host check can see (null pointers, shapes, leading dimensions, workspace too
+ *   small, unsupported sizes) are returned synchronously and nothing is enqueued.
+ * - Errors that depend on the data (a constant column, |rho| = 1, a singular design, a
+ *   non-finite input) are written by the kernels to the int32 `*dev_status` on the stream
+ *   (VL_OK = 0 is written first by every call).  The caller reads it after synchronising.
+ *   When dev_status holds an error the numerical outputs of that call are unspecified.
+ * - Calls are reentrant given distinct workspaces and status words.
+ */
+#ifndef VARLINGAM_H
+#define VARLINGAM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  VL_OK = 0,
+  VL_ERR_INVALID_ARG = -1, /* null pointer, bad enum, leading dimension too small        */
+  VL_ERR_SHAPE = -2,       /* sizes outside what the method or the library supports      */
+  VL_ERR_DEGENERATE = -3,  /* zero-variance column or a pair with 1 - rho^2 < 1e-12      */
+  VL_ERR_SINGULAR = -4,    /* VAR design (or residual covariance) not positive definite  */
+  VL_ERR_NONFINITE = -5,   /* NaN or Inf in the input                                    */
+  VL_ERR_WORKSPACE = -6,   /* workspace smaller than the *_workspace_bytes() query       */
+  VL_ERR_HIP = -7          /* a HIP launch failed                                        */
+} vl_status;
+
+/* Arithmetic of the GEMM-shaped stages (the input series and E are always FP32; the pairwise
+ * moments are always evaluated per sample in FP32, summed per wave in FP32 and across waves in
+ * FP64; the score combination, the ordering and the B estimation always run in FP64).
+ *   VL_PREC_FP32:  VAR Gram matrices, VAR residual GEMM and residual covariance by FP32 MFMA
+ *                  with FP32 sums; FP64 Cholesky of the FP32 Gram.
+ *   VL_PREC_MIXED: the same three products by FP64 MFMA on the widened FP32 data (exact
+ *                  products, FP64 sums); FP64 Cholesky.
+ *   VL_PREC_BF16:  reserved (BF16 VAR Gram repaired by FP64 refinement); currently rejected with
+ *                  VL_ERR_INVALID_ARG. */
+typedef enum { VL_PREC_FP32 = 0, VL_PREC_MIXED = 1, VL_PREC_BF16 = 2 } vl_precision;
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char* varlingam_status_string(int status);
+
+/* ------------------------------------------------------------------------------------- */
+/* VAR(p) least-squares fit (Sec. 2.1: VarLiNGAM first fits a VAR model and runs the      */
+/* ordering on its residuals).                                                            */
+/*                                                                                        */
+/*   x(t) = sum_{tau=1..p} M_tau x(t - tau) + c + e(t),   t = p .. n-1                     */
+/*                                                                                        */
+/* X         n x m series, row t = sample t, leading dimension ldx >= m (float32).        */
+/* M         out, p x m x m (float64): M[(tau-1)*m*m + i*m + k] = coefficient of           */
+/*           x_k(t - tau) in the equation of x_i(t).                                       */
+/* intercept out, m (float64).                                                             */
+/* E         out, (n - p) x m residuals (float32), leading dimension lde >= m.             */
+/* Host errors: m < 1, p < 1, n - p <= m p + 1, m p > 4096 -> VL_ERR_SHAPE.                */
+/* Device errors: VL_ERR_NONFINITE, VL_ERR_SINGULAR (Gram of the centred lags not PD).     */
+/* ------------------------------------------------------------------------------------- */
+size_t varlingam_fit_var_workspace_bytes(int64_t n, int64_t m, int p, int prec);
+int varlingam_fit_var(const float* X, int64_t n, int64_t m, int64_t ldx, int p, int prec,
+                      double* M, double* intercept, float* E, int64_t lde, void* ws,
+                      size_t ws_bytes, int32_t* dev_status, void* stream);
+
+/* ------------------------------------------------------------------------------------- */
+/* Precompute of every pairwise statistic, once (Sec. 4.2 steps 1-2; Alg. 1 first two     */
+/* lines), from the unaltered residual matrix.                                            */
+/*                                                                                        */
+/* Each column e_i is standardised with population moments (Sec. 3 step 1) into x_i;       */
+/* for every ordered pair i != j the residual r_{i<-j} = x_i - cov/var x_j of Eq. 1 is      */
+/* re-standardised to u_{i<-j} and its entropy is approximated (Eq. 2) by                  */
+/*   H(u) = (1 + ln 2pi)/2 - 79.047 (E[log cosh u] - 0.37457)^2 - 7.4129 (E[u e^{-u^2/2}])^2 */
+/* Outputs (all float64, row-major m x m, leading dimension m):                            */
+/*   Hx[i]      = H(x_i)                                           (size m)                */
+/*   Hr[i*m+j]  = H(u_{i<-j}), diagonal 0                                                  */
+/*   S[i*m+j]   = (Hx[j] + Hr[i,j]) - (Hx[i] + Hr[j,i]) = T_{j<-i} - T_{i<-j}; S = -S^T      */
+/*                exactly; S[i,j] > 0 favours i before j                                   */
+/*   Cov[i*m+j] = population covariance of e_i, e_j (feeds estimate_B)  -- may be NULL      */
+/* E is n_eff x m float32 with leading dimension lde >= m.                                  */
+/* Host errors: m < 2, n_eff < 2, m > 65536 -> VL_ERR_SHAPE.                                */
+/* Device errors: VL_ERR_NONFINITE, VL_ERR_DEGENERATE.                                      */
+/* ------------------------------------------------------------------------------------- */
+size_t pairwise_stats_workspace_bytes(int64_t n_eff, int64_t m, int prec);
+int pairwise_stats(const float* E, int64_t n_eff, int64_t m, int64_t lde, int prec, double* Hx,
+                   double* Hr, double* S, double* Cov, void* ws, size_t ws_bytes,
+                   int32_t* dev_status, void* stream);
+
+/* ------------------------------------------------------------------------------------- */
+/* Lookup-only causal ordering (Alg. 1 main loop with Eq. 3): m steps over the static S.  */
+/* At step k, with U the variables not yet ordered,                                       */
+/*   M_i = sum_{j in U, j != i} min(0, S[i,j])^2,   c_k = argmin_{i in U} M_i              */
+/* (exact ties -> lowest index), then U <- U \ {c_k}.                                      */
+/* S        in, m x m float64 (leading dimension m), antisymmetric.                        */
+/* order    out, m int32: order[k] = c_k.                                                  */
+/* margin   out, m float64: second-smallest minus smallest M at step k; +inf at the last.  */
+/* Host errors: m < 1 or m > 16384 -> VL_ERR_SHAPE.                                         */
+/* ------------------------------------------------------------------------------------- */
+size_t approx_order_workspace_bytes(int64_t m);
+int approx_order(const double* S, int64_t m, int32_t* order, double* margin, void* ws,
+                 size_t ws_bytes, int32_t* dev_status, void* stream);
+
+/* ------------------------------------------------------------------------------------- */
+/* B0 and lag matrices from the order (Sec. 4: estimation of the instantaneous matrix B0; */
+/* Sec. 2.1: VarLiNGAM lag matrices).                                                     */
+/*   B0[K_k, K_<k] = least-squares coefficients of e_{K_k} on its predecessors, obtained   */
+/*                   from the LDL^T factor of the order-permuted covariance:               */
+/*                   Sigma_KK = L D L^T,  B0_KK = I - L^{-1};  every other entry 0;         */
+/*   B_tau = (I - B0) M_tau.                                                               */
+/* Cov   in, m x m float64 population covariance of the residuals (from pairwise_stats).  */
+/* M     in, p x m x m float64 (from varlingam_fit_var); may be NULL when p == 0.          */
+/* order in, m int32 permutation (from approx_order).                                      */
+/* B0    out, m x m float64.   Blag out, p x m x m float64 (may be NULL when p == 0).       */
+/* Host errors: m < 1, m > 16384, p < 0 -> VL_ERR_SHAPE.                                    */
+/* Device errors: VL_ERR_SINGULAR (Cov not positive definite), VL_ERR_INVALID_ARG (order   */
+/* is not a permutation).                                                                  */
+/* ------------------------------------------------------------------------------------- */
+size_t estimate_B_workspace_bytes(int64_t m, int p);
+int estimate_B(const double* Cov, const double* M, const int32_t* order, int64_t m, int p,
+               double* B0, double* Blag, void* ws, size_t ws_bytes, int32_t* dev_status,
+               void* stream);
+
+/* ------------------------------------------------------------------------------------- */
+/* Stage timing (diagnostics).  varlingam_profile_enable(stages) starts recording a HIP    */
+/* event pair, on the caller's stream, around every launch of the named stages ("*" = all; */
+/* a comma-separated list; NULL or "" = off) and clears earlier totals.  Stage names:       */
+/*   var_gram, var_solve, var_residual, var_refine, pairwise_cov, pairwise_prep,            */
+/*   pairwise_moments, pairwise_combine, order, estimate_b.                                 */
+/* varlingam_profile_read() waits for the recorded events of one stage and returns the      */
+/* accumulated milliseconds and the number of recorded launches.  Thread-safe.              */
+/* ------------------------------------------------------------------------------------- */
+void varlingam_profile_enable(const char* stages);
+int varlingam_profile_read(const char* stage, double* total_ms, int64_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VARLINGAM_H */

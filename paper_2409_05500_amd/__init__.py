@@ -1,0 +1,16 @@
+"""Heuristic VarLiNGAM hot path on MI355X (gfx950): VAR fit, one-time pairwise entropy
+precompute, lookup-only causal ordering and B estimation, as hand-written HIP kernels behind a
+C ABI (include/varlingam.h).
+
+`import paper_2409_05500_amd` loads nothing; the HIP library is loaded on first use of the
+API (`paper_2409_05500_amd.api`), which raises if libvarlingam.so has not been built.
+"""
+_API = ("fit", "fit_var", "pairwise_stats", "approx_order", "estimate_B", "FitResult",
+        "DeviceStatus")
+
+
+def __getattr__(name):
+    if name in _API:
+        from . import api
+        return getattr(api, name)
+    raise AttributeError(name)

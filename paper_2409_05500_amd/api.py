@@ -1,0 +1,215 @@
+"""Torch-facing wrappers of the C ABI: they allocate outputs and workspace as CUDA (HIP)
+tensors, pass raw device pointers and the current stream, and check the status codes.
+All arithmetic happens in the HIP library."""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import PREC, check, lib
+
+
+def _stream_ptr(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _prec(prec) -> int:
+    if isinstance(prec, int):
+        return prec
+    return PREC[prec]
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    # torch's caching allocator returns 256-byte aligned blocks (512 in practice)
+    ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+    assert ws.data_ptr() % 256 == 0
+    return ws
+
+
+class DeviceStatus:
+    """The int32 status word the kernels write; read() synchronises and raises on error."""
+
+    def __init__(self, device):
+        self.t = torch.zeros(1, dtype=torch.int32, device=device)
+
+    @property
+    def ptr(self) -> int:
+        return self.t.data_ptr()
+
+    def read(self, where: str) -> None:
+        code = int(self.t.item())
+        check(code, where)
+
+
+def _require(t: torch.Tensor, dtype, name: str) -> None:
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.dim() == 2 and t.stride(1) != 1:
+        raise ValueError(f"{name} must have unit column stride")
+
+
+def fit_var(X: torch.Tensor, p: int, prec="mixed", status: "DeviceStatus | None" = None):
+    """VAR(p) least-squares fit with intercept.  X: n x m float32 device tensor.
+    Returns (M [p, m, m] f64, intercept [m] f64, E [n-p, m] f32)."""
+    _require(X, torch.float32, "X")
+    n, m = X.shape
+    dev = X.device
+    M = torch.empty((p, m, m), dtype=torch.float64, device=dev)
+    c = torch.empty(m, dtype=torch.float64, device=dev)
+    E = torch.empty((n - p, m), dtype=torch.float32, device=dev)
+    nb = lib.varlingam_fit_var_workspace_bytes(n, m, p, _prec(prec))
+    ws = _workspace(nb, dev)
+    st = status if status is not None else DeviceStatus(dev)
+    check(lib.varlingam_fit_var(X.data_ptr(), n, m, X.stride(0), p, _prec(prec), M.data_ptr(),
+                                c.data_ptr(), E.data_ptr(), E.stride(0), ws.data_ptr(),
+                                ws.numel(), st.ptr, _stream_ptr(dev)), "varlingam_fit_var")
+    if status is None:
+        st.read("varlingam_fit_var")
+    return M, c, E
+
+
+def pairwise_stats(E: torch.Tensor, prec="mixed", status: "DeviceStatus | None" = None):
+    """Hx [m], Hr [m, m], S [m, m], Cov [m, m] (all f64) from the n_eff x m residuals."""
+    _require(E, torch.float32, "E")
+    n_eff, m = E.shape
+    dev = E.device
+    Hx = torch.empty(m, dtype=torch.float64, device=dev)
+    Hr = torch.empty((m, m), dtype=torch.float64, device=dev)
+    S = torch.empty((m, m), dtype=torch.float64, device=dev)
+    Cov = torch.empty((m, m), dtype=torch.float64, device=dev)
+    nb = lib.pairwise_stats_workspace_bytes(n_eff, m, _prec(prec))
+    ws = _workspace(nb, dev)
+    st = status if status is not None else DeviceStatus(dev)
+    check(lib.pairwise_stats(E.data_ptr(), n_eff, m, E.stride(0), _prec(prec), Hx.data_ptr(),
+                             Hr.data_ptr(), S.data_ptr(), Cov.data_ptr(), ws.data_ptr(),
+                             ws.numel(), st.ptr, _stream_ptr(dev)), "pairwise_stats")
+    if status is None:
+        st.read("pairwise_stats")
+    return Hx, Hr, S, Cov
+
+
+def approx_order(S: torch.Tensor, status: "DeviceStatus | None" = None):
+    """(order [m] int32, margin [m] f64) from the m x m score matrix."""
+    _require(S, torch.float64, "S")
+    m = S.shape[0]
+    dev = S.device
+    order = torch.empty(m, dtype=torch.int32, device=dev)
+    margin = torch.empty(m, dtype=torch.float64, device=dev)
+    ws = _workspace(lib.approx_order_workspace_bytes(m), dev)
+    st = status if status is not None else DeviceStatus(dev)
+    check(lib.approx_order(S.contiguous().data_ptr(), m, order.data_ptr(), margin.data_ptr(),
+                           ws.data_ptr(), ws.numel(), st.ptr, _stream_ptr(dev)), "approx_order")
+    if status is None:
+        st.read("approx_order")
+    return order, margin
+
+
+def estimate_B(Cov: torch.Tensor, M: torch.Tensor, order: torch.Tensor,
+               status: "DeviceStatus | None" = None):
+    """(B0 [m, m], B_lags [p, m, m]) f64 from the residual covariance, VAR matrices and order."""
+    _require(Cov, torch.float64, "Cov")
+    m = Cov.shape[0]
+    p = M.shape[0] if M is not None else 0
+    dev = Cov.device
+    B0 = torch.zeros((m, m), dtype=torch.float64, device=dev)
+    Bl = torch.empty((max(p, 1), m, m), dtype=torch.float64, device=dev)
+    ws = _workspace(lib.estimate_B_workspace_bytes(m, p), dev)
+    st = status if status is not None else DeviceStatus(dev)
+    Mp = M.contiguous().data_ptr() if p > 0 else None
+    check(lib.estimate_B(Cov.contiguous().data_ptr(), Mp, order.contiguous().data_ptr(), m, p,
+                         B0.data_ptr(), Bl.data_ptr() if p > 0 else None, ws.data_ptr(),
+                         ws.numel(), st.ptr, _stream_ptr(dev)), "estimate_B")
+    if status is None:
+        st.read("estimate_B")
+    return B0, Bl[:p]
+
+
+@dataclass
+class FitResult:
+    M: torch.Tensor
+    intercept: torch.Tensor
+    E: torch.Tensor
+    Hx: torch.Tensor
+    Hr: torch.Tensor
+    S: torch.Tensor
+    Cov: torch.Tensor
+    order: torch.Tensor
+    margin: torch.Tensor
+    B0: torch.Tensor
+    B_lags: torch.Tensor
+
+
+def fit(X: torch.Tensor, p: int, prec="mixed", verify: bool = True) -> FitResult:
+    """The whole heuristic VarLiNGAM on the device: VAR fit -> pairwise precompute ->
+    ordering -> B0 and B_tau, enqueued back to back on the current stream.  With `verify`, the
+    four status words are read (one synchronisation) at the end."""
+    dev = X.device
+    st = [DeviceStatus(dev) for _ in range(4)]
+    M, c, E = fit_var(X, p, prec, status=st[0])
+    Hx, Hr, S, Cov = pairwise_stats(E, prec, status=st[1])
+    order, margin = approx_order(S, status=st[2])
+    B0, Bl = estimate_B(Cov, M, order, status=st[3])
+    if verify:
+        for s, name in zip(st, ("varlingam_fit_var", "pairwise_stats", "approx_order",
+                                "estimate_B")):
+            s.read(name)
+    return FitResult(M, c, E, Hx, Hr, S, Cov, order, margin, B0, Bl)
+
+
+class Fitter:
+    """Preallocated outputs and one shared workspace for repeated fits of one shape: run(X)
+    enqueues the four stages on the current stream with no host allocation and no
+    synchronisation; check() reads the four status words."""
+
+    STAGES = ("varlingam_fit_var", "pairwise_stats", "approx_order", "estimate_B")
+
+    def __init__(self, n: int, m: int, p: int, prec="mixed", device="cuda:0"):
+        dev = torch.device(device)
+        self.n, self.m, self.p, self.prec, self.dev = n, m, p, _prec(prec), dev
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.M = torch.empty((p, m, m), **f64)
+        self.intercept = torch.empty(m, **f64)
+        self.E = torch.empty((n - p, m), dtype=torch.float32, device=dev)
+        self.Hx = torch.empty(m, **f64)
+        self.Hr = torch.empty((m, m), **f64)
+        self.S = torch.empty((m, m), **f64)
+        self.Cov = torch.empty((m, m), **f64)
+        self.order = torch.empty(m, dtype=torch.int32, device=dev)
+        self.margin = torch.empty(m, **f64)
+        self.B0 = torch.empty((m, m), **f64)
+        self.B_lags = torch.empty((p, m, m), **f64)
+        need = max(lib.varlingam_fit_var_workspace_bytes(n, m, p, self.prec),
+                   lib.pairwise_stats_workspace_bytes(n - p, m, self.prec),
+                   lib.approx_order_workspace_bytes(m), lib.estimate_B_workspace_bytes(m, p))
+        if need == 0:
+            raise ValueError(f"unsupported shape n={n} m={m} p={p}")
+        self.ws = _workspace(need, dev)
+        self.status = torch.zeros(4, dtype=torch.int32, device=dev)
+
+    def run(self, X: torch.Tensor) -> None:
+        _require(X, torch.float32, "X")
+        if tuple(X.shape) != (self.n, self.m):
+            raise ValueError(f"X must be {self.n} x {self.m}")
+        n, m, p, pr = self.n, self.m, self.p, self.prec
+        s = _stream_ptr(self.dev)
+        ws, nb = self.ws.data_ptr(), self.ws.numel()
+        st = self.status.data_ptr()
+        check(lib.varlingam_fit_var(X.data_ptr(), n, m, X.stride(0), p, pr, self.M.data_ptr(),
+                                    self.intercept.data_ptr(), self.E.data_ptr(), m, ws, nb, st,
+                                    s), "varlingam_fit_var")
+        check(lib.pairwise_stats(self.E.data_ptr(), n - p, m, m, pr, self.Hx.data_ptr(),
+                                 self.Hr.data_ptr(), self.S.data_ptr(), self.Cov.data_ptr(), ws,
+                                 nb, st + 4, s), "pairwise_stats")
+        check(lib.approx_order(self.S.data_ptr(), m, self.order.data_ptr(),
+                               self.margin.data_ptr(), ws, nb, st + 8, s), "approx_order")
+        check(lib.estimate_B(self.Cov.data_ptr(), self.M.data_ptr(), self.order.data_ptr(), m, p,
+                             self.B0.data_ptr(), self.B_lags.data_ptr(), ws, nb, st + 12, s),
+              "estimate_B")
+
+    def check(self) -> None:
+        for code, name in zip(self.status.cpu().tolist(), self.STAGES):
+            check(int(code), name)

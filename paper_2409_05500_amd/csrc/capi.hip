@@ -1,0 +1,128 @@
+// extern "C" entry points: argument validation, workspace carving, status handling.
+#include "estimate_b.hpp"
+#include "order.hpp"
+#include "pairwise.hpp"
+#include "var_fit.hpp"
+
+using namespace vl;
+
+namespace {
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline bool valid_prec(int prec) { return prec == VL_PREC_FP32 || prec == VL_PREC_MIXED; }
+
+inline bool aligned256(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
+
+int begin(int32_t* dev_status, hipStream_t stream) {
+  reset_status_kernel<<<1, 64, 0, stream>>>(dev_status);
+  return hipGetLastError() == hipSuccess ? VL_OK : VL_ERR_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* varlingam_status_string(int status) {
+  switch (status) {
+    case VL_OK: return "ok";
+    case VL_ERR_INVALID_ARG: return "invalid argument";
+    case VL_ERR_SHAPE: return "unsupported shape";
+    case VL_ERR_DEGENERATE: return "degenerate data (zero variance or |rho| = 1)";
+    case VL_ERR_SINGULAR: return "matrix not positive definite";
+    case VL_ERR_NONFINITE: return "non-finite input";
+    case VL_ERR_WORKSPACE: return "workspace too small";
+    case VL_ERR_HIP: return "HIP launch failure";
+    default: return "unknown status";
+  }
+}
+
+// ----------------------------------------------------------------------------------------
+size_t varlingam_fit_var_workspace_bytes(int64_t n, int64_t m, int p, int prec) {
+  (void)prec;
+  if (m < 1 || p < 1 || n - p <= m * p + 1) return 0;
+  return var_ws_bytes(plan_var(n, m, p), nullptr, nullptr);
+}
+
+int varlingam_fit_var(const float* X, int64_t n, int64_t m, int64_t ldx, int p, int prec,
+                      double* M, double* intercept, float* E, int64_t lde, void* ws,
+                      size_t ws_bytes, int32_t* dev_status, void* stream) {
+  if (!X || !M || !intercept || !E || !dev_status || !valid_prec(prec)) return VL_ERR_INVALID_ARG;
+  if (m < 1 || p < 1 || n - p <= m * p + 1 || m * p > 4096) return VL_ERR_SHAPE;
+  if (ldx < m || lde < m) return VL_ERR_INVALID_ARG;
+  const VarPlan v = plan_var(n, m, p);
+  const size_t need = var_ws_bytes(v, nullptr, nullptr);
+  if (!ws || ws_bytes < need || !aligned256(ws)) return VL_ERR_WORKSPACE;
+  VarWs w;
+  var_ws_bytes(v, ws, &w);
+  hipStream_t s = as_stream(stream);
+  int rc = begin(dev_status, s);
+  if (rc) return rc;
+  return run_var(v, w, X, ldx, prec, M, intercept, E, lde, dev_status, s);
+}
+
+// ----------------------------------------------------------------------------------------
+size_t pairwise_stats_workspace_bytes(int64_t n_eff, int64_t m, int prec) {
+  (void)prec;
+  if (m < 2 || n_eff < 2 || m > 65536) return 0;
+  return pairwise_ws_bytes(plan_pairwise(n_eff, m), nullptr, nullptr);
+}
+
+int pairwise_stats(const float* E, int64_t n_eff, int64_t m, int64_t lde, int prec, double* Hx,
+                   double* Hr, double* S, double* Cov, void* ws, size_t ws_bytes,
+                   int32_t* dev_status, void* stream) {
+  if (!E || !Hx || !Hr || !S || !dev_status || !valid_prec(prec)) return VL_ERR_INVALID_ARG;
+  if (m < 2 || n_eff < 2 || m > 65536) return VL_ERR_SHAPE;
+  if (lde < m) return VL_ERR_INVALID_ARG;
+  const PairwisePlan p = plan_pairwise(n_eff, m);
+  const size_t need = pairwise_ws_bytes(p, nullptr, nullptr);
+  if (!ws || ws_bytes < need || !aligned256(ws)) return VL_ERR_WORKSPACE;
+  PairwiseWs w;
+  pairwise_ws_bytes(p, ws, &w);
+  hipStream_t s = as_stream(stream);
+  int rc = begin(dev_status, s);
+  if (rc) return rc;
+  return run_pairwise(p, w, E, lde, prec, Hx, Hr, S, Cov, nullptr, dev_status, s);
+}
+
+// ----------------------------------------------------------------------------------------
+size_t approx_order_workspace_bytes(int64_t m) {
+  if (m < 1 || m > kMaxOrderM) return 0;
+  Carver c(nullptr);
+  c.take<double>(m);
+  return c.used;
+}
+
+int approx_order(const double* S, int64_t m, int32_t* order, double* margin, void* ws,
+                 size_t ws_bytes, int32_t* dev_status, void* stream) {
+  if (!S || !order || !margin || !dev_status) return VL_ERR_INVALID_ARG;
+  if (m < 1 || m > kMaxOrderM) return VL_ERR_SHAPE;
+  if (!ws || ws_bytes < approx_order_workspace_bytes(m) || !aligned256(ws)) return VL_ERR_WORKSPACE;
+  hipStream_t s = as_stream(stream);
+  int rc = begin(dev_status, s);
+  if (rc) return rc;
+  return run_order(S, m, order, margin, static_cast<double*>(ws), dev_status, s);
+}
+
+// ----------------------------------------------------------------------------------------
+size_t estimate_B_workspace_bytes(int64_t m, int p) {
+  if (m < 1 || m > kMaxOrderM || p < 0) return 0;
+  return b_ws_bytes(m, nullptr, nullptr);
+}
+
+int estimate_B(const double* Cov, const double* M, const int32_t* order, int64_t m, int p,
+               double* B0, double* Blag, void* ws, size_t ws_bytes, int32_t* dev_status,
+               void* stream) {
+  if (!Cov || !order || !B0 || !dev_status) return VL_ERR_INVALID_ARG;
+  if (m < 1 || m > kMaxOrderM || p < 0) return VL_ERR_SHAPE;
+  if (p > 0 && (!M || !Blag)) return VL_ERR_INVALID_ARG;
+  if (!ws || ws_bytes < b_ws_bytes(m, nullptr, nullptr) || !aligned256(ws)) return VL_ERR_WORKSPACE;
+  BWs w;
+  b_ws_bytes(m, ws, &w);
+  hipStream_t s = as_stream(stream);
+  int rc = begin(dev_status, s);
+  if (rc) return rc;
+  return run_estimate_b(w, Cov, M, order, m, p, B0, Blag, dev_status, s);
+}
+
+}  // extern "C"

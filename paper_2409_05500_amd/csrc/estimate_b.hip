@@ -1,0 +1,104 @@
+// B0 and lag matrices from the causal order (Sec. 4: estimation of the instantaneous matrix
+// B0; Sec. 2.1: VarLiNGAM lag matrices).
+//
+// Regressing each variable on its predecessors in the order K by least squares is the LDL^T
+// factorisation of the order-permuted covariance:  Sigma_KK = L D L^T with L unit lower-
+// triangular, and the regression coefficients are B0_KK = I - L^{-1} (row k holds the
+// coefficients of variable K_k on K_0 .. K_{k-1}).  With the Cholesky factor Lc = L D^{1/2},
+// L^{-1} = diag(Lc) Lc^{-1}.  Then B_tau = (I - B0) M_tau.
+#include "estimate_b.hpp"
+#include "linalg.hpp"
+#include "profile.hpp"
+
+namespace vl {
+
+// P[a][b] = Cov[K_a][K_b]; seen[] counts each index (the permutation check).
+__global__ void permute_cov_kernel(const double* __restrict__ Cov, const int32_t* __restrict__ K,
+                                   int64_t m, double* __restrict__ P, int32_t* __restrict__ seen,
+                                   int32_t* st) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m * m) return;
+  const int64_t a = e / m, b = e % m;
+  const int32_t ka = K[a], kb = K[b];
+  if (ka < 0 || ka >= m || kb < 0 || kb >= m) {
+    raise_status(st, VL_ERR_INVALID_ARG);
+    P[e] = a == b ? 1.0 : 0.0;
+    return;
+  }
+  P[e] = Cov[(int64_t)ka * m + kb];
+  if (b == 0) atomicAdd(reinterpret_cast<int*>(seen + ka), 1);
+}
+
+__global__ void check_perm_kernel(const int32_t* __restrict__ seen, int64_t m, int32_t* st) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < m && seen[e] != 1) raise_status(st, VL_ERR_INVALID_ARG);
+}
+
+__global__ void zero_i32_kernel(int32_t* __restrict__ a, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) a[e] = 0;
+}
+
+__global__ void identity_kernel(double* __restrict__ a, int64_t m) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < m * m) a[e] = (e / m == e % m) ? 1.0 : 0.0;
+}
+
+// B0[K_a][K_b] = -Lc[a][a] * Linv[a][b] for b < a; 0 otherwise (zero diagonal).
+__global__ void assemble_b0_kernel(const double* __restrict__ Lc, const double* __restrict__ Linv,
+                                   const int32_t* __restrict__ K, int64_t m,
+                                   double* __restrict__ B0) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m * m) return;
+  const int64_t a = e / m, b = e % m;
+  int32_t ka = K[a], kb = K[b];
+  if (ka < 0 || ka >= m || kb < 0 || kb >= m) return;
+  B0[(int64_t)ka * m + kb] = b < a ? -Lc[a * m + a] * Linv[a * m + b] : 0.0;
+}
+
+__global__ void copy_f64_kernel(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) b[e] = a[e];
+}
+
+size_t b_ws_bytes(int64_t m, void* base, BWs* out) {
+  Carver c(base);
+  BWs w;
+  w.P = c.take<double>(m * m);
+  w.Linv = c.take<double>(m * m);
+  w.seen = c.take<int32_t>(m);
+  w.diag0 = c.take<double>(m);
+  if (out) *out = w;
+  return c.used;
+}
+
+int run_estimate_b(const BWs& w, const double* Cov, const double* M, const int32_t* K, int64_t m,
+                   int p, double* B0, double* Blag, int32_t* st, hipStream_t stream) {
+  ProfileScope ps("estimate_b", stream);
+  const unsigned g = (unsigned)ceil_div(m * m, 256);
+  zero_i32_kernel<<<(unsigned)ceil_div(m, 256), 256, 0, stream>>>(w.seen, m);
+  VL_LAUNCH_CHECK();
+  permute_cov_kernel<<<g, 256, 0, stream>>>(Cov, K, m, w.P, w.seen, st);
+  VL_LAUNCH_CHECK();
+  check_perm_kernel<<<(unsigned)ceil_div(m, 256), 256, 0, stream>>>(w.seen, m, st);
+  VL_LAUNCH_CHECK();
+  int rc = potrf_lower(w.P, m, m, w.diag0, st, stream);
+  if (rc) return rc;
+  identity_kernel<<<g, 256, 0, stream>>>(w.Linv, m);
+  VL_LAUNCH_CHECK();
+  rc = trsm_lower(w.P, m, m, false, w.Linv, m, m, stream);
+  if (rc) return rc;
+  assemble_b0_kernel<<<g, 256, 0, stream>>>(w.P, w.Linv, K, m, B0);
+  VL_LAUNCH_CHECK();
+  for (int tau = 0; tau < p; ++tau) {
+    const double* Mt = M + (int64_t)tau * m * m;
+    double* Bt = Blag + (int64_t)tau * m * m;
+    copy_f64_kernel<<<g, 256, 0, stream>>>(Mt, Bt, m * m);
+    VL_LAUNCH_CHECK();
+    rc = gemm_f64(m, m, m, -1.0, B0, m, false, Mt, m, false, 1.0, Bt, m, false, stream);
+    if (rc) return rc;
+  }
+  return VL_OK;
+}
+
+}  // namespace vl

@@ -1,0 +1,359 @@
+// Column statistics and centred Gram matrices of sample-major data on gfx950 MFMA.
+//
+// Used for: the VAR normal equations (Sec. 2.1, Gram of the lag-embedded series), the
+// refinement residual Z^T E, and the residual covariance whose normalisation gives the
+// pairwise correlation of Eq. 1 (cov(x_i, x_j) / var(x_j) for standardised columns).
+//
+// Data are sample-major (row t = one time step).  A "column map" turns a virtual column c
+// into the element offset of its first sample, which lets one launch read the lag-shifted
+// views x(t - tau) of the same series without copies.
+#include "gram.hpp"
+
+namespace vl {
+
+__global__ void reset_status_kernel(int32_t* st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *st = VL_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// Column sums over K samples, split over row blocks: part[rs * ncol + c] (FP64), plus a
+// finiteness check.  Block = 256 threads = 64 columns x 4 row lanes.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void colsum_partial_kernel(const float* __restrict__ A,
+                                                             int64_t lda,
+                                                             const int64_t* __restrict__ colmap,
+                                                             int64_t ncol, int64_t K,
+                                                             int64_t rows_per_split,
+                                                             double* __restrict__ part,
+                                                             int32_t* st) {
+  __shared__ double red[4][64];
+  const int cc = threadIdx.x & 63, rg = threadIdx.x >> 6;
+  const int64_t c = (int64_t)blockIdx.x * 64 + cc;
+  const int64_t r0 = (int64_t)blockIdx.y * rows_per_split;
+  const int64_t r1 = r0 + rows_per_split < K ? r0 + rows_per_split : K;
+  double s = 0.0;
+  bool bad = false;
+  if (c < ncol) {
+    const float* p = A + (colmap ? colmap[c] : c);
+    for (int64_t t = r0 + rg; t < r1; t += 4) {
+      float v = p[t * lda];
+      bad |= !isfinite(v);
+      s += (double)v;
+    }
+  }
+  if (bad) raise_status(st, VL_ERR_NONFINITE);
+  red[rg][cc] = s;
+  __syncthreads();
+  if (rg == 0 && c < ncol)
+    part[(int64_t)blockIdx.y * ncol + c] = ((red[0][cc] + red[1][cc]) + red[2][cc]) + red[3][cc];
+}
+
+__global__ void colmean_final_kernel(const double* __restrict__ part, int64_t ncol, int splits,
+                                     int64_t K, double* __restrict__ mean) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncol) return;
+  double s = 0.0;
+  for (int z = 0; z < splits; ++z) s += part[(int64_t)z * ncol + c];
+  mean[c] = s / (double)K;
+}
+
+int colmeans(const float* A, int64_t lda, const int64_t* colmap, int64_t ncol, int64_t K,
+             double* mean, double* scratch, int32_t* st, hipStream_t stream) {
+  const int splits = colmean_splits(K);
+  const int64_t rows = ceil_div(K, splits);
+  dim3 grid((unsigned)ceil_div(ncol, 64), (unsigned)splits);
+  colsum_partial_kernel<<<grid, 256, 0, stream>>>(A, lda, colmap, ncol, K, rows, scratch, st);
+  VL_LAUNCH_CHECK();
+  colmean_final_kernel<<<(unsigned)ceil_div(ncol, 256), 256, 0, stream>>>(scratch, ncol, splits,
+                                                                          K, mean);
+  VL_LAUNCH_CHECK();
+  return VL_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// Centred TN Gram:  C[i][j] = sum_t (A(t,i) - muA[i]) (B(t,j) - muB[j])   (FP64 result)
+// with A(t,i) = A[mapA[i] + t * lda].  Block tile 64 x 64 (4 waves of 32 x 32, one
+// v_mfma_f32_32x32x2f32 accumulator each), 32 samples per LDS stage.  kFlush > 0 adds the
+// FP32 accumulator into FP64 registers every kFlush stages (FP32-accurate result); kFlush == 0
+// keeps a plain FP32 accumulator.  Split-K: blockIdx.z covers rows [z*kchunk, (z+1)*kchunk);
+// each split writes its FP64 partial tile to P[z] (M x N, ld N).
+// ------------------------------------------------------------------------------------------
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kGT = 64;    // tile side
+constexpr int kGK = 32;    // samples per stage
+constexpr int kGLd = 65;   // LDS row stride (floats): odd to keep the two half-waves apart
+
+template <int kFlush>
+__global__ __launch_bounds__(256) void gram_tn_kernel(
+    const float* __restrict__ A, int64_t lda, const int64_t* __restrict__ mapA,
+    const double* __restrict__ muA, int64_t M, const float* __restrict__ B, int64_t ldb,
+    const int64_t* __restrict__ mapB, const double* __restrict__ muB, int64_t N, int64_t K,
+    int64_t kchunk, double* __restrict__ P) {
+  __shared__ float As[kGK * kGLd];
+  __shared__ float Bs[kGK * kGLd];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t i0 = (int64_t)blockIdx.y * kGT, j0 = (int64_t)blockIdx.x * kGT;
+  const int64_t kb = (int64_t)blockIdx.z * kchunk;
+  const int64_t ke = kb + kchunk < K ? kb + kchunk : K;
+
+  // loader: column cc, rows rg + 4 r
+  const int cc = tid & 63, rg = tid >> 6;
+  const int64_t ia = i0 + cc, jb = j0 + cc;
+  const bool va = ia < M, vb = jb < N;
+  const float* pa = A + (va ? (mapA ? mapA[ia] : ia) : 0);
+  const float* pb = B + (vb ? (mapB ? mapB[jb] : jb) : 0);
+  const float ma = va ? (float)muA[ia] : 0.f;
+  const float mb = vb ? (float)muB[jb] : 0.f;
+  // Centring with the float-rounded mean leaves an offset d ~ 1e-8 |mu|; it changes the Gram
+  // by K d_a d_b only, since the centred columns sum to zero.
+
+  const int wi = wave >> 1, wj = wave & 1;
+  f32x16 acc = {};
+  double acc64[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc64[r] = 0.0;
+
+  int stage = 0;
+  for (int64_t k0 = kb; k0 < ke; k0 += kGK, ++stage) {
+#pragma unroll
+    for (int r = 0; r < kGK / 4; ++r) {
+      const int row = rg + 4 * r;
+      const int64_t t = k0 + row;
+      const bool in = t < ke;
+      As[row * kGLd + cc] = (va && in) ? pa[t * lda] - ma : 0.f;
+      Bs[row * kGLd + cc] = (vb && in) ? pb[t * ldb] - mb : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kGK; kk += 2) {
+      const float a = As[(kk + (lane >> 5)) * kGLd + wi * 32 + (lane & 31)];
+      const float b = Bs[(kk + (lane >> 5)) * kGLd + wj * 32 + (lane & 31)];
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+    }
+    __syncthreads();
+    if (kFlush > 0 && (stage % kFlush) == kFlush - 1) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        acc64[r] += (double)acc[r];
+        acc[r] = 0.f;
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc64[r] += (double)acc[r];
+
+  // D layout of 32x32x2: lane l, reg r -> row 8*(r/4) + 4*(l/32) + r%4, column l%32
+  double* Pz = P + (int64_t)blockIdx.z * M * N;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int64_t i = i0 + wi * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    const int64_t j = j0 + wj * 32 + (lane & 31);
+    if (i < M && j < N) Pz[i * N + j] = acc64[r];
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// FP64 variant: same tiling, v_mfma_f64_16x16x4f64.  FP32 inputs are widened when read from
+// LDS, so every product is exact and the sum is FP64 throughout.  Wave tile 32 x 32 = 2 x 2
+// blocks of 16 x 16; 16 samples per LDS stage.
+// ------------------------------------------------------------------------------------------
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kGK64 = 16;
+
+__global__ __launch_bounds__(256) void gram_tn_f64_kernel(
+    const float* __restrict__ A, int64_t lda, const int64_t* __restrict__ mapA,
+    const double* __restrict__ muA, int64_t M, const float* __restrict__ B, int64_t ldb,
+    const int64_t* __restrict__ mapB, const double* __restrict__ muB, int64_t N, int64_t K,
+    int64_t kchunk, double* __restrict__ P) {
+  __shared__ float As[kGK64 * kGLd];
+  __shared__ float Bs[kGK64 * kGLd];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t i0 = (int64_t)blockIdx.y * kGT, j0 = (int64_t)blockIdx.x * kGT;
+  const int64_t kb = (int64_t)blockIdx.z * kchunk;
+  const int64_t ke = kb + kchunk < K ? kb + kchunk : K;
+  const int cc = tid & 63, rg = tid >> 6;
+  const int64_t ia = i0 + cc, jb = j0 + cc;
+  const bool va = ia < M, vb = jb < N;
+  const float* pa = A + (va ? (mapA ? mapA[ia] : ia) : 0);
+  const float* pb = B + (vb ? (mapB ? mapB[jb] : jb) : 0);
+  const int wi = wave >> 1, wj = wave & 1;
+  // the means are subtracted after widening (in FP64), per operand column of this lane
+  double mua[2], mub[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int64_t ii = i0 + wi * 32 + q * 16 + (lane & 15);
+    const int64_t jj = j0 + wj * 32 + q * 16 + (lane & 15);
+    mua[q] = ii < M ? muA[ii] : 0.0;
+    mub[q] = jj < N ? muB[jj] : 0.0;
+  }
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int64_t k0 = kb; k0 < ke; k0 += kGK64) {
+#pragma unroll
+    for (int r = 0; r < kGK64 / 4; ++r) {
+      const int row = rg + 4 * r;
+      const int64_t t = k0 + row;
+      const bool in = t < ke;
+      // raw values; rows past the end of the split are zeroed again after centring below
+      As[row * kGLd + cc] = (va && in) ? pa[t * lda] : 0.f;
+      Bs[row * kGLd + cc] = (vb && in) ? pb[t * ldb] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kGK64; kk += 4) {
+      const bool in = k0 + kk + (lane >> 4) < ke;
+      double av[2], bv[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const double ra = (double)As[(kk + (lane >> 4)) * kGLd + wi * 32 + q * 16 + (lane & 15)];
+        const double rb = (double)Bs[(kk + (lane >> 4)) * kGLd + wj * 32 + q * 16 + (lane & 15)];
+        av[q] = in ? ra - mua[q] : 0.0;
+        bv[q] = in ? rb - mub[q] : 0.0;
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // D layout of 16x16x4 f64: lane l, reg r -> row l/16 + 4 r, column l%16
+  double* Pz = P + (int64_t)blockIdx.z * M * N;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = i0 + wi * 32 + a * 16 + (lane >> 4) + 4 * r;
+        const int64_t j = j0 + wj * 32 + b * 16 + (lane & 15);
+        if (i < M && j < N) Pz[i * N + j] = acc[a][b][r];
+      }
+}
+
+// C[i][j] = sum_t (A(t,i) - muA[i]) B64[t][j] with an FP64 right operand (not centred): the
+// refinement residual Zc^T E64.  Same tiling as gram_tn_f64_kernel.
+__global__ __launch_bounds__(256) void gram_tn_f64b_kernel(
+    const float* __restrict__ A, int64_t lda, const int64_t* __restrict__ mapA,
+    const double* __restrict__ muA, int64_t M, const double* __restrict__ B, int64_t ldb,
+    int64_t N, int64_t K, int64_t kchunk, double* __restrict__ P) {
+  __shared__ float As[kGK64 * kGLd];
+  __shared__ double Bs[kGK64 * kGLd];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t i0 = (int64_t)blockIdx.y * kGT, j0 = (int64_t)blockIdx.x * kGT;
+  const int64_t kb = (int64_t)blockIdx.z * kchunk;
+  const int64_t ke = kb + kchunk < K ? kb + kchunk : K;
+  const int cc = tid & 63, rg = tid >> 6;
+  const int64_t ia = i0 + cc, jb = j0 + cc;
+  const bool va = ia < M, vb = jb < N;
+  const float* pa = A + (va ? (mapA ? mapA[ia] : ia) : 0);
+  const double* pb = B + (vb ? jb : 0);
+  const int wi = wave >> 1, wj = wave & 1;
+  double mua[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int64_t ii = i0 + wi * 32 + q * 16 + (lane & 15);
+    mua[q] = ii < M ? muA[ii] : 0.0;
+  }
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int64_t k0 = kb; k0 < ke; k0 += kGK64) {
+#pragma unroll
+    for (int r = 0; r < kGK64 / 4; ++r) {
+      const int row = rg + 4 * r;
+      const int64_t t = k0 + row;
+      const bool in = t < ke;
+      As[row * kGLd + cc] = (va && in) ? pa[t * lda] : 0.f;
+      Bs[row * kGLd + cc] = (vb && in) ? pb[t * ldb] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kGK64; kk += 4) {
+      const bool in = k0 + kk + (lane >> 4) < ke;
+      double av[2], bv[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const double ra = (double)As[(kk + (lane >> 4)) * kGLd + wi * 32 + q * 16 + (lane & 15)];
+        av[q] = in ? ra - mua[q] : 0.0;
+        bv[q] = Bs[(kk + (lane >> 4)) * kGLd + wj * 32 + q * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  double* Pz = P + (int64_t)blockIdx.z * M * N;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = i0 + wi * 32 + a * 16 + (lane >> 4) + 4 * r;
+        const int64_t j = j0 + wj * 32 + b * 16 + (lane & 15);
+        if (i < M && j < N) Pz[i * N + j] = acc[a][b][r];
+      }
+}
+
+// C[i * ldc + j] = scale * sum_z P[z][i][j], fixed order (deterministic).
+__global__ void sum_splits_kernel(const double* __restrict__ P, int splits, int64_t M, int64_t N,
+                                  double scale, double* __restrict__ C, int64_t ldc) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * N) return;
+  double s = 0.0;
+  for (int z = 0; z < splits; ++z) s += P[(int64_t)z * M * N + e];
+  C[(e / N) * ldc + (e % N)] = s * scale;
+}
+
+int gram_tn(const float* A, int64_t lda, const int64_t* mapA, const double* muA, int64_t M,
+            const float* B, int64_t ldb, const int64_t* mapB, const double* muB, int64_t N,
+            int64_t K, GramMode mode, double scale, double* C, int64_t ldc, double* scratch,
+            hipStream_t stream) {
+  const int splits = gram_splits(M, N, K);
+  const int64_t kchunk = round_up(ceil_div(K, splits), kGK);
+  dim3 grid((unsigned)ceil_div(N, kGT), (unsigned)ceil_div(M, kGT), (unsigned)splits);
+  if (mode == GramMode::kFp64)
+    gram_tn_f64_kernel<<<grid, 256, 0, stream>>>(A, lda, mapA, muA, M, B, ldb, mapB, muB, N, K,
+                                                 kchunk, scratch);
+  else if (mode == GramMode::kFp32Flush64)
+    gram_tn_kernel<4><<<grid, 256, 0, stream>>>(A, lda, mapA, muA, M, B, ldb, mapB, muB, N, K,
+                                                kchunk, scratch);
+  else
+    gram_tn_kernel<0><<<grid, 256, 0, stream>>>(A, lda, mapA, muA, M, B, ldb, mapB, muB, N, K,
+                                                kchunk, scratch);
+  VL_LAUNCH_CHECK();
+  const int64_t tot = M * N;
+  sum_splits_kernel<<<(unsigned)ceil_div(tot, 256), 256, 0, stream>>>(scratch, splits, M, N,
+                                                                     scale, C, ldc);
+  VL_LAUNCH_CHECK();
+  return VL_OK;
+}
+
+int gram_tn_f64b(const float* A, int64_t lda, const int64_t* mapA, const double* muA, int64_t M,
+                 const double* B, int64_t ldb, int64_t N, int64_t K, double* C, int64_t ldc,
+                 double* scratch, hipStream_t stream) {
+  const int splits = gram_splits(M, N, K);
+  const int64_t kchunk = round_up(ceil_div(K, splits), kGK);
+  dim3 grid((unsigned)ceil_div(N, kGT), (unsigned)ceil_div(M, kGT), (unsigned)splits);
+  gram_tn_f64b_kernel<<<grid, 256, 0, stream>>>(A, lda, mapA, muA, M, B, ldb, N, K, kchunk,
+                                                scratch);
+  VL_LAUNCH_CHECK();
+  sum_splits_kernel<<<(unsigned)ceil_div(M * N, 256), 256, 0, stream>>>(scratch, splits, M, N,
+                                                                       1.0, C, ldc);
+  VL_LAUNCH_CHECK();
+  return VL_OK;
+}
+
+}  // namespace vl

@@ -1,0 +1,46 @@
+// Column statistics and centred Gram matrices (declarations).
+#pragma once
+#include "common.hpp"
+
+namespace vl {
+
+// Row splits used by colmeans(); scratch must hold colmean_splits(K) * ncol doubles.
+inline int colmean_splits(int64_t K) {
+  int64_t s = K / 512;
+  return (int)(s < 1 ? 1 : (s > 64 ? 64 : s));
+}
+
+// mean[c] = (1/K) sum_{t<K} A[map(c) + t*lda]  (FP64);  raises VL_ERR_NONFINITE on NaN/Inf.
+int colmeans(const float* A, int64_t lda, const int64_t* colmap, int64_t ncol, int64_t K,
+             double* mean, double* scratch, int32_t* st, hipStream_t stream);
+
+// Split-K factor of gram_tn(); scratch must hold gram_splits(M,N,K) * M * N doubles.
+inline int gram_splits(int64_t M, int64_t N, int64_t K) {
+  int64_t tiles = ceil_div(M, 64) * ceil_div(N, 64);
+  int64_t s = ceil_div(1024, tiles);
+  int64_t smax = K / 256;
+  if (smax < 1) smax = 1;
+  if (s > smax) s = smax;
+  if (s > 64) s = 64;
+  return (int)(s < 1 ? 1 : s);
+}
+
+// Arithmetic of gram_tn():
+//   kFp32        FP32 MFMA, FP32 accumulation over the whole split;
+//   kFp32Flush64 FP32 MFMA partial sums over 128-sample blocks accumulated in FP64;
+//   kFp64        FP64 MFMA on the widened FP32 inputs (exact products, FP64 sums).
+enum class GramMode { kFp32, kFp32Flush64, kFp64 };
+
+// C[i*ldc + j] = scale * sum_{t<K} (A(t,i) - muA[i]) (B(t,j) - muB[j]),
+//   A(t,i) = A[mapA[i] + t*lda] (mapA == nullptr: mapA[i] = i); likewise B.
+int gram_tn(const float* A, int64_t lda, const int64_t* mapA, const double* muA, int64_t M,
+            const float* B, int64_t ldb, const int64_t* mapB, const double* muB, int64_t N,
+            int64_t K, GramMode mode, double scale, double* C, int64_t ldc, double* scratch,
+            hipStream_t stream);
+
+// C[i*ldc + j] = sum_{t<K} (A(t,i) - muA[i]) B[t*ldb + j] with an FP64, uncentred B (FP64 MFMA).
+int gram_tn_f64b(const float* A, int64_t lda, const int64_t* mapA, const double* muA, int64_t M,
+                 const double* B, int64_t ldb, int64_t N, int64_t K, double* C, int64_t ldc,
+                 double* scratch, hipStream_t stream);
+
+}  // namespace vl

@@ -1,0 +1,39 @@
+// Pairwise-statistic precompute: launch plan and workspace layout.
+#pragma once
+#include "common.hpp"
+
+namespace vl {
+
+struct PairwisePlan {
+  int64_t m = 0, n_eff = 0;
+  int nt = 0;             // micro-tiles per side (4 variables each)
+  int64_t m_pad = 0;      // nt * 4
+  int64_t tiles = 0;      // nt (nt + 1) / 2 upper-triangular micro-tiles
+  int nc = 0;             // sample chunks
+  int chunk_len = 0;      // samples per chunk, multiple of 256
+  int64_t n_pad = 0;      // nc * chunk_len >= n_eff
+  int64_t items = 0;      // tiles * nc (one wave each)
+  int64_t blocks = 0;     // ceil(items / 4) rounded up to a multiple of 8
+};
+
+struct PairwiseWs {
+  double* mu = nullptr;       // m column means
+  double* cov = nullptr;      // m x m covariance when the caller passes none
+  double* scratch = nullptr;  // split partials of the column sums / Gram
+  float* Xs = nullptr;        // m_pad x n_pad standardised, variable-major
+  float2* coef = nullptr;     // m_pad x m_pad pair coefficients
+  float* partU = nullptr;     // nc x m x m
+  float* partB = nullptr;     // nc x m x m
+  double* momx = nullptr;     // 2 m: E[log cosh x_i], E[x_i exp(-x_i^2/2)]
+};
+
+PairwisePlan plan_pairwise(int64_t n_eff, int64_t m);
+size_t scratch_doubles(const PairwisePlan& p);
+// Total workspace bytes; with base != nullptr also fills *out with the carved pointers.
+size_t pairwise_ws_bytes(const PairwisePlan& p, void* base, PairwiseWs* out);
+// mom (nullable): 2 m^2 doubles, (A, B) per ordered pair, for tests and the backward pass.
+int run_pairwise(const PairwisePlan& p, const PairwiseWs& w, const float* E, int64_t lde,
+                 int prec, double* Hx, double* Hr, double* S, double* Cov, double* mom,
+                 int32_t* st, hipStream_t stream);
+
+}  // namespace vl

@@ -1,0 +1,30 @@
+// VAR(p) least-squares fit (declarations).
+#pragma once
+#include "common.hpp"
+
+namespace vl {
+
+struct VarPlan {
+  int64_t n = 0, m = 0, n_eff = 0, dz = 0;
+  int p = 0;
+};
+
+struct VarWs {
+  int64_t* colmap = nullptr;  // m (p+1) sample offsets of the lag-embedded columns
+  double* mu = nullptr;       // m (p+1) column means (Y first, then Z)
+  double* zeros = nullptr;    // m zeros (mean of E in the refinement Gram)
+  double* G = nullptr;        // dz x dz Gram, then its Cholesky factor
+  double* Coef = nullptr;     // dz x m solution
+  double* Rres = nullptr;     // dz x m refinement right-hand side
+  float* CoefF = nullptr;     // dz x m float copy for the residual GEMM
+  double* diag0 = nullptr;    // dz diagonal of G before factorisation
+  double* E64 = nullptr;      // n_eff x m FP64 residual of the refinement step
+  double* scratch = nullptr;  // split-K partials
+};
+
+VarPlan plan_var(int64_t n, int64_t m, int p);
+size_t var_ws_bytes(const VarPlan& v, void* base, VarWs* out);
+int run_var(const VarPlan& v, const VarWs& w, const float* X, int64_t ldx, int prec, double* M,
+            double* intercept, float* E, int64_t lde, int32_t* st, hipStream_t stream);
+
+}  // namespace vl

@@ -1,0 +1,94 @@
+"""The C ABI library loads and exports every function include/varlingam.h declares, and its
+host-side checks (shapes, pointers, workspace) answer without touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "varlingam.h")
+LIB = os.path.join(ROOT, "paper_2409_05500_amd", "libvarlingam.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libvarlingam.so not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", text, flags=re.M)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert {"varlingam_fit_var", "pairwise_stats", "approx_order", "estimate_B"} <= set(names)
+    lib = ctypes.CDLL(LIB)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_signatures_cover_header():
+    from paper_2409_05500_amd import _lib
+    assert set(declared_functions()) == set(_lib.SIGNATURES)
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2409_05500_amd import _lib
+    return _lib
+
+
+def test_status_strings(L):
+    for code in range(0, -8, -1):
+        assert L.status_string(code) != "unknown status"
+    assert L.status_string(5) == "unknown status"
+
+
+def test_workspace_queries(L):
+    lib = L.lib
+    assert lib.pairwise_stats_workspace_bytes(10000, 400, 1) > 400 * 10000 * 4
+    assert lib.pairwise_stats_workspace_bytes(10, 1, 1) == 0
+    assert lib.varlingam_fit_var_workspace_bytes(1000, 10, 1, 1) > 0
+    assert lib.varlingam_fit_var_workspace_bytes(10, 10, 1, 1) == 0     # n - p <= m p + 1
+    assert lib.approx_order_workspace_bytes(400) >= 400 * 8
+    assert lib.approx_order_workspace_bytes(0) == 0
+    assert lib.estimate_B_workspace_bytes(400, 2) >= 2 * 400 * 400 * 8
+
+
+FAKE = 0x10000   # a non-null, 256-aligned dummy pointer: never dereferenced on these paths
+
+
+def test_host_validation_without_gpu(L):
+    lib = L.lib
+    # null pointers
+    assert lib.pairwise_stats(None, 100, 4, 4, 1, FAKE, FAKE, FAKE, None, FAKE, 1 << 30, FAKE,
+                              None) == L.VL_ERR_INVALID_ARG
+    # shapes
+    assert lib.pairwise_stats(FAKE, 100, 1, 1, 1, FAKE, FAKE, FAKE, None, FAKE, 1 << 30, FAKE,
+                              None) == L.VL_ERR_SHAPE
+    assert lib.varlingam_fit_var(FAKE, 10, 10, 10, 1, 1, FAKE, FAKE, FAKE, 10, FAKE, 1 << 30,
+                                 FAKE, None) == L.VL_ERR_SHAPE
+    assert lib.varlingam_fit_var(FAKE, 100, 10, 10, 0, 1, FAKE, FAKE, FAKE, 10, FAKE, 1 << 30,
+                                 FAKE, None) == L.VL_ERR_SHAPE
+    assert lib.approx_order(FAKE, 0, FAKE, FAKE, FAKE, 1 << 30, FAKE, None) == L.VL_ERR_SHAPE
+    # leading dimension / precision enum
+    assert lib.pairwise_stats(FAKE, 100, 4, 3, 1, FAKE, FAKE, FAKE, None, FAKE, 1 << 30, FAKE,
+                              None) == L.VL_ERR_INVALID_ARG
+    assert lib.pairwise_stats(FAKE, 100, 4, 4, 7, FAKE, FAKE, FAKE, None, FAKE, 1 << 30, FAKE,
+                              None) == L.VL_ERR_INVALID_ARG
+    # workspace too small or misaligned
+    assert lib.pairwise_stats(FAKE, 100, 4, 4, 1, FAKE, FAKE, FAKE, None, FAKE, 16, FAKE,
+                              None) == L.VL_ERR_WORKSPACE
+    assert lib.pairwise_stats(FAKE, 100, 4, 4, 1, FAKE, FAKE, FAKE, None, FAKE + 8, 1 << 30,
+                              FAKE, None) == L.VL_ERR_WORKSPACE
+    assert lib.estimate_B(FAKE, None, FAKE, 4, 1, FAKE, FAKE, FAKE, 1 << 30, FAKE,
+                          None) == L.VL_ERR_INVALID_ARG
+    assert lib.approx_order(FAKE, 4, FAKE, FAKE, FAKE, 8, FAKE, None) == L.VL_ERR_WORKSPACE
+
+
+def test_build_flags_disable_packed_fp32():
+    from paper_2409_05500_amd import build
+    f = build.FLAGS
+    i = f.index("-packed-fp32-ops")
+    assert f[i - 1] == "-Xclang" and f[i - 2] == "-target-feature"
+    assert "--offload-arch=gfx950" in f

@@ -1,0 +1,296 @@
+"""GPU parity of the HIP library (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances (FP32 per-sample arithmetic, FP64 combination):
+* each moment term is evaluated in FP32 from FP32 standardised data, with a relative error of a
+  few ulps (2^-22); the means A = E[log cosh u] and B = E[u exp(-u^2/2)] therefore carry at most
+  ~1e-7 absolute error; H = H(nu) - k1 (A - gamma)^2 - k2 B^2 has |dH/dA| = 2 k1 |A - gamma|
+  <= 16 and |dH/dB| = 2 k2 |B| <= 3 on these laws, so |dHr| <= 2e-6;
+* Hx uses the library's accurate expf/log1pf: |dHx| <= 1e-6;
+* S[i,j] = (Hx[j] + Hr[i,j]) - (Hx[i] + Hr[j,i]) adds four such errors: |dS| <= 6e-6;
+* orders: identical except where the oracle's own margin is below 1e-9 (parity.ORDER_TIE);
+* B0 / B_tau: 1e-5 relative with a floor of 1e-2 max|B| (parity.b_rel_error).
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import varlingam as O
+import parity as PA
+
+pytestmark = pytest.mark.gpu
+
+TOL_HX = 1e-6
+TOL_HR = 2e-6
+TOL_S = 6e-6
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2409_05500_amd import api as _api
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return _api
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return torch.device("cuda:0")
+
+
+def _dev(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _residuals(m, n, seed):
+    rng = np.random.default_rng(seed)
+    mix = np.eye(m) + 0.3 * np.tril(rng.normal(size=(m, m)), -1)
+    return (rng.laplace(size=(n, m)) @ mix.T).astype(np.float32)
+
+
+def _check_pairwise(api, dev, E32):
+    Hx, Hr, S, Cov = [t.cpu().numpy() for t in api.pairwise_stats(_dev(E32, dev), "mixed")]
+    oHx, oHr, oS = O.pairwise_stats(E32.astype(np.float64))
+    np.testing.assert_allclose(Hx, oHx, rtol=0, atol=TOL_HX)
+    np.testing.assert_allclose(Hr, oHr, rtol=0, atol=TOL_HR)
+    np.testing.assert_allclose(S, oS, rtol=0, atol=TOL_S)
+    assert np.array_equal(S, -S.T) and np.all(np.diag(S) == 0.0)
+    oCov = np.cov(E32.astype(np.float64).T, bias=True)
+    np.testing.assert_allclose(Cov, oCov, rtol=1e-12, atol=1e-12 * np.abs(oCov).max())
+    return S, oS
+
+
+# ------------------------------------------------------------------------------------------
+# pairwise_stats
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("m,n", [(2, 50), (3, 17), (5, 64), (7, 300), (13, 255), (37, 1234),
+                                 (64, 257), (65, 2049)])
+def test_pairwise_ragged_shapes(api, dev, m, n):
+    print(f"pairwise ragged m={m} n={n}", flush=True)
+    _check_pairwise(api, dev, _residuals(m, n, m * 1000 + n))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_pairwise_small_workload(api, dev, seed):
+    inst = synth.make_instance(synth.SMALL, seed)
+    _, _, E = O.fit_var(inst.X_parity, 1)
+    S, oS = _check_pairwise(api, dev, E.astype(np.float32))
+    order, _ = api.approx_order(_dev(S, dev))
+    assert PA.order_violations(order.cpu().numpy(), oS) == []
+
+
+def test_pairwise_medium_workload(api, dev):
+    inst = synth.make_instance(synth.MEDIUM, 0)
+    _, _, E = O.fit_var(inst.X_parity, 1)
+    S, oS = _check_pairwise(api, dev, E.astype(np.float32))
+    order, _ = api.approx_order(_dev(S, dev))
+    assert PA.order_violations(order.cpu().numpy(), oS) == []
+
+
+@pytest.mark.parametrize("wl,npairs", [(synth.FINANCE, 96), (synth.LARGE, 24)])
+def test_pairwise_full_size_sampled(api, dev, wl, npairs):
+    """The benchmark's full sizes: sampled pairs recomputed one by one by the oracle."""
+    print(f"pairwise full size {wl.name}", flush=True)
+    inst = synth.make_instance(wl, 0)
+    _, _, E = O.fit_var(inst.X_parity, wl.p)
+    E32 = E.astype(np.float32)
+    Hx, Hr, S, Cov = [t.cpu().numpy() for t in api.pairwise_stats(_dev(E32, dev), "mixed")]
+    assert np.array_equal(S, -S.T) and np.all(np.diag(S) == 0.0)
+    assert np.all(np.isfinite(Hr))
+    E64 = E32.astype(np.float64)
+    rng = np.random.default_rng(1)
+    m = wl.m
+    pairs = [(int(i), int(j)) for i, j in rng.integers(0, m, (npairs, 2)) if i != j]
+    pairs += [(0, m - 1), (m - 1, 0), (m - 2, m - 1)]        # the ragged last micro-tile
+    for i, j in pairs:
+        a, b = O.pair_moments(E64, i, j)
+        assert abs(Hr[i, j] - O.entropy_from_moments(a, b)) < TOL_HR, (i, j)
+    for i in {p[0] for p in pairs}:
+        assert abs(Hx[i] - O.entropy(O.standardize(E64[:, i]))) < TOL_HX
+        for j in (0, m - 1):
+            c = np.mean((E64[:, i] - E64[:, i].mean()) * (E64[:, j] - E64[:, j].mean()))
+            assert abs(Cov[i, j] - c) <= 1e-12 * max(abs(Cov[i, i]), abs(Cov[j, j]))
+
+
+def test_pairwise_permutation_equivariance(api, dev):
+    E32 = _residuals(23, 3000, 5)
+    P = np.random.default_rng(3).permutation(23)
+    S = api.pairwise_stats(_dev(E32, dev))[2].cpu().numpy()
+    SP = api.pairwise_stats(_dev(E32[:, P], dev))[2].cpu().numpy()
+    np.testing.assert_allclose(SP, S[np.ix_(P, P)], atol=TOL_S)
+
+
+def test_pairwise_affine_invariance(api, dev):
+    E32 = _residuals(11, 2000, 6)
+    S = api.pairwise_stats(_dev(E32, dev))[2].cpu().numpy()
+    a = np.linspace(-3, 4, 11).astype(np.float32)
+    a[a == 0] = 0.5
+    E2 = (E32 * a + np.float32(7.0)).astype(np.float32)
+    S2 = api.pairwise_stats(_dev(E2, dev))[2].cpu().numpy()
+    np.testing.assert_allclose(S2, S, atol=2 * TOL_S)
+
+
+def test_pairwise_deterministic(api, dev):
+    Et = _dev(_residuals(41, 5000, 7), dev)
+    r1 = [t.cpu().numpy() for t in api.pairwise_stats(Et)]
+    r2 = [t.cpu().numpy() for t in api.pairwise_stats(Et)]
+    for a, b in zip(r1, r2):
+        assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------------------------------------------
+# approx_order
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("m", [1, 2, 3, 17, 64, 255, 256, 257, 1000, 1100])
+def test_order_matches_oracle_on_same_S(api, dev, m):
+    rng = np.random.default_rng(m)
+    A = rng.normal(size=(m, m))
+    S = A - A.T
+    order, margin = api.approx_order(_dev(S, dev))
+    oo, om = O.approx_order(S)
+    assert np.array_equal(order.cpu().numpy(), oo)
+    # the GPU lowers M incrementally, the oracle recomputes it: rounding residue ~ eps * M * sqrt(m)
+    if m > 1:
+        np.testing.assert_allclose(margin.cpu().numpy()[:-1], om[:-1], rtol=1e-9,
+                                   atol=1e-14 * max(1.0, om[:-1].max()) * np.sqrt(m))
+    assert margin.cpu().numpy()[-1] == np.inf
+
+
+def test_order_hand_built_total_order(api, dev):
+    rng = np.random.default_rng(0)
+    m = 300
+    true = rng.permutation(m)
+    pos = np.empty(m, int)
+    pos[true] = np.arange(m)
+    mag = rng.uniform(0.1, 1, (m, m))
+    S = np.where(pos[:, None] < pos[None, :], 1.0, -1.0) * (mag + mag.T)
+    np.fill_diagonal(S, 0.0)
+    order, _ = api.approx_order(_dev(S, dev))
+    assert np.array_equal(order.cpu().numpy(), true)
+
+
+def test_order_ties_lowest_index(api, dev):
+    order, margin = api.approx_order(_dev(np.zeros((5, 5)), dev))
+    assert order.cpu().numpy().tolist() == [0, 1, 2, 3, 4]
+    assert np.all(margin.cpu().numpy()[:-1] == 0.0)
+
+
+# ------------------------------------------------------------------------------------------
+# varlingam_fit_var
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("wl,seed", [(synth.SMALL, 0), (synth.SMALL, 3), (synth.MEDIUM, 0),
+                                     (synth.FINANCE, 0)])
+def test_var_fit_parity(api, dev, wl, seed):
+    print(f"var fit {wl.name} seed {seed}", flush=True)
+    inst = synth.make_instance(wl, seed)
+    oM, oc, oE = O.fit_var(inst.X_parity, wl.p)
+    M, c, E = [t.cpu().numpy() for t in api.fit_var(_dev(inst.X32, dev), wl.p, "mixed")]
+    assert np.max(np.abs(M - oM)) <= 1e-7 * max(1.0, np.abs(oM).max())
+    assert np.max(np.abs(c - oc)) <= 1e-7 * max(1.0, np.abs(inst.X_parity).max())
+    # E is the FP32 rounding of the exact residual: half an ulp plus the FP64 solve's error
+    assert np.max(np.abs(E - oE)) <= 2.0 ** -23 * np.abs(oE).max() + 1e-7
+
+
+def test_var_fit_ragged(api, dev):
+    for m, n, p in [(1, 50, 1), (3, 40, 3), (7, 500, 2), (70, 700, 1)]:
+        inst = synth.make_custom(m, n, p, "laplace", m + n)
+        oM, oc, oE = O.fit_var(inst.X_parity, p)
+        M, c, E = [t.cpu().numpy() for t in api.fit_var(_dev(inst.X32, dev), p, "mixed")]
+        np.testing.assert_allclose(M, oM, atol=1e-7 * max(1, np.abs(oM).max()))
+        np.testing.assert_allclose(E, oE, atol=2.0 ** -23 * np.abs(oE).max() + 1e-7)
+
+
+# ------------------------------------------------------------------------------------------
+# estimate_B and the whole fit
+# ------------------------------------------------------------------------------------------
+def test_estimate_B_on_oracle_inputs(api, dev):
+    inst = synth.make_instance(synth.MEDIUM, 1)
+    res = O.fit(inst.X_parity, 1)
+    Cov = np.cov(res["E"].T, bias=True)
+    B0, Bl = api.estimate_B(_dev(Cov, dev), _dev(res["M"], dev),
+                            _dev(res["order"].astype(np.int32), dev))
+    assert PA.b_rel_error(B0.cpu().numpy(), res["B0"]) < 1e-9
+    assert PA.b_rel_error(Bl.cpu().numpy(), res["B_lags"]) < 1e-9
+
+
+def _fit_and_compare(api, dev, inst, p, prec, tol):
+    res = O.fit(inst.X_parity, p)
+    g = api.fit(_dev(inst.X32, dev), p, prec)
+    order = g.order.cpu().numpy()
+    assert PA.order_violations(order, res["S"]) == []
+    if np.array_equal(order, res["order"]):
+        B0_ref, Bl_ref = res["B0"], res["B_lags"]
+    else:
+        B0_ref, Bl_ref = O.estimate_B(res["E"], order, res["M"])
+    e0 = PA.b_rel_error(g.B0.cpu().numpy(), B0_ref)
+    e1 = PA.b_rel_error(g.B_lags.cpu().numpy(), Bl_ref)
+    assert e0 <= tol and e1 <= tol, (e0, e1)
+    return e0, e1
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_fit_small_workload(api, dev, seed):
+    _fit_and_compare(api, dev, synth.make_instance(synth.SMALL, seed), 1, "mixed", PA.B_TOL_FP32)
+
+
+def test_fit_medium_workload(api, dev):
+    _fit_and_compare(api, dev, synth.make_instance(synth.MEDIUM, 0), 1, "mixed", PA.B_TOL_FP32)
+
+
+def test_fit_deterministic(api, dev):
+    Xt = _dev(synth.make_instance(synth.SMALL, 1).X32, dev)
+    a, b = api.fit(Xt, 1), api.fit(Xt, 1)
+    for f in ("E", "S", "order", "B0", "B_lags"):
+        assert torch.equal(getattr(a, f), getattr(b, f)), f
+
+
+# ------------------------------------------------------------------------------------------
+# data-dependent errors (forced from the host by the input)
+# ------------------------------------------------------------------------------------------
+def test_error_zero_variance(api, dev):
+    from paper_2409_05500_amd._lib import VarLiNGAMError, VL_ERR_DEGENERATE
+    E = _residuals(4, 100, 1)
+    E[:, 2] = 3.0
+    with pytest.raises(VarLiNGAMError) as ei:
+        api.pairwise_stats(_dev(E, dev))
+    assert ei.value.code == VL_ERR_DEGENERATE
+
+
+def test_error_collinear_pair(api, dev):
+    from paper_2409_05500_amd._lib import VarLiNGAMError, VL_ERR_DEGENERATE
+    E = _residuals(4, 100, 2)
+    E[:, 3] = -2.0 * E[:, 0]
+    with pytest.raises(VarLiNGAMError) as ei:
+        api.pairwise_stats(_dev(E, dev))
+    assert ei.value.code == VL_ERR_DEGENERATE
+
+
+def test_error_nonfinite(api, dev):
+    from paper_2409_05500_amd._lib import VarLiNGAMError, VL_ERR_NONFINITE
+    E = _residuals(4, 100, 3)
+    E[17, 1] = np.nan
+    with pytest.raises(VarLiNGAMError) as ei:
+        api.pairwise_stats(_dev(E, dev))
+    assert ei.value.code == VL_ERR_NONFINITE
+    X = synth.make_custom(3, 200, 1, "uniform", 1).X32
+    X[50, 0] = np.inf
+    with pytest.raises(VarLiNGAMError) as ei:
+        api.fit_var(_dev(X, dev), 1)
+    assert ei.value.code == VL_ERR_NONFINITE
+
+
+def test_error_singular_var_design(api, dev):
+    from paper_2409_05500_amd._lib import VarLiNGAMError, VL_ERR_SINGULAR
+    X = synth.make_custom(3, 300, 1, "uniform", 2).X32
+    X[:, 2] = X[:, 0]
+    with pytest.raises(VarLiNGAMError) as ei:
+        api.fit_var(_dev(X, dev), 1)
+    assert ei.value.code == VL_ERR_SINGULAR
+
+
+def test_error_order_not_permutation(api, dev):
+    from paper_2409_05500_amd._lib import VarLiNGAMError, VL_ERR_INVALID_ARG
+    Cov = np.eye(4)
+    M = np.zeros((1, 4, 4))
+    with pytest.raises(VarLiNGAMError) as ei:
+        api.estimate_B(_dev(Cov, dev), _dev(M, dev), _dev(np.array([0, 1, 1, 3], np.int32), dev))
+    assert ei.value.code == VL_ERR_INVALID_ARG
