@@ -67,7 +67,9 @@ size_t b_ws_bytes(int64_t m, void* base, BWs* out) {
   w.P = c.take<double>(m * m);
   w.Linv = c.take<double>(m * m);
   w.seen = c.take<int32_t>(m);
-  w.diag0 = c.take<double>(m);
+  w.Lc = c.take<double>(m * m);
+  w.Id = c.take<double>(m * m);
+  w.chol = c.take<double>(chol_ws_doubles(m));
   if (out) *out = w;
   return c.used;
 }
@@ -82,13 +84,13 @@ int run_estimate_b(const BWs& w, const double* Cov, const double* M, const int32
   VL_LAUNCH_CHECK();
   check_perm_kernel<<<(unsigned)ceil_div(m, 256), 256, 0, stream>>>(w.seen, m, st);
   VL_LAUNCH_CHECK();
-  int rc = potrf_lower(w.P, m, m, w.diag0, st, stream);
+  int rc = potrf_lower(w.P, m, m, w.Lc, m, w.chol, st, stream);
   if (rc) return rc;
-  identity_kernel<<<g, 256, 0, stream>>>(w.Linv, m);
+  identity_kernel<<<g, 256, 0, stream>>>(w.Id, m);
   VL_LAUNCH_CHECK();
-  rc = trsm_lower(w.P, m, m, false, w.Linv, m, m, stream);
+  rc = trsm_lower(w.Lc, m, m, w.chol, false, w.Id, m, m, w.Linv, m, stream);
   if (rc) return rc;
-  assemble_b0_kernel<<<g, 256, 0, stream>>>(w.P, w.Linv, K, m, B0);
+  assemble_b0_kernel<<<g, 256, 0, stream>>>(w.Lc, w.Linv, K, m, B0);
   VL_LAUNCH_CHECK();
   for (int tau = 0; tau < p; ++tau) {
     const double* Mt = M + (int64_t)tau * m * m;

@@ -5,10 +5,12 @@
 namespace vl {
 
 struct BWs {
-  double* P = nullptr;     // m x m permuted covariance, then its Cholesky factor
+  double* P = nullptr;     // m x m permuted covariance (destroyed by the factorisation)
+  double* Lc = nullptr;    // m x m Cholesky factor
+  double* Id = nullptr;    // m x m identity, consumed by the solve
   double* Linv = nullptr;  // m x m inverse of the factor
   int32_t* seen = nullptr; // m permutation counters
-  double* diag0 = nullptr; // m diagonal before factorisation
+  double* chol = nullptr;  // factorisation scratch
 };
 
 size_t b_ws_bytes(int64_t m, void* base, BWs* out);

@@ -114,17 +114,27 @@ __global__ __launch_bounds__(256) void gram_tn_kernel(
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc64[r] = 0.0;
 
+  // register prefetch of the next stage overlaps its loads with this stage's MFMAs
+  float ra[kGK / 4], rb[kGK / 4];
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int r = 0; r < kGK / 4; ++r) {
+      const int64_t t = k0 + rg + 4 * r;
+      const bool in = t < ke;
+      ra[r] = (va && in) ? pa[t * lda] - ma : 0.f;
+      rb[r] = (vb && in) ? pb[t * ldb] - mb : 0.f;
+    }
+  };
+  load(kb);
   int stage = 0;
   for (int64_t k0 = kb; k0 < ke; k0 += kGK, ++stage) {
 #pragma unroll
     for (int r = 0; r < kGK / 4; ++r) {
-      const int row = rg + 4 * r;
-      const int64_t t = k0 + row;
-      const bool in = t < ke;
-      As[row * kGLd + cc] = (va && in) ? pa[t * lda] - ma : 0.f;
-      Bs[row * kGLd + cc] = (vb && in) ? pb[t * ldb] - mb : 0.f;
+      As[(rg + 4 * r) * kGLd + cc] = ra[r];
+      Bs[(rg + 4 * r) * kGLd + cc] = rb[r];
     }
     __syncthreads();
+    if (k0 + kGK < ke) load(k0 + kGK);
 #pragma unroll
     for (int kk = 0; kk < kGK; kk += 2) {
       const float a = As[(kk + (lane >> 5)) * kGLd + wi * 32 + (lane & 31)];
@@ -160,7 +170,7 @@ __global__ __launch_bounds__(256) void gram_tn_kernel(
 // ------------------------------------------------------------------------------------------
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kGK64 = 16;
+constexpr int kGK64 = 32;
 
 __global__ __launch_bounds__(256) void gram_tn_f64_kernel(
     const float* __restrict__ A, int64_t lda, const int64_t* __restrict__ mapA,
@@ -193,17 +203,26 @@ __global__ __launch_bounds__(256) void gram_tn_f64_kernel(
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-  for (int64_t k0 = kb; k0 < ke; k0 += kGK64) {
+  float ra[kGK64 / 4], rb[kGK64 / 4];
+  auto load = [&](int64_t k0) {
 #pragma unroll
     for (int r = 0; r < kGK64 / 4; ++r) {
-      const int row = rg + 4 * r;
-      const int64_t t = k0 + row;
+      const int64_t t = k0 + rg + 4 * r;
       const bool in = t < ke;
-      // raw values; rows past the end of the split are zeroed again after centring below
-      As[row * kGLd + cc] = (va && in) ? pa[t * lda] : 0.f;
-      Bs[row * kGLd + cc] = (vb && in) ? pb[t * ldb] : 0.f;
+      ra[r] = (va && in) ? pa[t * lda] : 0.f;
+      rb[r] = (vb && in) ? pb[t * ldb] : 0.f;
+    }
+  };
+  load(kb);
+  for (int64_t k0 = kb; k0 < ke; k0 += kGK64) {
+    // raw values; rows past the end of the split are zeroed again after centring below
+#pragma unroll
+    for (int r = 0; r < kGK64 / 4; ++r) {
+      As[(rg + 4 * r) * kGLd + cc] = ra[r];
+      Bs[(rg + 4 * r) * kGLd + cc] = rb[r];
     }
     __syncthreads();
+    if (k0 + kGK64 < ke) load(k0 + kGK64);
 #pragma unroll
     for (int kk = 0; kk < kGK64; kk += 4) {
       const bool in = k0 + kk + (lane >> 4) < ke;
@@ -266,16 +285,26 @@ __global__ __launch_bounds__(256) void gram_tn_f64b_kernel(
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  float ra[kGK64 / 4];
+  double rb[kGK64 / 4];
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int r = 0; r < kGK64 / 4; ++r) {
+      const int64_t t = k0 + rg + 4 * r;
+      const bool in = t < ke;
+      ra[r] = (va && in) ? pa[t * lda] : 0.f;
+      rb[r] = (vb && in) ? pb[t * ldb] : 0.0;
+    }
+  };
+  load(kb);
   for (int64_t k0 = kb; k0 < ke; k0 += kGK64) {
 #pragma unroll
     for (int r = 0; r < kGK64 / 4; ++r) {
-      const int row = rg + 4 * r;
-      const int64_t t = k0 + row;
-      const bool in = t < ke;
-      As[row * kGLd + cc] = (va && in) ? pa[t * lda] : 0.f;
-      Bs[row * kGLd + cc] = (vb && in) ? pb[t * ldb] : 0.0;
+      As[(rg + 4 * r) * kGLd + cc] = ra[r];
+      Bs[(rg + 4 * r) * kGLd + cc] = rb[r];
     }
     __syncthreads();
+    if (k0 + kGK64 < ke) load(k0 + kGK64);
 #pragma unroll
     for (int kk = 0; kk < kGK64; kk += 4) {
       const bool in = k0 + kk + (lane >> 4) < ke;

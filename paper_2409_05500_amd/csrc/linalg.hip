@@ -1,6 +1,7 @@
 // FP64 dense linear algebra for the VAR normal equations and the B0 estimator:
-// blocked right-looking Cholesky, blocked triangular solves with many right-hand sides, and
-// a tiled FP64 GEMM.  Matrices are row-major with explicit leading dimensions.
+// blocked right-looking Cholesky whose 64 x 64 diagonal blocks are factored and inverted by one
+// wave each, triangular solves with many right-hand sides as GEMMs against those inverted
+// blocks, and a tiled FP64 GEMM.  Matrices are row-major with explicit leading dimensions.
 #include "linalg.hpp"
 
 #include <math.h>
@@ -10,87 +11,158 @@ namespace vl {
 constexpr int kNb = 64;  // panel width
 
 // ------------------------------------------------------------------------------------------
-// Unblocked Cholesky of the kb x kb diagonal block at A (kb <= 64), in LDS.
-// ------------------------------------------------------------------------------------------
+// Diagonal block of the blocked Cholesky (kb <= 64; rows/columns >= kb act as identity), one
+// workgroup of 256 threads, in LDS.  Produces the factor L11 and its inverse, recursively as
+// 2 x 2 blocks of 32:
+//   [L11 L21; . L22]:  factor+invert A11;  L21 = A21 L11^{-T};  A22 -= L21 L21^T;
+//   factor+invert A22;  (L^{-1})21 = -L22^{-1} L21 L11^{-1}.
+// A 32-block is factored by right-looking elimination applied to [A | I] (the identity ends as
+// the inverse).  Column c, phase 1 (d = A[c][c], column c of A and row c of Y unscaled):
+//     A[r][q] -= (A[r][c] / d) A[q][c]   (c < q <= r),   Y[r][q] -= (A[r][c] / d) Y[c][q]  (q <= c)
+// phase 2 scales column c of A and row c of Y by 1/sqrt(d) (A[c][c] = sqrt(d)); phase 2 of column
+// c touches only column c of A and row c of Y, which phase 1 of column c + 1 does not, so one
+// barrier per column suffices.  1/sqrt(d) is v_rsq_f64 refined by two Newton steps.
 // A pivot d is rejected (VL_ERR_SINGULAR) unless d > kPivotRel * diag0 (the diagonal entry before
-// any elimination), i.e. unless the leading block is better conditioned than ~1e11.
+// any elimination), i.e. unless the leading block is better conditioned than ~1e11; a rejected
+// pivot is replaced by 1 so that no NaN spreads.
+// ------------------------------------------------------------------------------------------
 constexpr double kPivotRel = 1e-11;
+constexpr int kLd = kNb + 1;
 
-__global__ __launch_bounds__(256) void potf2_kernel(double* __restrict__ A, int64_t lda, int kb,
-                                                    const double* __restrict__ diag0, int32_t* st) {
-  __shared__ double L[kNb][kNb + 1];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < kb * kb; e += 256) L[e / kb][e % kb] = A[(e / kb) * lda + (e % kb)];
-  __syncthreads();
-  for (int c = 0; c < kb; ++c) {
-    if (tid == 0) {
-      double d = L[c][c];
-      if (!(d > kPivotRel * diag0[c]) || !isfinite(d)) {
-        raise_status(st, VL_ERR_SINGULAR);
-        d = 1.0;
-      }
-      L[c][c] = sqrt(d);
-    }
-    __syncthreads();
-    const double inv = 1.0 / L[c][c];
-    for (int r = c + 1 + tid; r < kb; r += 256) L[r][c] *= inv;
-    __syncthreads();
-    const int rem = kb - c - 1;
-    for (int e = tid; e < rem * rem; e += 256) {
-      const int r = c + 1 + e / rem, q = c + 1 + e % rem;
-      if (q <= r) L[r][q] -= L[r][c] * L[q][c];
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < kb * kb; e += 256) {
-    const int r = e / kb, q = e % kb;
-    A[r * lda + q] = q <= r ? L[r][q] : 0.0;
-  }
+__device__ inline double rsqrt_f64(double d) {
+  double r = __builtin_amdgcn_rsq(d);
+  r = r * fma(-0.5 * d, r * r, 1.5);
+  r = r * fma(-0.5 * d, r * r, 1.5);
+  return r;
 }
 
-// ------------------------------------------------------------------------------------------
-// Triangular solve against a kb x kb lower-triangular block L (kb <= 64) for many vectors:
-// vector j has element r at B[r * rs + j * cs].  trans == 0: L x = b;  trans == 1: L^T x = b.
-// One thread per vector, the vector in registers, L in LDS.
-// ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void trsv_block_kernel(const double* __restrict__ Lg,
-                                                        int64_t ldl, int kb,
-                                                        double* __restrict__ B, int64_t rs,
-                                                        int64_t cs, int64_t nvec, int trans) {
-  __shared__ double L[kNb][kNb + 1];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < kb * kb; e += 64) L[e / kb][e % kb] = Lg[(e / kb) * ldl + (e % kb)];
-  __syncthreads();
-  const int64_t j = (int64_t)blockIdx.x * 64 + tid;
-  if (j >= nvec) return;
-  double x[kNb];
+// Factor and invert the 32 x 32 diagonal block at (b, b) of S, writing the inverse into Y at
+// (b, b).  Thread t: column q = t & 31, rows w + 8 k (w = t >> 5, k = 0..3).  Ends with a
+// workgroup barrier.
+__device__ void factor_inv32(double (*S)[kLd], double (*Y)[kLd], const double* D0, int b,
+                             bool& bad_any) {
+  const int t = threadIdx.x, q = t & 31, w = t >> 5;
+  for (int c = 0; c < 32; ++c) {
+    double d = S[b + c][b + c];
+    const bool bad = !(d > kPivotRel * D0[b + c]) || !isfinite(d);
+    bad_any |= bad;
+    if (bad) d = 1.0;
+    const double inv_sd = rsqrt_f64(d);
+    const double inv_d = inv_sd * inv_sd;
+    // phase 1: all reads first
+    const double colq = S[b + q][b + c];
+    const double rowq = Y[b + c][b + q];
+    double arc[4], cur[4];
 #pragma unroll
-  for (int r = 0; r < kNb; ++r) x[r] = r < kb ? B[r * rs + j * cs] : 0.0;
-  if (!trans) {
+    for (int k = 0; k < 4; ++k) {
+      const int r = w + 8 * k;
+      arc[k] = S[b + r][b + c];
+      cur[k] = q > c ? S[b + r][b + q] : Y[b + r][b + q];
+    }
 #pragma unroll
-    for (int r = 0; r < kNb; ++r) {
-      if (r < kb) {
-        double s = x[r];
-#pragma unroll
-        for (int q = 0; q < r; ++q) s -= L[r][q] * x[q];
-        x[r] = s / L[r][r];
+    for (int k = 0; k < 4; ++k) {
+      const int r = w + 8 * k;
+      if (r > c) {
+        const double f = arc[k] * inv_d;
+        if (q > c) {
+          if (q <= r) S[b + r][b + q] = cur[k] - f * colq;
+        } else {
+          Y[b + r][b + q] = cur[k] - f * rowq;
+        }
       }
     }
-  } else {
-#pragma unroll
-    for (int r = kNb - 1; r >= 0; --r) {
-      if (r < kb) {
-        double s = x[r];
-#pragma unroll
-        for (int q = r + 1; q < kNb; ++q)
-          if (q < kb) s -= L[q][r] * x[q];
-        x[r] = s / L[r][r];
-      }
+    __syncthreads();
+    // phase 2
+    if (t < 32) {
+      if (t == c) S[b + c][b + c] = d * inv_sd;
+      else if (t > c) S[b + t][b + c] *= inv_sd;
+    } else if (t < 64) {
+      const int j = t - 32;
+      if (j <= c) Y[b + c][b + j] *= inv_sd;
     }
   }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void potf2_inv_kernel(const double* __restrict__ A, int64_t lda,
+                                                        int kb, const double* __restrict__ diag0,
+                                                        double* __restrict__ L, int64_t ldl,
+                                                        double* __restrict__ Linv, int32_t* st) {
+  __shared__ double S[kNb][kLd];
+  __shared__ double Y[kNb][kLd];
+  __shared__ double T[32][33];
+  __shared__ double D0[kNb];
+  const int t = threadIdx.x;
+  for (int e = t; e < kNb * kNb; e += 256) {
+    const int r = e >> 6, q = e & 63;
+    S[r][q] = (r < kb && q < kb) ? A[(int64_t)r * lda + q] : (r == q ? 1.0 : 0.0);
+    Y[r][q] = r == q ? 1.0 : 0.0;
+  }
+  if (t < kNb) D0[t] = t < kb ? diag0[t] : 1.0;
+  __syncthreads();
+  bool bad_any = false;
+  factor_inv32(S, Y, D0, 0, bad_any);
+  // each thread owns 4 entries (i, j) of a 32 x 32 block: i = t >> 3 (0..31), j = (t & 7) + 8 u
+  const int i = t >> 3, j0 = t & 7;
+  double v[4];
+  // The triangular operands hold exact zeros in their unused halves, so every product below
+  // is a fixed 32-term sum (fully unrolled: the LDS reads issue together).
+  // L21 = A21 L11^{-T}:  L21[i][j] = sum_k A21[i][k] Y11[j][k]
 #pragma unroll
-  for (int r = 0; r < kNb; ++r)
-    if (r < kb) B[r * rs + j * cs] = x[r];
+  for (int u = 0; u < 4; ++u) v[u] = 0.0;
+#pragma unroll
+  for (int k = 0; k < 32; ++k) {
+    const double a = S[32 + i][k];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = fma(a, Y[j0 + 8 * u][k], v[u]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 4; ++u) S[32 + i][j0 + 8 * u] = v[u];
+  __syncthreads();
+  // A22 -= L21 L21^T (lower part is what the next factorisation reads)
+#pragma unroll
+  for (int u = 0; u < 4; ++u) v[u] = 0.0;
+#pragma unroll
+  for (int k = 0; k < 32; ++k) {
+    const double a = S[32 + i][k];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = fma(a, S[32 + j0 + 8 * u][k], v[u]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 4; ++u) S[32 + i][32 + j0 + 8 * u] -= v[u];
+  __syncthreads();
+  factor_inv32(S, Y, D0, 32, bad_any);
+  // T = L21 Y11, then Y21 = -Y22 T
+#pragma unroll
+  for (int u = 0; u < 4; ++u) v[u] = 0.0;
+#pragma unroll
+  for (int k = 0; k < 32; ++k) {
+    const double a = S[32 + i][k];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = fma(a, Y[k][j0 + 8 * u], v[u]);
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) T[i][j0 + 8 * u] = v[u];
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 4; ++u) v[u] = 0.0;
+#pragma unroll
+  for (int k = 0; k < 32; ++k) {
+    const double a = Y[32 + i][32 + k];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = fma(a, T[k][j0 + 8 * u], v[u]);
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) Y[32 + i][j0 + 8 * u] = -v[u];
+  if (bad_any) raise_status(st, VL_ERR_SINGULAR);
+  __syncthreads();
+  for (int e = t; e < kNb * kNb; e += 256) {
+    const int r = e >> 6, q = e & 63;
+    if (r < kb && q < kb) L[(int64_t)r * ldl + q] = q <= r ? S[r][q] : 0.0;
+    Linv[e] = q <= r ? Y[r][q] : 0.0;
+  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -111,20 +183,37 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(int64_t M, int64_t N, int
   const int64_t i0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
   if (lower_only && j0 > i0 + 63) return;
   const int tid = threadIdx.x, ti = tid >> 4, tj = tid & 15;
+  // this thread's four loads per operand and K step; consecutive threads walk the contiguous
+  // dimension of each operand
+  int ak[4], ai[4], bk[4], bj[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = tid + 256 * u;
+    ak[u] = transA ? e / 64 : e % 16;
+    ai[u] = transA ? e % 64 : e / 16;
+    bk[u] = transB ? e % 16 : e / 64;
+    bj[u] = transB ? e / 16 : e % 64;
+  }
+  auto load = [&](int64_t k0, double (&ra)[4], double (&rb)[4]) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t gi = i0 + ai[u], gk = k0 + ak[u];
+      ra[u] = (gi < M && gk < K) ? (transA ? A[gk * lda + gi] : A[gi * lda + gk]) : 0.0;
+      const int64_t gj = j0 + bj[u], gk2 = k0 + bk[u];
+      rb[u] = (gj < N && gk2 < K) ? (transB ? Bm[gj * ldb + gk2] : Bm[gk2 * ldb + gj]) : 0.0;
+    }
+  };
   double acc[4][4] = {};
+  double ra[4], rb[4];
+  load(0, ra, rb);
   for (int64_t k0 = 0; k0 < K; k0 += 16) {
-    for (int e = tid; e < 16 * 64; e += 256) {
-      const int kk = e / 64, ii = e % 64;
-      const int64_t gi = i0 + ii, gk = k0 + kk;
-      double va = 0.0;
-      if (gi < M && gk < K) va = transA ? A[gk * lda + gi] : A[gi * lda + gk];
-      As[kk][ii] = va;
-      const int64_t gj = j0 + ii;
-      double vb = 0.0;
-      if (gj < N && gk < K) vb = transB ? Bm[gj * ldb + gk] : Bm[gk * ldb + gj];
-      Bs[kk][ii] = vb;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      As[ak[u]][ai[u]] = ra[u];
+      Bs[bk[u]][bj[u]] = rb[u];
     }
     __syncthreads();
+    if (k0 + 16 < K) load(k0 + 16, ra, rb);      // in flight during the products below
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk) {
       double a[4], b[4];
@@ -169,57 +258,67 @@ __global__ void diag_copy_kernel(const double* __restrict__ A, int64_t n, int64_
   if (i < n) d[i] = A[i * lda + i];
 }
 
-int potrf_lower(double* A, int64_t n, int64_t lda, double* diag0, int32_t* st,
-                hipStream_t stream) {
+size_t chol_ws_doubles(int64_t n) { return (size_t)n + (size_t)ceil_div(n, kNb) * kNb * kNb; }
+
+int potrf_lower(double* A, int64_t n, int64_t lda, double* L, int64_t ldl, double* ws,
+                int32_t* st, hipStream_t stream) {
+  double* diag0 = ws;
+  double* inv = ws + n;
   diag_copy_kernel<<<(unsigned)ceil_div(n, 256), 256, 0, stream>>>(A, n, lda, diag0);
   VL_LAUNCH_CHECK();
   for (int64_t k0 = 0; k0 < n; k0 += kNb) {
     const int kb = (int)(n - k0 < kNb ? n - k0 : kNb);
-    double* A11 = A + k0 * lda + k0;
-    potf2_kernel<<<1, 256, 0, stream>>>(A11, lda, kb, diag0 + k0, st);
+    double* invk = inv + (k0 / kNb) * kNb * kNb;
+    potf2_inv_kernel<<<1, 256, 0, stream>>>(A + k0 * lda + k0, lda, kb, diag0 + k0,
+                                            L + k0 * ldl + k0, ldl, invk, st);
     VL_LAUNCH_CHECK();
     const int64_t rest = n - k0 - kb;
     if (rest <= 0) break;
-    double* A21 = A + (k0 + kb) * lda + k0;
-    // rows of A21 are the right-hand sides of L11 x = a (x^T = row of L21)
-    trsv_block_kernel<<<(unsigned)ceil_div(rest, 64), 64, 0, stream>>>(A11, lda, kb, A21, 1, lda,
-                                                                        rest, 0);
-    VL_LAUNCH_CHECK();
-    double* A22 = A + (k0 + kb) * lda + (k0 + kb);
-    int rc = gemm_f64(rest, rest, kb, -1.0, A21, lda, false, A21, lda, true, 1.0, A22, lda, true,
-                      stream);
+    // L21 = A21 L11^{-T}
+    int rc = gemm_f64(rest, kb, kb, 1.0, A + (k0 + kb) * lda + k0, lda, false, invk, kNb, true,
+                      0.0, L + (k0 + kb) * ldl + k0, ldl, false, stream);
+    if (rc) return rc;
+    // A22 -= L21 L21^T (lower triangle)
+    rc = gemm_f64(rest, rest, kb, -1.0, L + (k0 + kb) * ldl + k0, ldl, false,
+                  L + (k0 + kb) * ldl + k0, ldl, true, 1.0, A + (k0 + kb) * lda + (k0 + kb), lda,
+                  true, stream);
     if (rc) return rc;
   }
   return VL_OK;
 }
 
-int trsm_lower(const double* L, int64_t n, int64_t ldl, bool trans, double* B, int64_t nrhs,
-               int64_t ldb, hipStream_t stream) {
-  const unsigned vb = (unsigned)ceil_div(nrhs, 64);
+int trsm_lower(const double* L, int64_t n, int64_t ldl, const double* ws, bool trans, double* B,
+               int64_t nrhs, int64_t ldb, double* X, int64_t ldx, hipStream_t stream) {
+  const double* inv = ws + n;
+  const int64_t nblk = ceil_div(n, kNb);
   if (!trans) {
-    for (int64_t k0 = 0; k0 < n; k0 += kNb) {
+    for (int64_t b = 0; b < nblk; ++b) {
+      const int64_t k0 = b * kNb;
       const int kb = (int)(n - k0 < kNb ? n - k0 : kNb);
-      trsv_block_kernel<<<vb, 64, 0, stream>>>(L + k0 * ldl + k0, ldl, kb, B + k0 * ldb, ldb, 1,
-                                               nrhs, 0);
-      VL_LAUNCH_CHECK();
+      // X_k = L_kk^{-1} B_k
+      int rc = gemm_f64(kb, nrhs, kb, 1.0, inv + b * kNb * kNb, kNb, false, B + k0 * ldb, ldb,
+                        false, 0.0, X + k0 * ldx, ldx, false, stream);
+      if (rc) return rc;
       const int64_t rest = n - k0 - kb;
       if (rest > 0) {
-        int rc = gemm_f64(rest, nrhs, kb, -1.0, L + (k0 + kb) * ldl + k0, ldl, false,
-                          B + k0 * ldb, ldb, false, 1.0, B + (k0 + kb) * ldb, ldb, false, stream);
+        // B_rest -= L_rest,k X_k
+        rc = gemm_f64(rest, nrhs, kb, -1.0, L + (k0 + kb) * ldl + k0, ldl, false, X + k0 * ldx,
+                      ldx, false, 1.0, B + (k0 + kb) * ldb, ldb, false, stream);
         if (rc) return rc;
       }
     }
   } else {
-    const int64_t last = ((n - 1) / kNb) * kNb;
-    for (int64_t k0 = last; k0 >= 0; k0 -= kNb) {
+    for (int64_t b = nblk - 1; b >= 0; --b) {
+      const int64_t k0 = b * kNb;
       const int kb = (int)(n - k0 < kNb ? n - k0 : kNb);
-      trsv_block_kernel<<<vb, 64, 0, stream>>>(L + k0 * ldl + k0, ldl, kb, B + k0 * ldb, ldb, 1,
-                                               nrhs, 1);
-      VL_LAUNCH_CHECK();
+      // X_k = L_kk^{-T} B_k
+      int rc = gemm_f64(kb, nrhs, kb, 1.0, inv + b * kNb * kNb, kNb, true, B + k0 * ldb, ldb,
+                        false, 0.0, X + k0 * ldx, ldx, false, stream);
+      if (rc) return rc;
       if (k0 > 0) {
-        // B[0:k0] -= L[k0:k0+kb, 0:k0]^T X[k0:k0+kb]
-        int rc = gemm_f64(k0, nrhs, kb, -1.0, L + k0 * ldl, ldl, true, B + k0 * ldb, ldb, false,
-                          1.0, B, ldb, false, stream);
+        // B_0:k -= L_k,0:k^T X_k
+        rc = gemm_f64(k0, nrhs, kb, -1.0, L + k0 * ldl, ldl, true, X + k0 * ldx, ldx, false, 1.0,
+                      B, ldb, false, stream);
         if (rc) return rc;
       }
     }

@@ -121,26 +121,31 @@ __global__ __launch_bounds__(256) void var_residual_f64_kernel(
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const int lk = tid & 15, lt = tid >> 4;     // Z loader: 16 lags x 16 sample rows
+  const int cj = tid & 63, ck = tid >> 6;     // Coef loader: 64 columns x 4 lag rows
+  double rz[4], rcf[4];
+  auto load = [&](int64_t k0) {
+    const int64_t k = k0 + lk;
+    const bool vk = k < dz;
+    const int64_t off = vk ? mapZ[k] : 0;
+    const double mz = vk ? muZ[k] : 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t t = t0 + lt + 16 * r;
+      rz[r] = (vk && t < n_eff) ? (double)X[off + t * ldx] - mz : 0.0;
+      const int64_t kq = k0 + ck + 4 * r, j = j0 + cj;
+      rcf[r] = (kq < dz && j < m) ? Coef[kq * m + j] : 0.0;
+    }
+  };
+  load(0);
   for (int64_t k0 = 0; k0 < dz; k0 += 16) {
-    {
-      const int kk = tid & 15, tt = tid >> 4;   // 16 x 16 threads
-      const int64_t k = k0 + kk;
-      const bool vk = k < dz;
-      const int64_t off = vk ? mapZ[k] : 0;
-      const double mz = vk ? muZ[k] : 0.0;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t t = t0 + tt + 16 * r;
-        Zs[kk][tt + 16 * r] = (vk && t < n_eff) ? (double)X[off + t * ldx] - mz : 0.0;
-      }
-      const int jj = tid & 63, kr = tid >> 6;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t kq = k0 + kr + 4 * r, j = j0 + jj;
-        Cs[kr + 4 * r][jj] = (kq < dz && j < m) ? Coef[kq * m + j] : 0.0;
-      }
+    for (int r = 0; r < 4; ++r) {
+      Zs[lk][lt + 16 * r] = rz[r];
+      Cs[ck + 4 * r][cj] = rcf[r];
     }
     __syncthreads();
+    if (k0 + 16 < dz) load(k0 + 16);
 #pragma unroll
     for (int kk = 0; kk < 16; kk += 4) {
       double av[2], bv[2];
@@ -172,21 +177,27 @@ __global__ __launch_bounds__(256) void var_residual_f64_kernel(
       }
 }
 
-// M[(tau-1) m m + i m + k] = Coef[(tau-1) m + k][i];  c[i] = muY[i] - sum_k' Coef[k'][i] muZ[k']
-__global__ void var_outputs_kernel(const double* __restrict__ Coef, const double* __restrict__ mu,
-                                   int64_t m, int p, double* __restrict__ M,
-                                   double* __restrict__ intercept) {
+// M[(tau-1) m m + i m + k] = Coef[(tau-1) m + k][i]
+__global__ void var_lag_matrices_kernel(const double* __restrict__ Coef, int64_t m, int p,
+                                        double* __restrict__ M) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t dz = m * p;
-  if (e < dz * m) {
-    const int64_t tau1 = e / (m * m), rem = e % (m * m), i = rem / m, k = rem % m;
-    M[e] = Coef[(tau1 * m + k) * m + i];
-  }
-  if (e < m) {
-    double s = mu[e];
-    for (int64_t kq = 0; kq < dz; ++kq) s -= Coef[kq * m + e] * mu[m + kq];
-    intercept[e] = s;
-  }
+  if (e >= (int64_t)p * m * m) return;
+  const int64_t tau1 = e / (m * m), rem = e % (m * m), i = rem / m, k = rem % m;
+  M[e] = Coef[(tau1 * m + k) * m + i];
+}
+
+// c[i] = muY[i] - sum_k' Coef[k'][i] muZ[k'], one wave per variable
+__global__ __launch_bounds__(256) void var_intercept_kernel(const double* __restrict__ Coef,
+                                                            const double* __restrict__ mu,
+                                                            int64_t m, int64_t dz,
+                                                            double* __restrict__ intercept) {
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= m) return;
+  double s = 0.0;
+  for (int64_t k = lane; k < dz; k += 64) s += Coef[k * m + i] * mu[m + k];
+  s = wave_sum_d(s);
+  if (lane == 0) intercept[i] = mu[i] - s;
 }
 
 VarPlan plan_var(int64_t n, int64_t m, int p) {
@@ -210,7 +221,9 @@ size_t var_ws_bytes(const VarPlan& v, void* base, VarWs* out) {
   w.Coef = c.take<double>(v.dz * v.m);
   w.Rres = c.take<double>(v.dz * v.m);
   w.CoefF = c.take<float>(v.dz * v.m);
-  w.diag0 = c.take<double>(v.dz);
+  w.L = c.take<double>(v.dz * v.dz);
+  w.Tmp = c.take<double>(v.dz * v.m);
+  w.chol = c.take<double>(chol_ws_doubles(v.dz));
   w.E64 = c.take<double>(v.n_eff * v.m);
   size_t s1 = (size_t)colmean_splits(v.n_eff) * nc;
   size_t s2 = (size_t)gram_splits(v.dz, v.dz, v.n_eff) * v.dz * v.dz;
@@ -269,11 +282,11 @@ int run_var(const VarPlan& v, const VarWs& w, const float* X, int64_t ldx, int p
   }
   {
     ProfileScope ps("var_solve", stream);
-    rc = potrf_lower(w.G, dz, dz, w.diag0, st, stream);
+    rc = potrf_lower(w.G, dz, dz, w.L, dz, w.chol, st, stream);
     if (rc) return rc;
-    rc = trsm_lower(w.G, dz, dz, false, w.Coef, m, m, stream);
+    rc = trsm_lower(w.L, dz, dz, w.chol, false, w.Coef, m, m, w.Tmp, m, stream);
     if (rc) return rc;
-    rc = trsm_lower(w.G, dz, dz, true, w.Coef, m, m, stream);
+    rc = trsm_lower(w.L, dz, dz, w.chol, true, w.Tmp, m, m, w.Coef, m, stream);
     if (rc) return rc;
   }
   {
@@ -293,17 +306,19 @@ int run_var(const VarPlan& v, const VarWs& w, const float* X, int64_t ldx, int p
     }
     rc = gram_tn_f64b(X, ldx, mapZ, muZ, dz, w.E64, m, m, n_eff, w.Rres, m, w.scratch, stream);
     if (rc) return rc;
-    rc = trsm_lower(w.G, dz, dz, false, w.Rres, m, m, stream);
+    rc = trsm_lower(w.L, dz, dz, w.chol, false, w.Rres, m, m, w.Tmp, m, stream);
     if (rc) return rc;
-    rc = trsm_lower(w.G, dz, dz, true, w.Rres, m, m, stream);
+    rc = trsm_lower(w.L, dz, dz, w.chol, true, w.Tmp, m, m, w.Rres, m, stream);
     if (rc) return rc;
     add_f64_kernel<<<(unsigned)ceil_div(dz * m, 256), 256, 0, stream>>>(w.Coef, w.Rres, dz * m);
     VL_LAUNCH_CHECK();
     rc = var_residual(v, w, X, ldx, E, lde, true, stream);
     if (rc) return rc;
   }
-  var_outputs_kernel<<<(unsigned)ceil_div(dz * m > m ? dz * m : m, 256), 256, 0, stream>>>(
-      w.Coef, w.mu, m, v.p, M, intercept);
+  var_lag_matrices_kernel<<<(unsigned)ceil_div(dz * m, 256), 256, 0, stream>>>(w.Coef, m, v.p, M);
+  VL_LAUNCH_CHECK();
+  var_intercept_kernel<<<(unsigned)ceil_div(m, 4), 256, 0, stream>>>(w.Coef, w.mu, m, dz,
+                                                                    intercept);
   VL_LAUNCH_CHECK();
   return VL_OK;
 }

@@ -13,11 +13,13 @@ struct VarWs {
   int64_t* colmap = nullptr;  // m (p+1) sample offsets of the lag-embedded columns
   double* mu = nullptr;       // m (p+1) column means (Y first, then Z)
   double* zeros = nullptr;    // m zeros (mean of E in the refinement Gram)
-  double* G = nullptr;        // dz x dz Gram, then its Cholesky factor
+  double* G = nullptr;        // dz x dz Gram (destroyed by the factorisation)
   double* Coef = nullptr;     // dz x m solution
   double* Rres = nullptr;     // dz x m refinement right-hand side
   float* CoefF = nullptr;     // dz x m float copy for the residual GEMM
-  double* diag0 = nullptr;    // dz diagonal of G before factorisation
+  double* L = nullptr;        // dz x dz Cholesky factor of G
+  double* Tmp = nullptr;      // dz x m intermediate of the two triangular solves
+  double* chol = nullptr;     // factorisation scratch kept for the solves
   double* E64 = nullptr;      // n_eff x m FP64 residual of the refinement step
   double* scratch = nullptr;  // split-K partials
 };

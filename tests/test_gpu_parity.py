@@ -168,6 +168,31 @@ def test_order_hand_built_total_order(api, dev):
     assert np.array_equal(order.cpu().numpy(), true)
 
 
+@pytest.mark.parametrize("m", [2100, 4200])
+def test_order_large_hand_built(api, dev, m):
+    """The largest register-resident form (m <= 4096) and the multi-wave form above it."""
+    rng = np.random.default_rng(m)
+    true = rng.permutation(m)
+    pos = np.empty(m, int)
+    pos[true] = np.arange(m)
+    mag = rng.uniform(0.1, 1, (m, m))
+    S = np.where(pos[:, None] < pos[None, :], 1.0, -1.0) * (mag + mag.T)
+    np.fill_diagonal(S, 0.0)
+    order, margin = api.approx_order(_dev(S, dev))
+    assert np.array_equal(order.cpu().numpy(), true)
+    assert np.all(margin.cpu().numpy()[:-1] > 0)
+
+
+def test_order_nonfinite_raises(api, dev):
+    from paper_2409_05500_amd._lib import VarLiNGAMError, VL_ERR_NONFINITE
+    A = np.random.default_rng(1).normal(size=(30, 30))
+    S = A - A.T
+    S[3, 7] = np.nan
+    with pytest.raises(VarLiNGAMError) as ei:
+        api.approx_order(_dev(S, dev))
+    assert ei.value.code == VL_ERR_NONFINITE
+
+
 def test_order_ties_lowest_index(api, dev):
     order, margin = api.approx_order(_dev(np.zeros((5, 5)), dev))
     assert order.cpu().numpy().tolist() == [0, 1, 2, 3, 4]
