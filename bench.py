@@ -27,8 +27,21 @@ METRIC = "pairwise m²n sample-evals/s + end-to-end fit time vs plain FP32, m=40
 # for log cosh, exp for the Gaussian weight).
 TRANS_PEAK = 256 * 32 * 2.4e9
 TRANS_PER_EVAL = 3
+# HBM bytes per launch of the pairwise kernel, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs
+# of this workload (KiB per dispatch x 1024), each scaled by the counter's reading for a plain
+# 256 MiB device copy (FETCH_SIZE reads half of the bytes a copy reads: x2; WRITE_SIZE reads them
+# exactly: x1).  Keyed by the SHA-256 of the kernel source the counters were taken with; any
+# other source reports null.
+MEASURED_TRAFFIC = {}
 STAGES = ("var_gram", "var_solve", "var_residual", "var_refine", "pairwise_cov",
           "pairwise_prep", "pairwise_moments", "pairwise_combine", "order", "estimate_b")
+
+
+def measured_traffic():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2409_05500_amd", "csrc", "pairwise.hip")
+    digest = hashlib.sha256(open(path, "rb").read()).hexdigest()
+    return MEASURED_TRAFFIC.get(digest)
 
 
 def cpu_baseline(E64, cols: int):
@@ -62,6 +75,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cols", type=int, default=160)
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB first (a plain copy "
+                         "kernel of known traffic, for calibrating hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path's multi-GPU "
@@ -80,6 +96,13 @@ def main():
     n, m, p = wl.n, wl.m, wl.p
     n_eff = n - p
     evals = m * (m - 1) * n_eff
+
+    if args.copy_calibration_mb:
+        src = torch.empty(args.copy_calibration_mb << 18, dtype=torch.float32, device=dev)
+        src.fill_(1.0)
+        dst = src.clone()          # reads and writes copy_calibration_mb MiB once
+        torch.cuda.synchronize()
+        del src, dst
 
     fit = api.Fitter(n, m, p, "mixed", dev)
     for _ in range(args.warmup):
@@ -126,7 +149,8 @@ def main():
                    "precision": "mixed", "seed": args.seed},
         "roofline": {"kernel": "pairwise_moments_kernel", "bound": "alu",
                      "achieved": achieved / 1e12, "peak": TRANS_PEAK / 1e12,
-                     "unit": "Ttrans/s", "frac": achieved / TRANS_PEAK, "traffic": None},
+                     "unit": "Ttrans/s", "frac": achieved / TRANS_PEAK,
+                     "traffic": measured_traffic()},
         "pairwise_kernel_ms": k_s * 1e3,
         "pairwise_kernel_sample_evals_per_s": evals / k_s,
         "sample_evals_per_step": evals,
