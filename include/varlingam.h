@@ -101,6 +101,27 @@ int pairwise_stats(const float* E, int64_t n_eff, int64_t m, int64_t lde, int pr
                    int32_t* dev_status, void* stream);
 
 /* ------------------------------------------------------------------------------------- */
+/* Gradient of the pairwise score (the precompute of Sec. 4.2 steps 1-2 with Eq. 1-2 made  */
+/* differentiable): dE = d<G, S(E)>/dE for an m x m cotangent G.                           */
+/*                                                                                        */
+/* E     in, n_eff x m float32, leading dimension lde >= m (the same input as              */
+/*       pairwise_stats; the forward statistics are recomputed inside the call, nothing of  */
+/*       size m^2 n is stored).                                                            */
+/* G     in, m x m float64 row-major cotangent of S (only G - G^T matters: S is            */
+/*       antisymmetric; the diagonal is ignored).                                          */
+/* dE    out, n_eff x m float32, leading dimension ldde >= m.                              */
+/* prec  arithmetic of the recomputed covariance (VL_PREC_FP32 or VL_PREC_MIXED); the      */
+/*       per-sample terms are FP32, per-pair coefficients and column reductions FP64.      */
+/* Deterministic: no floating-point atomics; repeated calls give identical bits.           */
+/* Host errors: m < 2, n_eff < 2, m > 65536 -> VL_ERR_SHAPE.                                */
+/* Device errors: as pairwise_stats (VL_ERR_NONFINITE, VL_ERR_DEGENERATE).                  */
+/* ------------------------------------------------------------------------------------- */
+size_t pairwise_stats_backward_workspace_bytes(int64_t n_eff, int64_t m, int prec);
+int pairwise_stats_backward(const float* E, int64_t n_eff, int64_t m, int64_t lde, int prec,
+                            const double* G, float* dE, int64_t ldde, void* ws, size_t ws_bytes,
+                            int32_t* dev_status, void* stream);
+
+/* ------------------------------------------------------------------------------------- */
 /* Lookup-only causal ordering (Alg. 1 main loop with Eq. 3): m steps over the static S.  */
 /* At step k, with U the variables not yet ordered,                                       */
 /*   M_i = sum_{j in U, j != i} min(0, S[i,j])^2,   c_k = argmin_{i in U} M_i              */
@@ -139,7 +160,8 @@ int estimate_B(const double* Cov, const double* M, const int32_t* order, int64_t
 /* event pair, on the caller's stream, around every launch of the named stages ("*" = all; */
 /* a comma-separated list; NULL or "" = off) and clears earlier totals.  Stage names:       */
 /*   var_gram, var_solve, var_residual, var_refine, pairwise_cov, pairwise_prep,            */
-/*   pairwise_moments, pairwise_combine, order, estimate_b.                                 */
+/*   pairwise_moments, pairwise_combine, backward_prep, backward_owner, backward_tail,       */
+/*   order, estimate_b.                                                                     */
 /* varlingam_profile_read() waits for the recorded events of one stage and returns the      */
 /* accumulated milliseconds and the number of recorded launches.  Thread-safe.              */
 /* ------------------------------------------------------------------------------------- */

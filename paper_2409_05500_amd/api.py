@@ -92,6 +92,49 @@ def pairwise_stats(E: torch.Tensor, prec="mixed", status: "DeviceStatus | None" 
     return Hx, Hr, S, Cov
 
 
+def pairwise_stats_backward(E: torch.Tensor, G: torch.Tensor, prec="mixed",
+                            status: "DeviceStatus | None" = None) -> torch.Tensor:
+    """dE = d<G, S(E)>/dE (n_eff x m f32) for the m x m f64 cotangent G of the score matrix."""
+    _require(E, torch.float32, "E")
+    n_eff, m = E.shape
+    dev = E.device
+    G = G.to(device=dev, dtype=torch.float64).contiguous()
+    if G.shape != (m, m):
+        raise ValueError(f"G must be {m} x {m}, got {tuple(G.shape)}")
+    dE = torch.empty((n_eff, m), dtype=torch.float32, device=dev)
+    nb = lib.pairwise_stats_backward_workspace_bytes(n_eff, m, _prec(prec))
+    ws = _workspace(nb, dev)
+    st = status if status is not None else DeviceStatus(dev)
+    check(lib.pairwise_stats_backward(E.data_ptr(), n_eff, m, E.stride(0), _prec(prec),
+                                      G.data_ptr(), dE.data_ptr(), dE.stride(0), ws.data_ptr(),
+                                      ws.numel(), st.ptr, _stream_ptr(dev)),
+          "pairwise_stats_backward")
+    if status is None:
+        st.read("pairwise_stats_backward")
+    return dE
+
+
+class PairwiseScore(torch.autograd.Function):
+    """S = score(E) with a backward through the HIP gradient kernels (the forward statistics
+    are recomputed in the backward; only E is saved)."""
+
+    @staticmethod
+    def forward(ctx, E, prec="mixed"):
+        ctx.prec = prec
+        ctx.save_for_backward(E)
+        return pairwise_stats(E.detach(), prec)[2]
+
+    @staticmethod
+    def backward(ctx, G):
+        (E,) = ctx.saved_tensors
+        return pairwise_stats_backward(E.detach(), G, ctx.prec), None
+
+
+def pairwise_score(E: torch.Tensor, prec="mixed") -> torch.Tensor:
+    """Differentiable S(E) (m x m f64) for an n_eff x m f32 device tensor."""
+    return PairwiseScore.apply(E, prec)
+
+
 def approx_order(S: torch.Tensor, status: "DeviceStatus | None" = None):
     """(order [m] int32, margin [m] f64) from the m x m score matrix."""
     _require(S, torch.float64, "S")

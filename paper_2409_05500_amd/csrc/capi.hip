@@ -1,4 +1,5 @@
 // extern "C" entry points: argument validation, workspace carving, status handling.
+#include "backward.hpp"
 #include "estimate_b.hpp"
 #include "order.hpp"
 #include "pairwise.hpp"
@@ -83,6 +84,30 @@ int pairwise_stats(const float* E, int64_t n_eff, int64_t m, int64_t lde, int pr
   int rc = begin(dev_status, s);
   if (rc) return rc;
   return run_pairwise(p, w, E, lde, prec, Hx, Hr, S, Cov, nullptr, dev_status, s);
+}
+
+// ----------------------------------------------------------------------------------------
+size_t pairwise_stats_backward_workspace_bytes(int64_t n_eff, int64_t m, int prec) {
+  (void)prec;
+  if (m < 2 || n_eff < 2 || m > 65536) return 0;
+  return bwd_ws_bytes(plan_backward(n_eff, m), nullptr, nullptr);
+}
+
+int pairwise_stats_backward(const float* E, int64_t n_eff, int64_t m, int64_t lde, int prec,
+                            const double* G, float* dE, int64_t ldde, void* ws, size_t ws_bytes,
+                            int32_t* dev_status, void* stream) {
+  if (!E || !G || !dE || !dev_status || !valid_prec(prec)) return VL_ERR_INVALID_ARG;
+  if (m < 2 || n_eff < 2 || m > 65536) return VL_ERR_SHAPE;
+  if (lde < m || ldde < m) return VL_ERR_INVALID_ARG;
+  const BwdPlan b = plan_backward(n_eff, m);
+  if (!ws || ws_bytes < bwd_ws_bytes(b, nullptr, nullptr) || !aligned256(ws))
+    return VL_ERR_WORKSPACE;
+  BwdWs w;
+  bwd_ws_bytes(b, ws, &w);
+  hipStream_t s = as_stream(stream);
+  int rc = begin(dev_status, s);
+  if (rc) return rc;
+  return run_backward(b, w, E, lde, prec, G, dE, ldde, dev_status, s);
 }
 
 // ----------------------------------------------------------------------------------------

@@ -351,6 +351,16 @@ size_t scratch_doubles(const PairwisePlan& p) {
   return a > b ? a : b;
 }
 
+int standardize_to(const float* E, int64_t lde, int64_t n_eff, int64_t m, const double* mu,
+                   const double* cov, float* Xs, int64_t n_pad, int64_t m_pad, int32_t* st,
+                   hipStream_t stream) {
+  dim3 g((unsigned)ceil_div(n_pad, 64), (unsigned)ceil_div(m_pad, 64));
+  standardize_transpose_kernel<<<g, 256, 0, stream>>>(E, lde, n_eff, m, mu, cov, Xs, n_pad,
+                                                       m_pad, st);
+  VL_LAUNCH_CHECK();
+  return VL_OK;
+}
+
 int run_pairwise(const PairwisePlan& p, const PairwiseWs& w, const float* E, int64_t lde,
                  int prec, double* Hx, double* Hr, double* S, double* Cov, double* mom,
                  int32_t* st, hipStream_t stream) {
@@ -368,10 +378,8 @@ int run_pairwise(const PairwisePlan& p, const PairwiseWs& w, const float* E, int
   }
   {
     ProfileScope ps("pairwise_prep", stream);
-    dim3 g1((unsigned)ceil_div(p.n_pad, 64), (unsigned)ceil_div(p.m_pad, 64));
-    standardize_transpose_kernel<<<g1, 256, 0, stream>>>(E, lde, n_eff, m, w.mu, cov, w.Xs,
-                                                          p.n_pad, p.m_pad, st);
-    VL_LAUNCH_CHECK();
+    int rc = standardize_to(E, lde, n_eff, m, w.mu, cov, w.Xs, p.n_pad, p.m_pad, st, stream);
+    if (rc) return rc;
     hx_kernel<<<(unsigned)m, 256, 0, stream>>>(w.Xs, p.n_pad, n_eff, Hx, w.momx);
     VL_LAUNCH_CHECK();
     pair_coef_kernel<<<(unsigned)ceil_div(p.m_pad * p.m_pad, 256), 256, 0, stream>>>(

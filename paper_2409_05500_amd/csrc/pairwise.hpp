@@ -31,6 +31,11 @@ PairwisePlan plan_pairwise(int64_t n_eff, int64_t m);
 size_t scratch_doubles(const PairwisePlan& p);
 // Total workspace bytes; with base != nullptr also fills *out with the carved pointers.
 size_t pairwise_ws_bytes(const PairwisePlan& p, void* base, PairwiseWs* out);
+// Standardise E with the given means and covariance diagonal into the variable-major Xs
+// (m_pad x n_pad, zero padded).  n_pad >= n_eff, m_pad >= m.
+int standardize_to(const float* E, int64_t lde, int64_t n_eff, int64_t m, const double* mu,
+                   const double* cov, float* Xs, int64_t n_pad, int64_t m_pad, int32_t* st,
+                   hipStream_t stream);
 // mom (nullable): 2 m^2 doubles, (A, B) per ordered pair, for tests and the backward pass.
 int run_pairwise(const PairwisePlan& p, const PairwiseWs& w, const float* E, int64_t lde,
                  int prec, double* Hx, double* Hr, double* S, double* Cov, double* mom,

@@ -53,6 +53,10 @@ def test_workspace_queries(L):
     assert lib.approx_order_workspace_bytes(400) >= 400 * 8
     assert lib.approx_order_workspace_bytes(0) == 0
     assert lib.estimate_B_workspace_bytes(400, 2) >= 2 * 400 * 400 * 8
+    # backward: at least the forward's workspace plus dL/dx and the standardised copy
+    assert lib.pairwise_stats_backward_workspace_bytes(10000, 400, 1) > \
+        lib.pairwise_stats_workspace_bytes(10000, 400, 1) + 2 * 400 * 10000 * 4
+    assert lib.pairwise_stats_backward_workspace_bytes(10, 1, 1) == 0
 
 
 FAKE = 0x10000   # a non-null, 256-aligned dummy pointer: never dereferenced on these paths
@@ -84,6 +88,14 @@ def test_host_validation_without_gpu(L):
     assert lib.estimate_B(FAKE, None, FAKE, 4, 1, FAKE, FAKE, FAKE, 1 << 30, FAKE,
                           None) == L.VL_ERR_INVALID_ARG
     assert lib.approx_order(FAKE, 4, FAKE, FAKE, FAKE, 8, FAKE, None) == L.VL_ERR_WORKSPACE
+    # backward: null cotangent, shape, leading dimension of dE, workspace
+    bw = lib.pairwise_stats_backward
+    assert bw(FAKE, 100, 4, 4, 1, None, FAKE, 4, FAKE, 1 << 30, FAKE, None) == L.VL_ERR_INVALID_ARG
+    assert bw(FAKE, 100, 1, 4, 1, FAKE, FAKE, 4, FAKE, 1 << 30, FAKE, None) == L.VL_ERR_SHAPE
+    assert bw(FAKE, 1, 4, 4, 1, FAKE, FAKE, 4, FAKE, 1 << 30, FAKE, None) == L.VL_ERR_SHAPE
+    assert bw(FAKE, 100, 4, 4, 1, FAKE, FAKE, 3, FAKE, 1 << 30, FAKE, None) == L.VL_ERR_INVALID_ARG
+    assert bw(FAKE, 100, 4, 4, 2, FAKE, FAKE, 4, FAKE, 1 << 30, FAKE, None) == L.VL_ERR_INVALID_ARG
+    assert bw(FAKE, 100, 4, 4, 1, FAKE, FAKE, 4, FAKE, 64, FAKE, None) == L.VL_ERR_WORKSPACE
 
 
 def test_build_flags_disable_packed_fp32():

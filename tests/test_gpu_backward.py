@@ -1,0 +1,173 @@
+"""GPU parity of the score gradient dE = d<G, S(E)>/dE (pairwise_stats_backward, through the C
+ABI) against the FP64 references of oracle/backward.py.
+
+Tolerance, element by element: |dE - ref| <= K_ULP 2^-24 mag + DA cmag, with mag and cmag from
+oracle.backward.grad_E_columns(with_scale=True): mag sums the absolute sizes of the terms that
+make up the element, cmag its change per unit error of the moments A, B behind the per-pair
+coefficients.  This is the forward error bound of a floating-point sum.  Each term is
+evaluated in FP32 from FP32 standardised data (rounding of w = c u and of the FP32 pair
+coefficients, exp2 and rcp approximations good to 1 ulp): K_ULP = 16 units.  The moments come
+from the forward pass, whose FP32 sums leave them accurate to DA = 1e-7 (the bound the forward
+tests use).  The sum for dL/dx_i(t) is ill-conditioned by construction (each pair term follows
+Hr_ij - Hx_i, a small difference): on the m = 1000 Laplace workload mag is ~500 times |dE|.
+The partner sums run in FP64 on the GPU, so rounding does not accumulate with m.  Any dropped
+or mis-signed term moves dE by far more than the bound (>= 1e-1 of max|dE|).
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import backward as OB
+from oracle import varlingam as O
+
+pytestmark = pytest.mark.gpu
+
+K_ULP = 16
+UNIT = 2.0 ** -24
+DA = 1e-7
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2409_05500_amd import api as _api
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return _api
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return torch.device("cuda:0")
+
+
+def _dev(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _residuals(m, n, seed):
+    rng = np.random.default_rng(seed)
+    mix = np.eye(m) + 0.3 * np.tril(rng.normal(size=(m, m)), -1)
+    return (rng.laplace(size=(n, m)) @ mix.T + rng.normal(0, 3, m)).astype(np.float32)
+
+
+def _check(dE, E32, G, ref=None, cols=None, rel_max=None):
+    """dE (n x len(cols)) against the reference within K_ULP units of the sum's magnitude;
+    with rel_max, also max|err| <= rel_max max|ref|."""
+    E64 = E32.astype(np.float64)
+    cols = list(range(E64.shape[1])) if cols is None else cols
+    col_ref, mag, cmag = OB.grad_E_columns(E64, G, cols, with_scale=True)
+    ref = col_ref if ref is None else ref[:, cols]
+    err = np.abs(dE.astype(np.float64) - ref)
+    ratio = float((err / (K_ULP * UNIT * mag + DA * cmag)).max())
+    rel = float(err.max() / np.abs(ref).max())
+    print(f"  max err / bound {ratio:.3f}; max err / max|dE| {rel:.2e}", flush=True)
+    assert ratio <= 1.0
+    if rel_max is not None:
+        assert rel <= rel_max
+
+
+@pytest.mark.parametrize("m,n", [(2, 37), (3, 17), (4, 512), (6, 700), (13, 1537), (33, 2100),
+                                 (64, 1025)])
+@pytest.mark.parametrize("prec", ["mixed", "fp32"])
+def test_backward_matches_autograd_reference(api, dev, m, n, prec):
+    print(f"backward m={m} n={n} prec={prec}", flush=True)
+    E32 = _residuals(m, n, 7 * m + n)
+    G = np.random.default_rng(m + n).normal(size=(m, m))
+    dE = api.pairwise_stats_backward(_dev(E32, dev), _dev(G, dev), prec).cpu().numpy()
+    _check(dE, E32, G, ref=OB.grad_E(E32.astype(np.float64), G).numpy())
+
+
+def test_backward_workload_residuals(api, dev):
+    """Residuals of the VAR fit of the small benchmark-law instance (uniform noise, m = 10)."""
+    inst = synth.make_instance(synth.SMALL, 3)
+    _, _, E = O.fit_var(inst.X_parity, 1)
+    E32 = E.astype(np.float32)
+    G = np.random.default_rng(5).normal(size=(10, 10))
+    dE = api.pairwise_stats_backward(_dev(E32, dev), _dev(G, dev)).cpu().numpy()
+    _check(dE, E32, G, ref=OB.grad_E(E32.astype(np.float64), G).numpy())
+
+
+def test_backward_full_size_sampled_columns(api, dev):
+    """m = 1000, n = 50000 (Laplace law): sampled columns from the column-wise reference, plus
+    the invariants of the whole gradient."""
+    wl = synth.LARGE
+    print(f"backward full size {wl.name}", flush=True)
+    inst = synth.make_instance(wl, 0)
+    _, _, E = O.fit_var(inst.X_parity, wl.p)
+    E32 = E.astype(np.float32)
+    m = wl.m
+    G = np.random.default_rng(11).normal(size=(m, m))
+    Ed = _dev(E32, dev)
+    dE = api.pairwise_stats_backward(Ed, _dev(G, dev)).cpu().numpy().astype(np.float64)
+    assert np.all(np.isfinite(dE))
+    scale = np.abs(dE).max()
+    E64 = E32.astype(np.float64)
+    # The worst-case bound is loose here (mag ~ 500 |dE|, and the rho chain's n-term sums enter
+    # mag in full).  Independent roundings add in quadrature instead: ~sqrt(m) 2^-22 times the
+    # typical term, 1e-5 of max|dE| (a CPU emulation of this arithmetic with exact moments:
+    # 7.8e-6).  2e-4 is a 5x margin over what the GPU gives (3.8e-5) and fails on a lost
+    # sample chunk of the rho chain (~5e-3 of max|dE|).
+    for i in (0, 517, m - 1):                      # first, interior, ragged last block
+        print(f"  column {i}", flush=True)
+        _check(dE[:, [i]], E32, G, cols=[i], rel_max=2e-4)
+    # shift invariance (column sums 0) and scale invariance (<dE_i, e_i - mean> = 0)
+    n = E64.shape[0]
+    assert np.abs(dE.sum(0)).max() <= 1e-5 * scale * np.sqrt(n)
+    Ec = E64 - E64.mean(0)
+    proj = np.abs((dE * Ec).sum(0)) / np.sqrt((Ec * Ec).sum(0))
+    assert proj.max() <= 1e-5 * scale * np.sqrt(n)
+    # a symmetric cotangent: G - G^T is exactly zero, so is every coefficient
+    Gs = G + G.T
+    assert torch.count_nonzero(api.pairwise_stats_backward(Ed, _dev(Gs, dev))).item() == 0
+
+
+def test_backward_deterministic(api, dev):
+    E = _dev(_residuals(37, 3000, 1), dev)
+    G = _dev(np.random.default_rng(2).normal(size=(37, 37)), dev)
+    a = api.pairwise_stats_backward(E, G)
+    b = api.pairwise_stats_backward(E, G)
+    assert torch.equal(a, b)
+
+
+def test_autograd_function(api, dev):
+    m, n = 9, 900
+    E32 = _residuals(m, n, 4)
+    G = _dev(np.random.default_rng(3).normal(size=(m, m)), dev)
+    E = _dev(E32, dev).requires_grad_(True)
+    S = api.pairwise_score(E)
+    S0 = api.pairwise_stats(E.detach())[2]
+    assert torch.equal(S, S0)
+    (S * G).sum().backward()
+    assert torch.equal(E.grad, api.pairwise_stats_backward(E.detach(), G))
+
+
+def test_backward_strided_input_output(api, dev):
+    """Leading dimensions larger than m on both sides (the C ABI's lde / ldde)."""
+    from paper_2409_05500_amd._lib import lib
+    m, n = 11, 800
+    E32 = _residuals(m, n, 9)
+    G = np.random.default_rng(9).normal(size=(m, m))
+    big = torch.zeros((n, m + 5), dtype=torch.float32, device=dev)
+    big[:, :m] = _dev(E32, dev)
+    out = torch.full((n, m + 3), 7.0, dtype=torch.float32, device=dev)
+    Gd = _dev(G, dev)
+    nb = lib.pairwise_stats_backward_workspace_bytes(n, m, 1)
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    st = torch.zeros(1, dtype=torch.int32, device=dev)
+    rc = lib.pairwise_stats_backward(big.data_ptr(), n, m, m + 5, 1, Gd.data_ptr(),
+                                     out.data_ptr(), m + 3, ws.data_ptr(), nb, st.data_ptr(),
+                                     torch.cuda.current_stream().cuda_stream)
+    assert rc == 0
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    o = out.cpu().numpy()
+    assert np.all(o[:, m:] == 7.0)                 # padding columns untouched
+    _check(o[:, :m], E32, G, ref=OB.grad_E(E32.astype(np.float64), G).numpy())
+
+
+def test_backward_zero_variance_raises(api, dev):
+    from paper_2409_05500_amd._lib import VarLiNGAMError
+    E32 = _residuals(5, 400, 2)
+    E32[:, 3] = 1.5
+    with pytest.raises(VarLiNGAMError):
+        api.pairwise_stats_backward(_dev(E32, dev), _dev(np.ones((5, 5)), dev))

@@ -53,3 +53,29 @@ def test_gradient_invariants():
     # a symmetric cotangent sees only S + S^T = 0
     gs = OB.grad_E(E, G + G.T).numpy()
     assert np.max(np.abs(gs)) < 1e-12 * scale
+
+
+@pytest.mark.parametrize("m,n,seed", [(5, 300, 5), (9, 1100, 6)])
+def test_column_gradient_matches_autograd(m, n, seed):
+    E = _data(m, n, seed)
+    G = np.random.default_rng(seed + 1).normal(size=(m, m))
+    g = OB.grad_E(E, G).numpy()
+    cols = list(range(m))
+    gc = OB.grad_E_columns(E, G, cols, block=3)     # several partner blocks
+    np.testing.assert_allclose(gc, g[:, cols], rtol=0, atol=1e-11 * np.abs(g).max())
+
+
+def test_column_scale_bounds_the_gradient_and_ignores_the_sign_of_G():
+    """The magnitudes returned with the columns: mag >= |dL/dE| elementwise (it sums the
+    absolute sizes of the same terms), and both are unchanged by the sign of G (they see only
+    |G - G^T|)."""
+    m, n = 6, 400
+    E = _data(m, n, 8)
+    G = np.random.default_rng(9).normal(size=(m, m))
+    g, sc, cs = OB.grad_E_columns(E, G, list(range(m)), with_scale=True)
+    assert np.all(sc >= np.abs(g) * (1 - 1e-12))
+    g2, sc2, cs2 = OB.grad_E_columns(E, -G, list(range(m)), with_scale=True)
+    np.testing.assert_allclose(g2, -g, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(sc2, sc, rtol=1e-12)
+    np.testing.assert_allclose(cs2, cs, rtol=1e-12)
+    assert np.all(cs > 0)
