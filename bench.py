@@ -35,6 +35,7 @@ TRANS_PER_EVAL = 3
 MEASURED_TRAFFIC = {}
 STAGES = ("var_gram", "var_solve", "var_residual", "var_refine", "pairwise_cov",
           "pairwise_prep", "pairwise_moments", "pairwise_combine", "order", "estimate_b")
+BATCH_STAGES = ("batch_var", "batch_pairwise", "batch_moments", "batch_order_b")
 
 
 def measured_traffic():
@@ -67,6 +68,59 @@ def time_steps(fitter, X, steps, torch):
     return (time.perf_counter() - t0) / steps
 
 
+def bench_batched(api, torch, steps: int, seed: int):
+    """The batched workload: 256 problems, m in [20, 200], n in [500, 8000], p = 1, uniform or
+    Laplace shocks.  Times one batched fit (one launch per stage for all problems, after the
+    chunk-length autotuner) against fitting the problems one after another through the
+    single-problem path (preallocated Fitters, no host synchronisation in between)."""
+    import synth
+    insts = synth.make_batch(seed)
+    shapes = [i.X32.shape for i in insts]
+    evals = sum(m * (m - 1) * (n - 1) for n, m in shapes)
+    dev = torch.device("cuda:0")
+    out = {"workload": f"{len(insts)} problems, m in [20, 200], n in [500, 8000], p=1",
+           "problems": len(insts), "sample_evals": evals}
+    for prec in ("mixed", "fp32"):
+        bf = api.BatchFitter(shapes, 1, prec, dev)
+        bf.load([i.X32 for i in insts])
+        out[f"chunk_len_{prec}"] = bf.autotune()
+        for _ in range(2):
+            bf.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            bf.run()
+        torch.cuda.synchronize()
+        out[f"batched_ms_{prec}"] = (time.perf_counter() - t0) / steps * 1e3
+        if prec == "mixed":
+            from paper_2409_05500_amd import _lib
+            _lib.profile_enable("*")
+            bf.run()
+            torch.cuda.synchronize()
+            out["batched_stage_ms_mixed"] = {st: round(_lib.profile_read(st)[0], 4)
+                                             for st in BATCH_STAGES}
+            _lib.profile_enable(None)
+        if any(bf.check()):
+            out[f"batched_status_{prec}"] = bf.check()
+        del bf
+        Xs = [torch.from_numpy(i.X32).to(dev) for i in insts]
+        fitters = [api.Fitter(n, m, 1, prec, dev) for n, m in shapes]
+        for f, X in zip(fitters, Xs):
+            f.run(X)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(max(1, steps // 5)):
+            for f, X in zip(fitters, Xs):
+                f.run(X)
+        torch.cuda.synchronize()
+        out[f"looped_ms_{prec}"] = (time.perf_counter() - t0) / max(1, steps // 5) * 1e3
+        del fitters, Xs
+        torch.cuda.empty_cache()
+    out["batched_sample_evals_per_s_mixed"] = evals / (out["batched_ms_mixed"] / 1e3)
+    out["speedup_batched_mixed_vs_looped_fp32"] = out["looped_ms_fp32"] / out["batched_ms_mixed"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +129,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cols", type=int, default=160)
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched-workload section (256 uneven problems)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a plain copy "
                          "kernel of known traffic, for calibrating hardware byte counters)")
@@ -158,6 +214,8 @@ def main():
         "fit_ms_fp32": fp32_s * 1e3,
         "stage_ms": stage_ms,
     }
+    if not args.no_batch:
+        out["batched"] = bench_batched(api, torch, max(3, args.steps // 2), args.seed)
     if not args.no_cpu_baseline:
         from oracle import varlingam as O  # noqa: F401  (CPU baseline only)
         out["cpu_baseline"] = cpu_baseline(fit.E.cpu().numpy().astype(np.float64), args.cpu_cols)

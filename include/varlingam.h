@@ -156,12 +156,63 @@ int estimate_B(const double* Cov, const double* M, const int32_t* order, int64_t
                void* stream);
 
 /* ------------------------------------------------------------------------------------- */
+/* Batched fit: many independent VarLiNGAM problems of uneven size (for instance rolling     */
+/* windows or many datasets) through the whole path -- VAR fit (Sec. 2.1), pairwise         */
+/* precompute (Sec. 4.2, Eq. 1-2), ordering (Alg. 1, Eq. 3), B0 / B_tau -- with one kernel  */
+/* launch per stage for all problems.                                                      */
+/*                                                                                        */
+/* vl_instance describes one problem; all pointers are device pointers owned by the caller. */
+/*   X, n, m, ldx, p   the series (n x m float32, leading dimension ldx >= m) and VAR lag.   */
+/*   M, intercept, E, lde, S, order, margin, B0, Blag   outputs as in varlingam_fit_var,     */
+/*                     pairwise_stats, approx_order and estimate_B (S and margin may be     */
+/*                     NULL: they are then kept in the workspace only).                    */
+/* Per-problem limits: 2 <= m <= 256, p >= 1, m p <= 256, n - p > m p + 1.                 */
+/* Usage: varlingam_batch_create() plans the batch on the host (the descriptors are copied; */
+/* the device buffers they name must stay valid); varlingam_batch_bind() uploads the plan's */
+/* tables into a workspace of varlingam_batch_workspace_bytes() (256-byte aligned) and      */
+/* waits for the copy; varlingam_fit_batched() then only launches kernels on `stream`, so a */
+/* caller may capture it in a HIP graph and replay it after refilling the X buffers.        */
+/* dev_status has one word per problem (VL_OK or that problem's first data-dependent error); */
+/* an error in one problem does not stop the others.                                        */
+/* varlingam_batch_autotune() times the candidate sample-chunk lengths of the pairwise      */
+/* stage with full fits on the bound data, keeps the fastest (cached per batch shape and    */
+/* precision for the process) and rebinds.                                                  */
+/* Host errors: VL_ERR_SHAPE for a problem outside the limits, VL_ERR_INVALID_ARG for null  */
+/* pointers, a bad precision or a workspace that is not the bound one.                      */
+/* ------------------------------------------------------------------------------------- */
+typedef struct {
+  const float* X;
+  int64_t n, m, ldx;
+  int32_t p, reserved;
+  double* M;
+  double* intercept;
+  float* E;
+  int64_t lde;
+  double* S;
+  int32_t* order;
+  double* margin;
+  double* B0;
+  double* Blag;
+} vl_instance;
+
+typedef struct vl_batch vl_batch;
+
+int varlingam_batch_create(const vl_instance* inst, int count, int prec, vl_batch** out);
+size_t varlingam_batch_workspace_bytes(const vl_batch* batch);
+int varlingam_batch_bind(vl_batch* batch, void* ws, size_t ws_bytes, void* stream);
+int varlingam_fit_batched(const vl_batch* batch, void* ws, int32_t* dev_status, void* stream);
+int varlingam_batch_autotune(vl_batch* batch, void* ws, size_t ws_bytes, int32_t* dev_status,
+                             void* stream);
+int varlingam_batch_chunk_len(const vl_batch* batch);
+void varlingam_batch_destroy(vl_batch* batch);
+
+/* ------------------------------------------------------------------------------------- */
 /* Stage timing (diagnostics).  varlingam_profile_enable(stages) starts recording a HIP    */
 /* event pair, on the caller's stream, around every launch of the named stages ("*" = all; */
 /* a comma-separated list; NULL or "" = off) and clears earlier totals.  Stage names:       */
 /*   var_gram, var_solve, var_residual, var_refine, pairwise_cov, pairwise_prep,            */
 /*   pairwise_moments, pairwise_combine, backward_prep, backward_owner, backward_tail,       */
-/*   order, estimate_b.                                                                     */
+/*   order, estimate_b, batch_var, batch_pairwise, batch_moments, batch_order_b.            */
 /* varlingam_profile_read() waits for the recorded events of one stage and returns the      */
 /* accumulated milliseconds and the number of recorded launches.  Thread-safe.              */
 /* ------------------------------------------------------------------------------------- */

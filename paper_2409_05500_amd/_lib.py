@@ -25,6 +25,14 @@ _i32 = C.c_int
 _sz = C.c_size_t
 
 # name -> (restype, argtypes); the names and argument order are those of include/varlingam.h
+class VlInstance(C.Structure):
+    """Mirror of vl_instance (include/varlingam.h): one problem of a batched fit."""
+    _fields_ = [("X", C.c_void_p), ("n", _i64), ("m", _i64), ("ldx", _i64), ("p", _i32),
+                ("reserved", _i32), ("M", C.c_void_p), ("intercept", C.c_void_p),
+                ("E", C.c_void_p), ("lde", _i64), ("S", C.c_void_p), ("order", C.c_void_p),
+                ("margin", C.c_void_p), ("B0", C.c_void_p), ("Blag", C.c_void_p)]
+
+
 SIGNATURES = {
     "varlingam_status_string": (C.c_char_p, [_i32]),
     "varlingam_fit_var_workspace_bytes": (_sz, [_i64, _i64, _i32, _i32]),
@@ -39,6 +47,14 @@ SIGNATURES = {
     "approx_order": (_i32, [_p, _i64, _p, _p, _p, _sz, _p, _p]),
     "estimate_B_workspace_bytes": (_sz, [_i64, _i32]),
     "estimate_B": (_i32, [_p, _p, _p, _i64, _i32, _p, _p, _p, _sz, _p, _p]),
+    "varlingam_batch_create": (_i32, [C.POINTER(VlInstance), _i32, _i32,
+                                      C.POINTER(C.c_void_p)]),
+    "varlingam_batch_workspace_bytes": (_sz, [_p]),
+    "varlingam_batch_bind": (_i32, [_p, _p, _sz, _p]),
+    "varlingam_fit_batched": (_i32, [_p, _p, _p, _p]),
+    "varlingam_batch_autotune": (_i32, [_p, _p, _sz, _p, _p]),
+    "varlingam_batch_chunk_len": (_i32, [_p]),
+    "varlingam_batch_destroy": (None, [_p]),
     "varlingam_profile_enable": (None, [C.c_char_p]),
     "varlingam_profile_read": (_i32, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(_i64)]),
 }

@@ -3,6 +3,7 @@ tensors, pass raw device pointers and the current stream, and check the status c
 All arithmetic happens in the HIP library."""
 from __future__ import annotations
 
+import ctypes as C
 from dataclasses import dataclass
 
 import torch
@@ -256,3 +257,98 @@ class Fitter:
     def check(self) -> None:
         for code, name in zip(self.status.cpu().tolist(), self.STAGES):
             check(int(code), name)
+
+
+@dataclass
+class BatchResult:
+    M: torch.Tensor
+    intercept: torch.Tensor
+    E: torch.Tensor
+    S: torch.Tensor
+    order: torch.Tensor
+    margin: torch.Tensor
+    B0: torch.Tensor
+    B_lags: torch.Tensor
+
+
+class BatchFitter:
+    """Many problems of uneven (n, m) through the whole path with one kernel launch per stage
+    (varlingam_fit_batched).  Inputs and outputs are preallocated per problem; the plan is
+    bound to one workspace once.  load() copies new series in, run() enqueues the fit on the
+    current stream (no allocation, no synchronisation: it may be captured in a graph),
+    check() reads the per-problem status words."""
+
+    def __init__(self, shapes, p: int = 1, prec="mixed", device="cuda:0"):
+        dev = torch.device(device)
+        self.dev, self.p, self.prec = dev, p, _prec(prec)
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.X, self.results = [], []
+        desc = (_lib.VlInstance * len(shapes))()
+        for b, (n, m) in enumerate(shapes):
+            X = torch.zeros((n, m), dtype=torch.float32, device=dev)
+            r = BatchResult(M=torch.empty((p, m, m), **f64), intercept=torch.empty(m, **f64),
+                            E=torch.empty((n - p, m), dtype=torch.float32, device=dev),
+                            S=torch.empty((m, m), **f64),
+                            order=torch.empty(m, dtype=torch.int32, device=dev),
+                            margin=torch.empty(m, **f64), B0=torch.empty((m, m), **f64),
+                            B_lags=torch.empty((p, m, m), **f64))
+            self.X.append(X)
+            self.results.append(r)
+            d = desc[b]
+            d.X, d.n, d.m, d.ldx, d.p = X.data_ptr(), n, m, m, p
+            d.M, d.intercept, d.E, d.lde = r.M.data_ptr(), r.intercept.data_ptr(), \
+                r.E.data_ptr(), m
+            d.S, d.order, d.margin = r.S.data_ptr(), r.order.data_ptr(), r.margin.data_ptr()
+            d.B0, d.Blag = r.B0.data_ptr(), r.B_lags.data_ptr()
+        handle = C.c_void_p()
+        check(lib.varlingam_batch_create(desc, len(shapes), self.prec, C.byref(handle)),
+              "varlingam_batch_create")
+        self._h = handle
+        self.ws = _workspace(lib.varlingam_batch_workspace_bytes(handle), dev)
+        self.status = torch.zeros(len(shapes), dtype=torch.int32, device=dev)
+        check(lib.varlingam_batch_bind(handle, self.ws.data_ptr(), self.ws.numel(),
+                                       _stream_ptr(dev)), "varlingam_batch_bind")
+
+    def __len__(self):
+        return len(self.X)
+
+    def load(self, Xs) -> None:
+        for dst, src in zip(self.X, Xs):
+            dst.copy_(torch.as_tensor(src, dtype=torch.float32), non_blocking=False)
+
+    def run(self) -> None:
+        check(lib.varlingam_fit_batched(self._h, self.ws.data_ptr(), self.status.data_ptr(),
+                                        _stream_ptr(self.dev)), "varlingam_fit_batched")
+
+    def autotune(self) -> int:
+        """Time the pairwise chunk-length candidates on the loaded data; keep the fastest."""
+        check(lib.varlingam_batch_autotune(self._h, self.ws.data_ptr(), self.ws.numel(),
+                                           self.status.data_ptr(), _stream_ptr(self.dev)),
+              "varlingam_batch_autotune")
+        return lib.varlingam_batch_chunk_len(self._h)
+
+    @property
+    def chunk_len(self) -> int:
+        return lib.varlingam_batch_chunk_len(self._h)
+
+    def check(self) -> list:
+        """Per-problem status codes (0 = ok); synchronises."""
+        return [int(v) for v in self.status.cpu().tolist()]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib.varlingam_batch_destroy(h)
+            self._h = None
+
+
+def fit_batched(Xs, p: int = 1, prec="mixed", autotune: bool = False):
+    """Fit every series in Xs (a list of n_b x m_b arrays or tensors) in one batched pass.
+    Returns (results, status codes)."""
+    dev = torch.device("cuda:0")
+    bf = BatchFitter([tuple(x.shape) for x in Xs], p, prec, dev)
+    bf.load(Xs)
+    if autotune:
+        bf.autotune()
+    bf.run()
+    return bf.results, bf.check()

@@ -1,0 +1,701 @@
+// Batched fit of many small VarLiNGAM problems of uneven size: the whole path (VAR fit of
+// Sec. 2.1, pairwise precompute of Sec. 4.2 with Eq. 1-2, ordering of Alg. 1 with Eq. 3, and
+// B0 / B_tau) with one kernel launch per stage for all problems.
+//
+// Throughput stages (column means, Gram matrices, residual GEMM, standardisation, Hx, pair
+// coefficients, pairwise moments, combine) launch the sum of the problems' blocks; a
+// block -> problem table and each problem's first block turn a block index into (problem,
+// local block), and the block runs the same body as the single-problem kernel.  Latency-bound
+// stages (Cholesky solve of the VAR normal equations; ordering followed by the B estimation)
+// run one 256-thread workgroup per problem, so a batch of a few hundred problems fills the
+// chip in one launch instead of a few hundred serial ones.
+//
+// The Gram tiles here run over all samples in one block (no split-K; the batch supplies the
+// parallelism), so results differ from the single-problem path by summation order only.
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "gram_dev.hpp"
+#include "linalg_dev.hpp"
+#include "order_dev.hpp"
+#include "pairwise_dev.hpp"
+#include "profile.hpp"
+#include "var_dev.hpp"
+
+namespace vl {
+
+constexpr int kBatchMaxM = 256;      // order body with 4 variables per lane
+constexpr int kBatchMaxDz = 256;
+
+// Per-problem descriptor as the kernels see it (device copy in the workspace).
+struct BInst {
+  const float* X;
+  int64_t n, m, ldx, n_eff, dz, nc;   // nc: columns of the lag map, m (p + 1)
+  int p, fp32;
+  double* M;
+  double* intercept;
+  float* E;
+  int64_t lde;
+  double* S;
+  int32_t* order;
+  double* margin;
+  double* B0;
+  double* Blag;
+  // pairwise plan
+  int nt, nchunk, chunk_len, pad;
+  int64_t m_pad, tiles, n_pad, items;
+  // workspace
+  int64_t* colmap;
+  double *mu, *G, *Coef, *L, *Tmp, *chol;
+  float* CoefF;
+  double *emu, *cov, *momx, *Hx, *Hr;
+  float* Xs;
+  float2* coef;
+  float *partU, *partB;
+  double *P, *Lc, *Id, *Linv, *bchol;
+};
+
+enum BMap { kMapColVar, kMapColE, kMapGramVar, kMapGramCov, kMapResid, kMapStd, kMapPrep,
+            kMapMom, kMapComb, kNumMaps };
+
+struct BTables {
+  const BInst* inst;
+  const int32_t* bmap[kNumMaps];   // block -> problem
+  const int64_t* first[kNumMaps];  // problem -> its first block
+};
+
+// Wave-uniform copies in scalar registers (the descriptor fields are the same for a block).
+__device__ inline int64_t uni(int64_t v) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)(uint64_t)v);
+  const int hi = __builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+template <class T>
+__device__ inline T* uni(T* p) {
+  return reinterpret_cast<T*>(uni(reinterpret_cast<int64_t>(p)));
+}
+
+__device__ inline int bat_locate(const BTables& T, int map, int64_t blk, int64_t& local) {
+  const int b = T.bmap[map][blk];
+  local = blk - T.first[map][b];
+  return b;
+}
+
+// ------------------------------------------------------------------------------------------
+__global__ void bat_reset_kernel(int32_t* st, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) st[i] = VL_OK;
+}
+
+// Column means over all n_eff rows, 64 columns per block; which = 0: the lag map of X (VAR),
+// 1: the residuals E.  Raises VL_ERR_NONFINITE.
+__global__ __launch_bounds__(256) void bat_colmeans_kernel(BTables T, int which, int32_t* st0) {
+  int64_t lb;
+  const int b = bat_locate(T, which ? kMapColE : kMapColVar, blockIdx.x, lb);
+  const BInst& d = T.inst[b];
+  __shared__ double red[4][64];
+  const int cc = threadIdx.x & 63, rg = threadIdx.x >> 6;
+  const float* A = which ? d.E : d.X;
+  const int64_t lda = which ? d.lde : d.ldx;
+  const int64_t ncol = which ? d.m : d.nc;
+  const int64_t c = lb * 64 + cc;
+  double s = 0.0;
+  bool bad = false;
+  if (c < ncol) {
+    const float* p = A + (which ? c : d.colmap[c]);
+    const int64_t n_eff = d.n_eff;
+    int64_t t = rg;
+    for (; t + 28 < n_eff; t += 32) {                 // eight loads in flight per thread
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = p[(t + 4 * u) * lda];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        bad |= !isfinite(v[u]);
+        s += (double)v[u];
+      }
+    }
+    for (; t < n_eff; t += 4) {
+      const float v = p[t * lda];
+      bad |= !isfinite(v);
+      s += (double)v;
+    }
+  }
+  if (bad) raise_status(st0 + b, VL_ERR_NONFINITE);
+  red[rg][cc] = s;
+  __syncthreads();
+  if (rg == 0 && c < ncol)
+    (which ? d.emu : d.mu)[c] =
+        (((red[0][cc] + red[1][cc]) + red[2][cc]) + red[3][cc]) / (double)d.n_eff;
+}
+
+// Centred Gram tiles over all samples.  which = 0: the lower-triangle tiles of G = Zc^T Zc
+// (dz x dz; the Cholesky reads nothing above the diagonal blocks) then R = Zc^T Yc (dz x m,
+// into Coef); which = 1: the lower-triangle tiles of Cov = Ec^T Ec / n_eff, each off-diagonal
+// tile also written transposed (Cov exactly symmetric).  kFp64: FP64 MFMA on the widened data;
+// otherwise FP32 MFMA.
+// k-th tile (row-major) of the lower triangle of a t x t tile grid: (ti, tj), tj <= ti
+__device__ inline void lower_tile(int64_t k, int64_t& ti, int64_t& tj) {
+  ti = (int64_t)((sqrt(8.0 * (double)k + 1.0) - 1.0) * 0.5);
+  while (ti * (ti + 1) / 2 > k) --ti;
+  while ((ti + 1) * (ti + 2) / 2 <= k) ++ti;
+  tj = k - ti * (ti + 1) / 2;
+}
+
+template <bool kFp64>
+__device__ inline void bat_gram_tile(const float* A, int64_t lda, const int64_t* mapA,
+                                     const double* muA, int64_t M, const float* B, int64_t ldb,
+                                     const int64_t* mapB, const double* muB, int64_t N,
+                                     int64_t i0, int64_t j0, int64_t K, double* C, int64_t ldc,
+                                     double scale, bool mirror) {
+  if (kFp64)
+    gram_tile_f64(A, lda, mapA, muA, M, B, ldb, mapB, muB, N, i0, j0, 0, K, C, ldc, scale,
+                  mirror);
+  else  // FP32 partial sums over 128-sample blocks added in FP64 (the single-problem path gets
+        // the same from its FP64 combination of split-K partials)
+    gram_tile_f32<4>(A, lda, mapA, muA, M, B, ldb, mapB, muB, N, i0, j0, 0, K, C, ldc, scale,
+                     mirror);
+}
+
+template <bool kFp64>
+__global__ __launch_bounds__(256) void bat_gram_kernel(BTables T, int which) {
+  int64_t lb;
+  const int b = bat_locate(T, which ? kMapGramCov : kMapGramVar, blockIdx.x, lb);
+  const BInst& d = T.inst[b];
+  if (which == 0) {
+    const int64_t tz = ceil_div(d.dz, kGT), tm = ceil_div(d.m, kGT);
+    const int64_t* mapZ = d.colmap + d.m;
+    const double* muZ = d.mu + d.m;
+    const int64_t tri = tz * (tz + 1) / 2;
+    if (lb < tri) {
+      int64_t ti, tj;
+      lower_tile(lb, ti, tj);
+      bat_gram_tile<kFp64>(d.X, d.ldx, mapZ, muZ, d.dz, d.X, d.ldx, mapZ, muZ, d.dz, ti * kGT,
+                           tj * kGT, d.n_eff, d.G, d.dz, 1.0, false);
+    } else {
+      const int64_t l2 = lb - tri;
+      bat_gram_tile<kFp64>(d.X, d.ldx, mapZ, muZ, d.dz, d.X, d.ldx, d.colmap, d.mu, d.m,
+                           (l2 / tm) * kGT, (l2 % tm) * kGT, d.n_eff, d.Coef, d.m, 1.0, false);
+    }
+  } else {
+    int64_t ti, tj;
+    lower_tile(lb, ti, tj);
+    bat_gram_tile<kFp64>(d.E, d.lde, nullptr, d.emu, d.m, d.E, d.lde, nullptr, d.emu, d.m,
+                         ti * kGT, tj * kGT, d.n_eff, d.cov, d.m, 1.0 / (double)d.n_eff,
+                         ti != tj);
+  }
+}
+
+// One workgroup per problem: Cholesky of G, Coef = G^{-1} R, lag matrices, intercept, and the
+// FP32 copy of Coef for the FP32 residual GEMM.
+__global__ __launch_bounds__(256) void bat_var_solve_kernel(const BInst* __restrict__ I,
+                                                            int32_t* st0) {
+  const BInst& d = I[blockIdx.x];
+  int32_t* st = st0 + blockIdx.x;
+  const int64_t m = d.m, dz = d.dz;
+  wg_potrf_lower(d.G, dz, dz, d.L, dz, d.chol, st);
+  wg_trsm_lower(d.L, dz, dz, d.chol, false, d.Coef, m, m, d.Tmp, m);
+  wg_trsm_lower(d.L, dz, dz, d.chol, true, d.Tmp, m, m, d.Coef, m);
+  const int tid = threadIdx.x;
+  for (int64_t e = tid; e < (int64_t)d.p * m * m; e += 256) {
+    const int64_t tau1 = e / (m * m), rem = e % (m * m), i = rem / m, k = rem % m;
+    d.M[e] = d.Coef[(tau1 * m + k) * m + i];
+  }
+  for (int64_t i = tid; i < m; i += 256) {
+    double s = 0.0;
+    for (int64_t k = 0; k < dz; ++k) s += d.Coef[k * m + i] * d.mu[m + k];
+    d.intercept[i] = d.mu[i] - s;
+  }
+  if (d.fp32)
+    for (int64_t e = tid; e < dz * m; e += 256) d.CoefF[e] = (float)d.Coef[e];
+}
+
+template <bool kFp64>
+__global__ __launch_bounds__(256) void bat_var_residual_kernel(BTables T) {
+  int64_t lb;
+  const int b = bat_locate(T, kMapResid, blockIdx.x, lb);
+  const BInst& d = T.inst[b];
+  const int64_t tm = ceil_div(d.m, 64);
+  const int64_t t0 = (lb / tm) * 64, j0 = (lb % tm) * 64;
+  if (kFp64)
+    var_residual_tile_f64<float>(d.X, d.ldx, d.colmap, d.mu, d.m, d.p, d.n_eff, d.Coef, d.E,
+                                 d.lde, t0, j0);
+  else
+    var_residual_tile_f32(d.X, d.ldx, d.colmap, d.mu, d.m, d.p, d.n_eff, d.CoefF, d.E, d.lde, t0,
+                          j0);
+}
+
+__global__ __launch_bounds__(256) void bat_standardize_kernel(BTables T, int32_t* st0) {
+  int64_t lb;
+  const int b = bat_locate(T, kMapStd, blockIdx.x, lb);
+  const BInst& d = T.inst[b];
+  const int64_t gx = ceil_div(d.n_pad, 64);
+  standardize_tile(d.E, d.lde, d.n_eff, d.m, d.emu, d.cov, d.Xs, d.n_pad, d.m_pad, st0 + b,
+                   (lb % gx) * 64, (lb / gx) * 64);
+}
+
+// Blocks [0, m): Hx of variable lb; then the pair coefficients, 256 entries per block.
+__global__ __launch_bounds__(256) void bat_prep_kernel(BTables T, int32_t* st0) {
+  int64_t lb;
+  const int b = bat_locate(T, kMapPrep, blockIdx.x, lb);
+  const BInst& d = T.inst[b];
+  if (lb < d.m)
+    hx_block(d.Xs, d.n_pad, d.n_eff, d.Hx, d.momx, lb);
+  else
+    pair_coef_elem(d.cov, d.m, d.m_pad, d.coef, st0 + b, (lb - d.m) * 256 + threadIdx.x);
+}
+
+// The pairwise-moment items of all problems; the grid (a multiple of 8 blocks) is remapped so
+// that each XCD takes a contiguous range of blocks, i.e. mostly whole problems per L2.
+__global__ __launch_bounds__(256) void bat_moments_kernel(
+    BTables T, int64_t total) {
+  const int64_t nb = gridDim.x;
+  const int64_t g = (int64_t)(blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
+  if (g >= total) return;
+  int64_t lb;
+  const int b = bat_locate(T, kMapMom, g, lb);
+  const BInst& d = T.inst[b];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t item = uni(lb) * 4 + wave;
+  if (item >= uni(d.items)) return;
+  pairwise_moments_item(uni(d.Xs), uni(d.n_pad), uni(d.coef), uni(d.m_pad), uni(d.m),
+                        (int)uni(d.nt), uni(d.tiles), (int)uni(d.chunk_len), item, uni(d.partU),
+                        uni(d.partB));
+}
+
+// Per unordered pair (one thread at i <= j): Hr of both orders, then S[i][j] and S[j][i] with
+// the single-problem formula.
+__global__ __launch_bounds__(256) void bat_combine_kernel(BTables T) {
+  int64_t lb;
+  const int b = bat_locate(T, kMapComb, blockIdx.x, lb);
+  const BInst& d = T.inst[b];
+  const int64_t m = d.m, e = lb * 256 + threadIdx.x;
+  if (e >= m * m) return;
+  const int64_t i = e / m, j = e % m;
+  if (i > j) return;
+  combine_hr_elem(d.partU, d.partB, d.nchunk, m, d.n_eff, d.Hr, nullptr, e);
+  if (i == j) {
+    d.S[e] = 0.0;
+    return;
+  }
+  const int64_t e2 = j * m + i;
+  combine_hr_elem(d.partU, d.partB, d.nchunk, m, d.n_eff, d.Hr, nullptr, e2);
+  d.S[e] = (d.Hx[j] + d.Hr[e]) - (d.Hx[i] + d.Hr[e2]);
+  d.S[e2] = (d.Hx[i] + d.Hr[e2]) - (d.Hx[j] + d.Hr[e]);
+}
+
+// One workgroup per problem: the ordering, then B0 from the LDL^T of the order-permuted
+// covariance (B0_KK = I - L^{-1}) and B_tau = (I - B0) M_tau.
+__global__ __launch_bounds__(256) void bat_order_b_kernel(const BInst* __restrict__ I,
+                                                          int32_t* st0) {
+  const BInst& d = I[blockIdx.x];
+  int32_t* st = st0 + blockIdx.x;
+  const int64_t m = d.m;
+  const int tid = threadIdx.x;
+  order_wave_block<kBatchMaxM / 64, 256>(d.S, m, d.order, d.margin, st);
+  __shared__ int seen[kBatchMaxM];
+  for (int64_t a = tid; a < m; a += 256) seen[a] = 0;
+  __syncthreads();
+  const int32_t* K = d.order;
+  for (int64_t e = tid; e < m * m; e += 256) {
+    const int64_t a = e / m, c = e % m;
+    const int32_t ka = K[a], kc = K[c];
+    if (ka < 0 || ka >= m || kc < 0 || kc >= m) {
+      raise_status(st, VL_ERR_INVALID_ARG);
+      d.P[e] = a == c ? 1.0 : 0.0;
+      continue;
+    }
+    d.P[e] = d.cov[(int64_t)ka * m + kc];
+    if (c == 0) atomicAdd(&seen[ka], 1);
+  }
+  __syncthreads();
+  for (int64_t a = tid; a < m; a += 256)
+    if (seen[a] != 1) raise_status(st, VL_ERR_INVALID_ARG);
+  wg_potrf_lower(d.P, m, m, d.Lc, m, d.bchol, st);
+  for (int64_t e = tid; e < m * m; e += 256) d.Id[e] = (e / m == e % m) ? 1.0 : 0.0;
+  __syncthreads();
+  wg_trsm_lower(d.Lc, m, m, d.bchol, false, d.Id, m, m, d.Linv, m);
+  for (int64_t e = tid; e < m * m; e += 256) {
+    const int64_t a = e / m, c = e % m;
+    const int32_t ka = K[a], kc = K[c];
+    if (ka < 0 || ka >= m || kc < 0 || kc >= m) continue;
+    d.B0[(int64_t)ka * m + kc] = c < a ? -d.Lc[a * m + a] * d.Linv[a * m + c] : 0.0;
+  }
+  __syncthreads();
+  for (int tau = 0; tau < d.p; ++tau) {
+    const double* Mt = d.M + (int64_t)tau * m * m;
+    double* Bt = d.Blag + (int64_t)tau * m * m;
+    for (int64_t e = tid; e < m * m; e += 256) Bt[e] = Mt[e];
+    __syncthreads();
+    wg_gemm_f64(m, m, m, -1.0, d.B0, m, false, Mt, m, false, 1.0, Bt, m, false);
+  }
+}
+
+}  // namespace vl
+
+// ==========================================================================================
+// Host side: plan, workspace layout, tables, launches, autotuner.
+// ==========================================================================================
+using namespace vl;
+
+namespace {
+
+constexpr int kChunkCandidates[] = {512, 1024, 2048, 4096, 8192};
+
+struct InstLayout {
+  size_t off = 0;                 // byte offset of this problem's slice in the workspace
+  size_t cmap_off = 0;            // byte offset of its lag column map (in the table region)
+  int nt = 0, nchunk = 0, chunk_len = 0;
+  int64_t m_pad = 0, tiles = 0, n_pad = 0, items = 0;
+};
+
+// Carve one problem's slice; base == nullptr measures it.
+size_t carve_inst(const vl_instance& in, const InstLayout& L, char* base, BInst* d) {
+  Carver c(base);
+  const int64_t m = in.m, dz = in.m * in.p, nc = in.m * (in.p + 1);
+  const int64_t n_eff = in.n - in.p;
+  BInst t = {};
+  t.mu = c.take<double>(nc);
+  t.G = c.take<double>(dz * dz);
+  t.Coef = c.take<double>(dz * m);
+  t.L = c.take<double>(dz * dz);
+  t.Tmp = c.take<double>(dz * m);
+  t.chol = c.take<double>(dz + ceil_div(dz, 64) * 64 * 64);
+  t.CoefF = c.take<float>(dz * m);
+  t.emu = c.take<double>(m);
+  t.cov = c.take<double>(m * m);
+  t.momx = c.take<double>(2 * m);
+  t.Hx = c.take<double>(m);
+  t.Hr = c.take<double>(m * m);
+  t.S = c.take<double>(m * m);               // used when the caller passes no S
+  t.margin = c.take<double>(m);              // used when the caller passes no margin
+  t.Xs = c.take<float>(L.m_pad * L.n_pad);
+  t.coef = c.take<float2>(L.m_pad * L.m_pad);
+  t.partU = c.take<float>((size_t)L.nchunk * m * m);
+  t.partB = c.take<float>((size_t)L.nchunk * m * m);
+  t.P = c.take<double>(m * m);
+  t.Lc = c.take<double>(m * m);
+  t.Id = c.take<double>(m * m);
+  t.Linv = c.take<double>(m * m);
+  t.bchol = c.take<double>(m + ceil_div(m, 64) * 64 * 64);
+  (void)n_eff;
+  if (d) *d = t;
+  return c.used;
+}
+
+InstLayout layout_for(const vl_instance& in, int chunk) {
+  InstLayout L;
+  const int64_t m = in.m, n_eff = in.n - in.p;
+  L.nt = (int)ceil_div(m, 4);
+  L.m_pad = (int64_t)L.nt * 4;
+  L.tiles = (int64_t)L.nt * (L.nt + 1) / 2;
+  const int64_t cl = std::min<int64_t>(chunk, round_up(n_eff, 256));
+  L.chunk_len = (int)cl;
+  L.nchunk = (int)ceil_div(n_eff, cl);
+  L.n_pad = (int64_t)L.nchunk * cl;
+  L.items = L.tiles * L.nchunk;
+  return L;
+}
+
+int64_t blocks_for(int map, const vl_instance& in, const InstLayout& L) {
+  const int64_t m = in.m, dz = in.m * in.p, nc = in.m * (in.p + 1), n_eff = in.n - in.p;
+  switch (map) {
+    case kMapColVar: return ceil_div(nc, 64);
+    case kMapColE: return ceil_div(m, 64);
+    case kMapGramVar: return ceil_div(dz, 64) * (ceil_div(dz, 64) + 1) / 2 +
+                             ceil_div(dz, 64) * ceil_div(m, 64);
+    case kMapGramCov: return ceil_div(m, 64) * (ceil_div(m, 64) + 1) / 2;
+    case kMapResid: return ceil_div(m, 64) * ceil_div(n_eff, 64);
+    case kMapStd: return ceil_div(L.n_pad, 64) * ceil_div(L.m_pad, 64);
+    case kMapPrep: return m + ceil_div(L.m_pad * L.m_pad, 256);
+    case kMapMom: return ceil_div(L.items, 4);
+    case kMapComb: return ceil_div(m * m, 256);
+  }
+  return 0;
+}
+
+}  // namespace
+
+struct vl_batch {
+  std::vector<vl_instance> inst;
+  int count = 0;
+  int prec = VL_PREC_MIXED;
+  int chunk = 2048;
+  size_t ws_bytes = 0;       // enough for every chunk candidate
+  // current layout
+  std::vector<InstLayout> lay;
+  int64_t total[kNumMaps] = {};
+  size_t tab_off[kNumMaps * 2] = {};  // byte offsets of the bmap / first arrays
+  size_t slices_off = 0;                // end of the tables and column maps
+  void* bound = nullptr;
+};
+
+namespace {
+
+// Layout for the batch's current chunk length; returns the workspace bytes it needs.
+size_t build_layout(vl_batch* B) {
+  const int n = B->count;
+  B->lay.resize(n);
+  size_t used = round_up((int64_t)(n * sizeof(BInst)), 256);
+  for (int k = 0; k < kNumMaps; ++k) {
+    int64_t tot = 0;
+    for (int b = 0; b < n; ++b) {
+      if (k == 0) B->lay[b] = layout_for(B->inst[b], B->chunk);
+      tot += blocks_for(k, B->inst[b], B->lay[b]);
+    }
+    B->total[k] = tot;
+    B->tab_off[2 * k] = used;
+    used += round_up((int64_t)((tot + 8) * sizeof(int32_t)), 256);
+    B->tab_off[2 * k + 1] = used;
+    used += round_up((int64_t)(n * sizeof(int64_t)), 256);
+  }
+  for (int b = 0; b < n; ++b) {
+    B->lay[b].cmap_off = used;
+    used += round_up(B->inst[b].m * (B->inst[b].p + 1) * (int64_t)sizeof(int64_t), 256);
+  }
+  B->slices_off = used;
+  for (int b = 0; b < n; ++b) {
+    B->lay[b].off = used;
+    used += carve_inst(B->inst[b], B->lay[b], nullptr, nullptr);
+  }
+  return used;
+}
+
+int upload(vl_batch* B, void* ws, hipStream_t stream) {
+  const int n = B->count;
+  char* base = static_cast<char*>(ws);
+  std::vector<char> host(B->slices_off, 0);
+  BInst* I = reinterpret_cast<BInst*>(host.data());
+  for (int b = 0; b < n; ++b) {
+    const vl_instance& in = B->inst[b];
+    const InstLayout& L = B->lay[b];
+    BInst d;
+    carve_inst(in, L, base + L.off, &d);
+    d.colmap = reinterpret_cast<int64_t*>(base + L.cmap_off);
+    // colmap[tau m + i] = offset of x_i(t - tau) at t = 0 in the lag-embedded view (tau = 0: Y)
+    int64_t* cm = reinterpret_cast<int64_t*>(host.data() + L.cmap_off);
+    for (int64_t c = 0; c < in.m * (in.p + 1); ++c) cm[c] = (in.p - c / in.m) * in.ldx + c % in.m;
+    d.X = in.X;
+    d.n = in.n;
+    d.m = in.m;
+    d.ldx = in.ldx;
+    d.p = in.p;
+    d.n_eff = in.n - in.p;
+    d.dz = in.m * in.p;
+    d.nc = in.m * (in.p + 1);
+    d.fp32 = B->prec == VL_PREC_FP32 ? 1 : 0;
+    d.M = in.M;
+    d.intercept = in.intercept;
+    d.E = in.E;
+    d.lde = in.lde;
+    if (in.S) d.S = in.S;
+    d.order = in.order;
+    if (in.margin) d.margin = in.margin;
+    d.B0 = in.B0;
+    d.Blag = in.Blag;
+    d.nt = L.nt;
+    d.nchunk = L.nchunk;
+    d.chunk_len = L.chunk_len;
+    d.m_pad = L.m_pad;
+    d.tiles = L.tiles;
+    d.n_pad = L.n_pad;
+    d.items = L.items;
+    I[b] = d;
+  }
+  for (int k = 0; k < kNumMaps; ++k) {
+    int32_t* bm = reinterpret_cast<int32_t*>(host.data() + B->tab_off[2 * k]);
+    int64_t* first = reinterpret_cast<int64_t*>(host.data() + B->tab_off[2 * k + 1]);
+    int64_t pos = 0;
+    for (int b = 0; b < n; ++b) {
+      first[b] = pos;
+      const int64_t nb = blocks_for(k, B->inst[b], B->lay[b]);
+      for (int64_t q = 0; q < nb; ++q) bm[pos + q] = b;
+      pos += nb;
+    }
+    for (int64_t q = pos; q < B->total[k] + 8; ++q) bm[q] = n - 1;   // padding blocks
+  }
+  if (hipMemcpyAsync(ws, host.data(), host.size(), hipMemcpyHostToDevice, stream) != hipSuccess)
+    return VL_ERR_HIP;
+  if (hipStreamSynchronize(stream) != hipSuccess) return VL_ERR_HIP;
+  B->bound = ws;
+  return VL_OK;
+}
+
+BTables tables(const vl_batch* B, void* ws) {
+  char* base = static_cast<char*>(ws);
+  BTables T;
+  T.inst = reinterpret_cast<const BInst*>(base);
+  for (int k = 0; k < kNumMaps; ++k) {
+    T.bmap[k] = reinterpret_cast<const int32_t*>(base + B->tab_off[2 * k]);
+    T.first[k] = reinterpret_cast<const int64_t*>(base + B->tab_off[2 * k + 1]);
+  }
+  return T;
+}
+
+int launch_fit(const vl_batch* B, void* ws, int32_t* st, hipStream_t s) {
+  const BTables T = tables(B, ws);
+  const BInst* I = T.inst;
+  const int n = B->count;
+  const bool f64 = B->prec != VL_PREC_FP32;
+  bat_reset_kernel<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(st, n);
+  VL_LAUNCH_CHECK();
+  {
+    ProfileScope ps("batch_var", s);
+    bat_colmeans_kernel<<<(unsigned)B->total[kMapColVar], 256, 0, s>>>(T, 0, st);
+    VL_LAUNCH_CHECK();
+    if (f64) bat_gram_kernel<true><<<(unsigned)B->total[kMapGramVar], 256, 0, s>>>(T, 0);
+    else bat_gram_kernel<false><<<(unsigned)B->total[kMapGramVar], 256, 0, s>>>(T, 0);
+    VL_LAUNCH_CHECK();
+    bat_var_solve_kernel<<<(unsigned)n, 256, 0, s>>>(I, st);
+    VL_LAUNCH_CHECK();
+    if (f64) bat_var_residual_kernel<true><<<(unsigned)B->total[kMapResid], 256, 0, s>>>(T);
+    else bat_var_residual_kernel<false><<<(unsigned)B->total[kMapResid], 256, 0, s>>>(T);
+    VL_LAUNCH_CHECK();
+  }
+  {
+    ProfileScope ps("batch_pairwise", s);
+    bat_colmeans_kernel<<<(unsigned)B->total[kMapColE], 256, 0, s>>>(T, 1, st);
+    VL_LAUNCH_CHECK();
+    if (f64) bat_gram_kernel<true><<<(unsigned)B->total[kMapGramCov], 256, 0, s>>>(T, 1);
+    else bat_gram_kernel<false><<<(unsigned)B->total[kMapGramCov], 256, 0, s>>>(T, 1);
+    VL_LAUNCH_CHECK();
+    bat_standardize_kernel<<<(unsigned)B->total[kMapStd], 256, 0, s>>>(T, st);
+    VL_LAUNCH_CHECK();
+    bat_prep_kernel<<<(unsigned)B->total[kMapPrep], 256, 0, s>>>(T, st);
+    VL_LAUNCH_CHECK();
+  }
+  {
+    ProfileScope ps("batch_moments", s);
+    const int64_t tot = B->total[kMapMom];
+    bat_moments_kernel<<<(unsigned)round_up(tot, 8), 256, 0, s>>>(T, tot);
+    VL_LAUNCH_CHECK();
+  }
+  {
+    ProfileScope ps("batch_order_b", s);
+    bat_combine_kernel<<<(unsigned)B->total[kMapComb], 256, 0, s>>>(T);
+    VL_LAUNCH_CHECK();
+    bat_order_b_kernel<<<(unsigned)n, 256, 0, s>>>(I, st);
+    VL_LAUNCH_CHECK();
+  }
+  return VL_OK;
+}
+
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune_cache;
+
+std::string tune_key(const vl_batch* B) {
+  std::vector<std::string> parts;
+  for (const auto& in : B->inst)
+    parts.push_back(std::to_string(in.m) + "x" + std::to_string(in.n - in.p) + "p" +
+                    std::to_string(in.p));
+  std::sort(parts.begin(), parts.end());
+  std::string k = std::to_string(B->prec);
+  for (const auto& p : parts) k += "," + p;
+  return k;
+}
+
+}  // namespace
+
+extern "C" {
+
+int varlingam_batch_create(const vl_instance* inst, int count, int prec, vl_batch** out) {
+  if (!out) return VL_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!inst || count < 1 || count > (1 << 20)) return VL_ERR_INVALID_ARG;
+  if (prec != VL_PREC_FP32 && prec != VL_PREC_MIXED) return VL_ERR_INVALID_ARG;
+  for (int b = 0; b < count; ++b) {
+    const vl_instance& in = inst[b];
+    if (!in.X || !in.M || !in.intercept || !in.E || !in.order || !in.B0 || !in.Blag)
+      return VL_ERR_INVALID_ARG;
+    if (in.m < 2 || in.m > kBatchMaxM || in.p < 1 || in.m * in.p > kBatchMaxDz ||
+        in.n - in.p <= in.m * in.p + 1)
+      return VL_ERR_SHAPE;
+    if (in.ldx < in.m || in.lde < in.m) return VL_ERR_INVALID_ARG;
+  }
+  vl_batch* B = new vl_batch;
+  B->inst.assign(inst, inst + count);
+  B->count = count;
+  B->prec = prec;
+  size_t mx = 0;
+  for (int c : kChunkCandidates) {
+    B->chunk = c;
+    mx = std::max(mx, build_layout(B));
+  }
+  B->chunk = 2048;
+  build_layout(B);
+  B->ws_bytes = mx;
+  *out = B;
+  return VL_OK;
+}
+
+size_t varlingam_batch_workspace_bytes(const vl_batch* B) { return B ? B->ws_bytes : 0; }
+
+int varlingam_batch_chunk_len(const vl_batch* B) { return B ? B->chunk : 0; }
+
+int varlingam_batch_bind(vl_batch* B, void* ws, size_t ws_bytes, void* stream) {
+  if (!B || !ws) return VL_ERR_INVALID_ARG;
+  if (ws_bytes < B->ws_bytes || (reinterpret_cast<uintptr_t>(ws) & 255u)) return VL_ERR_WORKSPACE;
+  return upload(B, ws, reinterpret_cast<hipStream_t>(stream));
+}
+
+int varlingam_fit_batched(const vl_batch* B, void* ws, int32_t* dev_status, void* stream) {
+  if (!B || !ws || !dev_status) return VL_ERR_INVALID_ARG;
+  if (ws != B->bound) return VL_ERR_INVALID_ARG;
+  return launch_fit(B, ws, dev_status, reinterpret_cast<hipStream_t>(stream));
+}
+
+int varlingam_batch_autotune(vl_batch* B, void* ws, size_t ws_bytes, int32_t* dev_status,
+                             void* stream) {
+  if (!B || !ws || !dev_status) return VL_ERR_INVALID_ARG;
+  if (ws_bytes < B->ws_bytes || (reinterpret_cast<uintptr_t>(ws) & 255u)) return VL_ERR_WORKSPACE;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const std::string key = tune_key(B);
+  int best = -1;
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) best = it->second;
+  }
+  if (best < 0) {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return VL_ERR_HIP;
+    float best_ms = 0.f;
+    int rc = VL_OK;
+    for (int c : kChunkCandidates) {
+      B->chunk = c;
+      build_layout(B);
+      rc = upload(B, ws, s);
+      if (rc) break;
+      rc = launch_fit(B, ws, dev_status, s);                     // warm-up
+      if (rc) break;
+      hipEventRecord(e0, s);
+      for (int r = 0; r < 3 && !rc; ++r) rc = launch_fit(B, ws, dev_status, s);
+      hipEventRecord(e1, s);
+      if (rc || hipEventSynchronize(e1) != hipSuccess) {
+        rc = rc ? rc : VL_ERR_HIP;
+        break;
+      }
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (best < 0 || ms < best_ms) {
+        best = c;
+        best_ms = ms;
+      }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune_cache[key] = best;
+  }
+  B->chunk = best;
+  build_layout(B);
+  return upload(B, ws, s);
+}
+
+void varlingam_batch_destroy(vl_batch* B) { delete B; }
+
+}  // extern "C"

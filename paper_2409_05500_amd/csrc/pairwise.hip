@@ -15,148 +15,35 @@
 //      S[i,j] = (Hx[j] + Hr[i,j]) - (Hx[i] + Hr[j,i]).
 #include "gram.hpp"
 #include "pairwise.hpp"
+#include "pairwise_dev.hpp"
 #include "profile.hpp"
 
 namespace vl {
 
 // ------------------------------------------------------------------------------------------
-// Stage 2a: standardise + transpose.  Block = 64 x 64 tile of E (t x i), staged through LDS.
+// Kernels (single problem): one body call per block / thread.
 // ------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void standardize_transpose_kernel(
     const float* __restrict__ E, int64_t lde, int64_t n_eff, int64_t m,
     const double* __restrict__ mu, const double* __restrict__ cov, float* __restrict__ Xs,
     int64_t n_pad, int64_t m_pad, int32_t* st) {
-  __shared__ float tile[64][65];
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  const int64_t t0 = (int64_t)blockIdx.x * 64, i0 = (int64_t)blockIdx.y * 64;
-  const int64_t i = i0 + tx;
-  double mui = 0.0, inv = 0.0;
-  if (i < m) {
-    const double var = cov[i * m + i];
-    if (!(var > 0.0)) raise_status(st, VL_ERR_DEGENERATE);
-    mui = mu[i];
-    inv = var > 0.0 ? 1.0 / sqrt(var) : 0.0;
-  }
-  for (int r = ty; r < 64; r += 4) {
-    const int64_t t = t0 + r;
-    float v = 0.f;
-    if (i < m && t < n_eff) v = (float)(((double)E[t * lde + i] - mui) * inv);
-    tile[r][tx] = v;
-  }
-  __syncthreads();
-  for (int r = ty; r < 64; r += 4) {
-    const int64_t iv = i0 + r, t = t0 + tx;
-    if (iv < m_pad && t < n_pad) Xs[iv * n_pad + t] = tile[tx][r];  // rows >= m get zeros
-  }
+  standardize_tile(E, lde, n_eff, m, mu, cov, Xs, n_pad, m_pad, st, (int64_t)blockIdx.x * 64,
+                   (int64_t)blockIdx.y * 64);
 }
 
-// ------------------------------------------------------------------------------------------
-// Stage 2b: moments of the standardised columns -> Hx.  One block per variable; accurate
-// library exp/log (O(mn) work, not on the critical path).
-// ------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void hx_kernel(const float* __restrict__ Xs, int64_t n_pad,
                                                  int64_t n_eff, double* __restrict__ Hx,
                                                  double* __restrict__ momx) {
-  __shared__ double ra[4], rb[4];
-  const int64_t i = blockIdx.x;
-  const float* x = Xs + i * n_pad;
-  double sa = 0.0, sb = 0.0;
-  for (int64_t t = threadIdx.x; t < n_eff; t += 256) {
-    const float u = x[t];
-    const float a = fabsf(u);
-    sa += (double)(a + log1pf(expf(-2.f * a)) - (float)kLn2);
-    sb += (double)(u * expf(-0.5f * u * u));
-  }
-  sa = wave_sum_d(sa);
-  sb = wave_sum_d(sb);
-  if ((threadIdx.x & 63) == 0) {
-    ra[threadIdx.x >> 6] = sa;
-    rb[threadIdx.x >> 6] = sb;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const double A = (((ra[0] + ra[1]) + ra[2]) + ra[3]) / (double)n_eff;
-    const double B = (((rb[0] + rb[1]) + rb[2]) + rb[3]) / (double)n_eff;
-    Hx[i] = kHGauss - kK1 * (A - kGamma) * (A - kGamma) - kK2 * B * B;
-    if (momx) {
-      momx[2 * i] = A;
-      momx[2 * i + 1] = B;
-    }
-  }
+  hx_block(Xs, n_pad, n_eff, Hx, momx, blockIdx.x);
 }
 
-// ------------------------------------------------------------------------------------------
-// Stage 3: scaled pair coefficients (a, b) for i, j < m_pad; zero on the diagonal / padding.
-// ------------------------------------------------------------------------------------------
 __global__ void pair_coef_kernel(const double* __restrict__ cov, int64_t m, int64_t m_pad,
                                  float2* __restrict__ coef, int32_t* st) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= m_pad * m_pad) return;
-  const int64_t i = e / m_pad, j = e % m_pad;
-  float2 c = make_float2(0.f, 0.f);
-  if (i < m && j < m && i != j) {
-    const double vi = cov[i * m + i], vj = cov[j * m + j];
-    const double rho = cov[i * m + j] / sqrt(vi * vj);
-    const double omr = 1.0 - rho * rho;
-    if (!(omr >= kMinOneMinusRho2)) {
-      raise_status(st, VL_ERR_DEGENERATE);
-    } else {
-      const double s = sqrt(omr);
-      c = make_float2((float)(kWScale / s), (float)(kWScale * rho / s));
-    }
-  }
-  coef[e] = c;
+  pair_coef_elem(cov, m, m_pad, coef, st, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-// ------------------------------------------------------------------------------------------
-// Stage 4: the pairwise-moment kernel.
-//
-// Work item = (micro-tile of kT x kT variables {I, J} with bi <= bj, sample chunk).  One wave
-// per item; lanes run over samples (4 consecutive samples per lane per step, float4 loads of
-// the variable-major Xs), the kT*kT pair coefficients are wave-uniform (scalar registers).
-// Per pair, sample and direction (w = c u):
-//     q = w*w;  e = exp2(-q)  (= exp(-u^2/2));        Bacc += w * e
-//     t = exp2(kTScale * |w|) (= exp(-2|u|));         P    *= (1 + t)
-//     Uacc += |w|
-// log cosh u = |u| + ln(1 + exp(-2|u|)) - ln 2, so the logarithm is taken once per 64
-// samples of a lane from the running product P (each factor lies in (1, 2], P <= 2^64):
-//     Uacc += c ln2 (log2 P - count),  P = 1
-// which leaves Uacc = c * sum log cosh u exactly in real arithmetic.  Zero-padded samples
-// give w = 0, t = 1, factor 2: they add exactly 0 to Uacc and Bacc.
-// Two transcendentals and seven other VALU operations per (pair, sample, direction).
-//
-// At the end the 2 x 2 x kT x kT wave sums are formed by a reduce-scatter (lane l ends with
-// value l) and written to per-chunk FP32 partials part{U,B}[chunk][row][col].
-// Blocks are remapped so that XCD x (block id mod 8) processes a contiguous range of items
-// in chunk-major order, i.e. mostly one sample chunk per XCD and its L2.
-// ------------------------------------------------------------------------------------------
-constexpr int kT = 4;
-static_assert(2 * 2 * kT * kT == 64, "reduce-scatter expects 64 values per lane");
-
-__device__ inline void tile_coords(int64_t k, int nt, int& bi, int& bj) {
-  // upper-triangular tiles in row-major order: row r starts at r*nt - r*(r-1)/2
-  const double T = (double)nt;
-  const double disc = (2.0 * T + 1.0) * (2.0 * T + 1.0) - 8.0 * (double)k;
-  int r = (int)(((2.0 * T + 1.0) - sqrt(disc > 0.0 ? disc : 0.0)) * 0.5);
-  if (r < 0) r = 0;
-  if (r > nt - 1) r = nt - 1;
-  auto start = [nt](int q) { return (int64_t)q * nt - (int64_t)q * (q - 1) / 2; };
-  while (r > 0 && start(r) > k) --r;
-  while (r < nt - 1 && start(r + 1) <= k) ++r;
-  bi = r;
-  bj = r + (int)(k - start(r));
-}
-
-__device__ __forceinline__ void moment_step(float w, float& U, float& P, float& B) {
-  const float q = w * w;
-  const float e = __builtin_amdgcn_exp2f(-q);
-  B = fmaf(w, e, B);
-  const float aw = fabsf(w);
-  const float t = __builtin_amdgcn_exp2f(aw * (float)kTScale);
-  P = fmaf(P, t, P);
-  U += aw;
-}
-
+// Blocks are remapped so that XCD x (block id mod 8) processes a contiguous range of items in
+// chunk-major order, i.e. mostly one sample chunk per XCD and its L2.
 __global__ __launch_bounds__(256) void pairwise_moments_kernel(
     const float* __restrict__ Xs, int64_t n_pad, const float2* __restrict__ coef, int64_t m_pad,
     int64_t m, int nt, int64_t tiles, int chunk_len, int64_t items,
@@ -165,142 +52,21 @@ __global__ __launch_bounds__(256) void pairwise_moments_kernel(
   const int64_t b = blockIdx.x;
   const int64_t lb = (b & 7) * (nb >> 3) + (b >> 3);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
   const int64_t item = lb * 4 + wave;
   if (item >= items) return;
-  const int64_t chunk = item / tiles;
-  const int64_t tile = item - chunk * tiles;
-  int bi, bj;
-  tile_coords(tile, nt, bi, bj);
-  const int64_t i0 = (int64_t)bi * kT, j0 = (int64_t)bj * kT;
-
-  float ca[kT][kT], cb[kT][kT];
-#pragma unroll
-  for (int ii = 0; ii < kT; ++ii)
-#pragma unroll
-    for (int jj = 0; jj < kT; ++jj) {
-      const float2 c = coef[(i0 + ii) * m_pad + j0 + jj];
-      ca[ii][jj] = c.x;
-      cb[ii][jj] = c.y;
-    }
-
-  float U[2][kT][kT], P[2][kT][kT], B[2][kT][kT];
-#pragma unroll
-  for (int d = 0; d < 2; ++d)
-#pragma unroll
-    for (int ii = 0; ii < kT; ++ii)
-#pragma unroll
-      for (int jj = 0; jj < kT; ++jj) {
-        U[d][ii][jj] = 0.f;
-        P[d][ii][jj] = 1.f;
-        B[d][ii][jj] = 0.f;
-      }
-
-  const int64_t tb = chunk * chunk_len + 4 * lane;
-  const float4* xi_p[kT];
-  const float4* xj_p[kT];
-#pragma unroll
-  for (int k = 0; k < kT; ++k) {
-    xi_p[k] = reinterpret_cast<const float4*>(Xs + (i0 + k) * n_pad + tb);
-    xj_p[k] = reinterpret_cast<const float4*>(Xs + (j0 + k) * n_pad + tb);
-  }
-  const float cln2 = (float)(kWScale * kLn2);
-  const int steps = chunk_len / 256;                // 4 samples per lane per step
-  int since_flush = 0;
-  for (int s = 0; s < steps; ++s) {
-    float4 xi[kT], xj[kT];
-#pragma unroll
-    for (int k = 0; k < kT; ++k) {
-      xi[k] = xi_p[k][s * 64];
-      xj[k] = xj_p[k][s * 64];
-    }
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-#pragma unroll
-      for (int ii = 0; ii < kT; ++ii) {
-        const float xv = e == 0 ? xi[ii].x : e == 1 ? xi[ii].y : e == 2 ? xi[ii].z : xi[ii].w;
-#pragma unroll
-        for (int jj = 0; jj < kT; ++jj) {
-          const float yv = e == 0 ? xj[jj].x : e == 1 ? xj[jj].y : e == 2 ? xj[jj].z : xj[jj].w;
-          const float w0 = fmaf(xv, ca[ii][jj], -(yv * cb[ii][jj]));
-          const float w1 = fmaf(yv, ca[ii][jj], -(xv * cb[ii][jj]));
-          moment_step(w0, U[0][ii][jj], P[0][ii][jj], B[0][ii][jj]);
-          moment_step(w1, U[1][ii][jj], P[1][ii][jj], B[1][ii][jj]);
-        }
-      }
-    }
-    since_flush += 4;
-    if (since_flush == 64 || s == steps - 1) {
-      const float cnt = (float)since_flush;
-#pragma unroll
-      for (int d = 0; d < 2; ++d)
-#pragma unroll
-        for (int ii = 0; ii < kT; ++ii)
-#pragma unroll
-          for (int jj = 0; jj < kT; ++jj) {
-            U[d][ii][jj] = fmaf(__builtin_amdgcn_logf(P[d][ii][jj]) - cnt, cln2, U[d][ii][jj]);
-            P[d][ii][jj] = 1.f;
-          }
-      since_flush = 0;
-    }
-  }
-
-  // value index v = kind*32 + d*16 + ii*4 + jj (kind 0: U, 1: B)
-  float v[64];
-#pragma unroll
-  for (int d = 0; d < 2; ++d)
-#pragma unroll
-    for (int ii = 0; ii < kT; ++ii)
-#pragma unroll
-      for (int jj = 0; jj < kT; ++jj) {
-        v[d * 16 + ii * 4 + jj] = U[d][ii][jj];
-        v[32 + d * 16 + ii * 4 + jj] = B[d][ii][jj];
-      }
-  const float sum = wave_reduce_scatter64(v);
-  const int kind = lane >> 5, d = (lane >> 4) & 1, ii = (lane >> 2) & 3, jj = lane & 3;
-  const int64_t i = i0 + ii, j = j0 + jj;
-  if (i < m && j < m && i != j) {
-    const int64_t row = d ? j : i, col = d ? i : j;
-    float* dst = kind ? partB : partU;
-    dst[chunk * m * m + row * m + col] = sum;
-  }
+  pairwise_moments_item(Xs, n_pad, coef, m_pad, m, nt, tiles, chunk_len, item, partU, partB);
 }
 
-// ------------------------------------------------------------------------------------------
-// Stage 5: FP64 combine.  Hr[i][j] from the chunk partials (fixed order), then S.
-// ------------------------------------------------------------------------------------------
 __global__ void combine_hr_kernel(const float* __restrict__ partU, const float* __restrict__ partB,
                                   int nc, int64_t m, int64_t n_eff, double* __restrict__ Hr,
                                   double* __restrict__ mom) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= m * m) return;
-  const int64_t i = e / m, j = e % m;
-  if (i == j) {
-    Hr[e] = 0.0;
-    if (mom) mom[2 * e] = mom[2 * e + 1] = 0.0;
-    return;
-  }
-  double su = 0.0, sb = 0.0;
-  for (int c = 0; c < nc; ++c) {
-    su += (double)partU[(int64_t)c * m * m + e];
-    sb += (double)partB[(int64_t)c * m * m + e];
-  }
-  const double A = su / (kWScale * (double)n_eff);
-  const double B = sb / (kWScale * (double)n_eff);
-  Hr[e] = kHGauss - kK1 * (A - kGamma) * (A - kGamma) - kK2 * B * B;
-  if (mom) {
-    mom[2 * e] = A;
-    mom[2 * e + 1] = B;
-  }
+  combine_hr_elem(partU, partB, nc, m, n_eff, Hr, mom,
+                  (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 __global__ void score_kernel(const double* __restrict__ Hx, const double* __restrict__ Hr,
                              int64_t m, double* __restrict__ S) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= m * m) return;
-  const int64_t i = e / m, j = e % m;
-  // the same two sums in both orders -> S[j][i] == -S[i][j] bit for bit
-  S[e] = i == j ? 0.0 : (Hx[j] + Hr[i * m + j]) - (Hx[i] + Hr[j * m + i]);
+  score_elem(Hx, Hr, m, S, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ------------------------------------------------------------------------------------------

@@ -104,3 +104,32 @@ def test_build_flags_disable_packed_fp32():
     i = f.index("-packed-fp32-ops")
     assert f[i - 1] == "-Xclang" and f[i - 2] == "-target-feature"
     assert "--offload-arch=gfx950" in f
+
+
+def _desc(L, shapes, p=1):
+    d = (L.VlInstance * len(shapes))()
+    for b, (n, m) in enumerate(shapes):
+        d[b].X = d[b].M = d[b].intercept = d[b].E = d[b].order = d[b].B0 = d[b].Blag = FAKE
+        d[b].n, d[b].m, d[b].ldx, d[b].lde, d[b].p = n, m, m, m, p
+    return d
+
+
+def test_batch_plan_host_checks(L):
+    import ctypes
+    lib = L.lib
+    h = ctypes.c_void_p()
+    ok = _desc(L, [(500, 20), (8000, 200), (300, 2), (2000, 256)])
+    assert lib.varlingam_batch_create(ok, 4, 1, ctypes.byref(h)) == L.VL_OK
+    assert lib.varlingam_batch_workspace_bytes(h) > 4 * 8000 * 200 * 4   # >= the Xs copies
+    assert lib.varlingam_batch_chunk_len(h) == 2048
+    assert lib.varlingam_batch_bind(h, FAKE, 64, None) == L.VL_ERR_WORKSPACE
+    assert lib.varlingam_fit_batched(h, FAKE, FAKE, None) == L.VL_ERR_INVALID_ARG  # not bound
+    lib.varlingam_batch_destroy(h)
+    for shapes, p, code in [([(500, 257)], 1, L.VL_ERR_SHAPE), ([(500, 1)], 1, L.VL_ERR_SHAPE),
+                            ([(500, 129)], 2, L.VL_ERR_SHAPE), ([(21, 20)], 1, L.VL_ERR_SHAPE)]:
+        assert lib.varlingam_batch_create(_desc(L, shapes, p), 1, 1, ctypes.byref(h)) == code
+    bad = _desc(L, [(500, 20)])
+    bad[0].X = None
+    assert lib.varlingam_batch_create(bad, 1, 1, ctypes.byref(h)) == L.VL_ERR_INVALID_ARG
+    assert lib.varlingam_batch_create(ok, 4, 2, ctypes.byref(h)) == L.VL_ERR_INVALID_ARG
+    assert lib.varlingam_batch_create(ok, 0, 1, ctypes.byref(h)) == L.VL_ERR_INVALID_ARG

@@ -261,6 +261,13 @@ def test_fit_medium_workload(api, dev):
     _fit_and_compare(api, dev, synth.make_instance(synth.MEDIUM, 0), 1, "mixed", PA.B_TOL_FP32)
 
 
+@pytest.mark.parametrize("wl", [synth.SMALL, synth.MEDIUM])
+def test_fit_plain_fp32_accuracy(api, dev, wl):
+    """Plain FP32 mode (FP32 MFMA sums, no refinement) against the oracle, at its own bound."""
+    e0, e1 = _fit_and_compare(api, dev, synth.make_instance(wl, 0), 1, "fp32", PA.B_TOL_PLAIN)
+    print(f"plain fp32 {wl.name}: B rel err {e0:.1e} {e1:.1e}", flush=True)
+
+
 def test_fit_deterministic(api, dev):
     Xt = _dev(synth.make_instance(synth.SMALL, 1).X32, dev)
     a, b = api.fit(Xt, 1), api.fit(Xt, 1)
