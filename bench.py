@@ -30,19 +30,28 @@ TRANS_PER_EVAL = 3
 # HBM bytes per launch of the pairwise kernel, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs
 # of this workload (KiB per dispatch x 1024), each scaled by the counter's reading for a plain
 # 256 MiB device copy (FETCH_SIZE reads half of the bytes a copy reads: x2; WRITE_SIZE reads them
-# exactly: x1).  Keyed by the SHA-256 of the kernel source the counters were taken with; any
-# other source reports null.
-MEASURED_TRAFFIC = {}
+# exactly: x1).  Keyed by the SHA-256 of the kernel sources the counters were taken with
+# (kernel_source_digest); any other source reports null.
+MEASURED_TRAFFIC = {
+    # FETCH_SIZE 37683.6 KiB x 2, WRITE_SIZE 8558.8 KiB x 1 per dispatch (9 dispatches)
+    "35862cffcd80236e79ece5bd1bb71b39e1b2a37898d5fa38dc3369746dbe2835": 85940282,
+}
 STAGES = ("var_gram", "var_solve", "var_residual", "var_refine", "pairwise_cov",
           "pairwise_prep", "pairwise_moments", "pairwise_combine", "order", "estimate_b")
 BATCH_STAGES = ("batch_var", "batch_pairwise", "batch_moments", "batch_order_b")
 
 
-def measured_traffic():
+def kernel_source_digest():
+    """SHA-256 over the sources of the pairwise-moment kernel (launcher and device body)."""
     import hashlib
-    path = os.path.join(ROOT, "paper_2409_05500_amd", "csrc", "pairwise.hip")
-    digest = hashlib.sha256(open(path, "rb").read()).hexdigest()
-    return MEASURED_TRAFFIC.get(digest)
+    h = hashlib.sha256()
+    for f in ("pairwise.hip", "pairwise_dev.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2409_05500_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    return MEASURED_TRAFFIC.get(kernel_source_digest())
 
 
 def cpu_baseline(E64, cols: int):
@@ -121,6 +130,49 @@ def bench_batched(api, torch, steps: int, seed: int):
     return out
 
 
+def bench_backward(api, _lib, torch, steps: int, seed: int):
+    """Gradient of the score matrix, dE = d<G, S(E)>/dE, at m = 1000, n = 50000 (Laplace
+    shocks, p = 1): E is the GPU VAR fit's residual matrix, G a seeded N(0, 1) cotangent.
+    Algorithmic transcendentals: dL/du of both directions of every unordered pair and sample
+    (tanh: exp + reciprocal; Gaussian: exp) = 3 m (m - 1) n_eff; the owner-computes kernel
+    evaluates each pair twice (once per owner), so its own count is twice that."""
+    import numpy as np
+    import synth
+    wl = synth.LARGE
+    inst = synth.make_instance(wl, seed)
+    dev = torch.device("cuda:0")
+    _, _, E = api.fit_var(torch.from_numpy(inst.X32).to(dev), wl.p, "mixed")
+    m, n_eff = E.shape[1], E.shape[0]
+    G = torch.from_numpy(np.random.default_rng(seed + 1).normal(size=(m, m))).to(dev)
+    for _ in range(2):
+        api.pairwise_stats_backward(E, G)
+    torch.cuda.synchronize()
+    _lib.profile_enable("pairwise_cov,pairwise_prep,pairwise_moments,pairwise_combine,"
+                        "backward_prep,backward_owner,backward_tail")
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        api.pairwise_stats_backward(E, G)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    st = {k: _lib.profile_read(k) for k in ("pairwise_cov", "pairwise_prep", "pairwise_moments",
+                                            "pairwise_combine", "backward_prep",
+                                            "backward_owner", "backward_tail")}
+    _lib.profile_enable(None)
+    ms = {k: v[0] / max(v[1], 1) for k, v in st.items()}
+    owner_s = ms["backward_owner"] / 1e3
+    alg = 3.0 * m * (m - 1) * n_eff
+    return {"workload": f"{wl.name}, residuals of the GPU VAR fit, N(0,1) cotangent",
+            "m": m, "n_eff": n_eff, "backward_ms": dt * 1e3,
+            "forward_recompute_ms": sum(ms[k] for k in ("pairwise_cov", "pairwise_prep",
+                                                        "pairwise_moments", "pairwise_combine")),
+            "stage_ms": {k: round(v, 4) for k, v in ms.items()},
+            "owner_kernel_roofline": {"kernel": "bwd_owner_kernel", "bound": "alu",
+                                      "achieved": alg / owner_s / 1e12,
+                                      "peak": TRANS_PEAK / 1e12, "unit": "Ttrans/s",
+                                      "frac": alg / owner_s / TRANS_PEAK,
+                                      "evaluated_frac": 2 * alg / owner_s / TRANS_PEAK}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +183,10 @@ def main():
     ap.add_argument("--cpu-cols", type=int, default=160)
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-workload section (256 uneven problems)")
+    ap.add_argument("--no-backward", action="store_true",
+                    help="skip the score-gradient section (m = 1000, n = 50000)")
+    ap.add_argument("--only", choices=("batch", "backward"), default=None,
+                    help="profiling runs: run just one extra section and print its JSON")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a plain copy "
                          "kernel of known traffic, for calibrating hardware byte counters)")
@@ -144,6 +200,15 @@ def main():
     import torch
     import synth
     from paper_2409_05500_amd import api, _lib
+
+    if args.only == "batch":
+        print(json.dumps({"batched": bench_batched(api, torch, max(3, args.steps // 2),
+                                                   args.seed)}), flush=True)
+        return
+    if args.only == "backward":
+        print(json.dumps({"backward": bench_backward(api, _lib, torch, max(3, args.steps // 2),
+                                                     args.seed)}), flush=True)
+        return
 
     wl = synth.FINANCE
     inst = synth.make_instance(wl, args.seed)
@@ -216,6 +281,8 @@ def main():
     }
     if not args.no_batch:
         out["batched"] = bench_batched(api, torch, max(3, args.steps // 2), args.seed)
+    if not args.no_backward:
+        out["backward"] = bench_backward(api, _lib, torch, 3, args.seed)
     if not args.no_cpu_baseline:
         from oracle import varlingam as O  # noqa: F401  (CPU baseline only)
         out["cpu_baseline"] = cpu_baseline(fit.E.cpu().numpy().astype(np.float64), args.cpu_cols)
