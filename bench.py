@@ -33,8 +33,8 @@ TRANS_PER_EVAL = 3
 # exactly: x1).  Keyed by the SHA-256 of the kernel sources the counters were taken with
 # (kernel_source_digest); any other source reports null.
 MEASURED_TRAFFIC = {
-    # FETCH_SIZE 37683.6 KiB x 2, WRITE_SIZE 8558.8 KiB x 1 per dispatch (9 dispatches)
-    "35862cffcd80236e79ece5bd1bb71b39e1b2a37898d5fa38dc3369746dbe2835": 85940282,
+    # FETCH_SIZE 35146.8 KiB x 2, WRITE_SIZE 8492.7 KiB x 1 per dispatch (9 dispatches)
+    "4194558e3915907216da564fa6da429987fdebf0bf28efe67eb5695970b463be": 80677120,
 }
 STAGES = ("var_gram", "var_solve", "var_residual", "var_refine", "pairwise_cov",
           "pairwise_prep", "pairwise_moments", "pairwise_combine", "order", "estimate_b")

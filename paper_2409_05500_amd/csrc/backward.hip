@@ -14,7 +14,7 @@
 //   dE_i(t) = (dx_i(t) - mean dx_i - x_i(t) mean(dx_i x_i)) / sd_i      (standardisation)
 //
 // The per-sample terms are recomputed (nothing of size m^2 n is stored).  The transcendental
-// pass is owner-computes: one wave owns 4 variables and a 512-sample chunk and visits every
+// pass is owner-computes: one wave owns 4 variables and a 128-sample chunk and visits every
 // partner block, so each dx_i(t) is summed in registers in a fixed order (no atomics); the
 // pair's R contribution of that chunk is reduced across the wave and written per chunk.
 #include "backward.hpp"
@@ -23,7 +23,7 @@
 namespace vl {
 
 constexpr int kBT = 4;        // variables per wave (owner block)
-constexpr int kBSpl = 8;      // samples per lane
+constexpr int kBSpl = 2;      // samples per lane (67 VGPRs: many waves hide the trans latency)
 constexpr int kBChunk = 64 * kBSpl;
 
 // Per ordered pair (i, j), i != j, the wave-uniform constants of the transcendental pass:
@@ -102,8 +102,8 @@ __device__ __forceinline__ float dir_grad(float w, float a2, float na, float bb,
   return fmaf(a2, r, fmaf(fmaf(q, bq, bb), e, na));
 }
 
-// One wave per (block I of 4 variables, 512-sample chunk); lane l holds samples
-// chunk * 512 + 8 l + [0, 8).  The wave walks every partner j (runtime loop, next partner's
+// One wave per (block I of 4 variables, 128-sample chunk); lane l holds samples
+// chunk * 128 + 2 l + [0, 2).  The wave walks every partner j (runtime loop, next partner's
 // samples prefetched), and for the 4 pairs (i, j), i in I: dx_i += g_ij / s - rho g_ji / s and
 // the chunk's R partial of (i, j) is summed across the wave.  Output: dx (m_pad x n_pad,
 // variable-major FP32: direct and Hx terms) and Rp[chunk][i][j] for j > i.
@@ -127,20 +127,15 @@ __global__ __launch_bounds__(256) void bwd_owner_kernel(
   // carry rounding at many times the scale of the result.
   float xi[kBT][kBSpl], xj[kBSpl];
   double acc[kBT][kBSpl];
-  auto load16 = [&](const float* src, int64_t row, float* dst) {
-    const float4* p = reinterpret_cast<const float4*>(src + row * n_pad + tb);
-#pragma unroll
-    for (int v = 0; v < kBSpl / 4; ++v) {
-      const float4 f = p[v];
-      dst[4 * v] = f.x;
-      dst[4 * v + 1] = f.y;
-      dst[4 * v + 2] = f.z;
-      dst[4 * v + 3] = f.w;
-    }
+  static_assert(kBSpl == 2, "float2 loads and stores");
+  auto load_x = [&](const float* src, int64_t row, float* dst) {
+    const float2 f = *reinterpret_cast<const float2*>(src + row * n_pad + tb);
+    dst[0] = f.x;
+    dst[1] = f.y;
   };
 #pragma unroll
   for (int ii = 0; ii < kBT; ++ii) {
-    load16(Xs, i0 + ii, xi[ii]);
+    load_x(Xs, i0 + ii, xi[ii]);
     // Hx term: the standardised column's own entropy moments
     const float2 cx = vx[i0 + ii];
 #pragma unroll
@@ -148,11 +143,11 @@ __global__ __launch_bounds__(256) void bwd_owner_kernel(
       acc[ii][e] = (double)dir_grad(xi[ii][e] * (float)kWScale, 2.f * cx.x, -cx.x, cx.y,
                                     cx.y * (float)(-1.0 / (kWScale * kWScale)));
   }
-  load16(Xs, 0, xj);
+  load_x(Xs, 0, xj);
 
   for (int64_t j = 0; j < m; ++j) {
     float xn[kBSpl];
-    load16(Xs, j + 1 < m_pad ? j + 1 : j, xn);      // prefetch the next partner
+    load_x(Xs, j + 1 < m_pad ? j + 1 : j, xn);      // prefetch the next partner
     const BwdPair* c4 = bp + j * m_pad + i0;
     float rs[kBT];
 #pragma unroll
@@ -184,13 +179,9 @@ __global__ __launch_bounds__(256) void bwd_owner_kernel(
     for (int e = 0; e < kBSpl; ++e) xj[e] = xn[e];
   }
 #pragma unroll
-  for (int ii = 0; ii < kBT; ++ii) {
-    float4* p = reinterpret_cast<float4*>(dx + (i0 + ii) * n_pad + tb);
-#pragma unroll
-    for (int v = 0; v < kBSpl / 4; ++v)
-      p[v] = make_float4((float)acc[ii][4 * v], (float)acc[ii][4 * v + 1],
-                         (float)acc[ii][4 * v + 2], (float)acc[ii][4 * v + 3]);
-  }
+  for (int ii = 0; ii < kBT; ++ii)
+    *reinterpret_cast<float2*>(dx + (i0 + ii) * n_pad + tb) =
+        make_float2((float)acc[ii][0], (float)acc[ii][1]);
 }
 
 // R[i][j] = R[j][i] = -(sum over chunks of Rp[c][i][j], i < j) / (c s n)  (FP64 sum), the

@@ -11,8 +11,8 @@ struct BwdPlan {
   PairwisePlan fwd;        // forward recompute
   int nt = 0;              // 4-variable blocks
   int64_t m_pad = 0;       // nt * 4
-  int64_t nchunk = 0;      // 512-sample chunks
-  int64_t n_pad = 0;       // nchunk * 512
+  int64_t nchunk = 0;      // 128-sample chunks
+  int64_t n_pad = 0;       // nchunk * 128
 };
 
 struct BwdWs {

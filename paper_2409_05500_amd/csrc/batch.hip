@@ -392,7 +392,7 @@ InstLayout layout_for(const vl_instance& in, int chunk) {
   L.nt = (int)ceil_div(m, 4);
   L.m_pad = (int64_t)L.nt * 4;
   L.tiles = (int64_t)L.nt * (L.nt + 1) / 2;
-  const int64_t cl = std::min<int64_t>(chunk, round_up(n_eff, 256));
+  const int64_t cl = std::min<int64_t>(chunk, round_up(n_eff, 128));
   L.chunk_len = (int)cl;
   L.nchunk = (int)ceil_div(n_eff, cl);
   L.n_pad = (int64_t)L.nchunk * cl;

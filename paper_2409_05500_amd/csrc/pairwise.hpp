@@ -10,7 +10,7 @@ struct PairwisePlan {
   int64_t m_pad = 0;      // nt * 4
   int64_t tiles = 0;      // nt (nt + 1) / 2 upper-triangular micro-tiles
   int nc = 0;             // sample chunks
-  int chunk_len = 0;      // samples per chunk, multiple of 256
+  int chunk_len = 0;      // samples per chunk, multiple of 128
   int64_t n_pad = 0;      // nc * chunk_len >= n_eff
   int64_t items = 0;      // tiles * nc (one wave each)
   int64_t blocks = 0;     // ceil(items / 4) rounded up to a multiple of 8

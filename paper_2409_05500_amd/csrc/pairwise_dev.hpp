@@ -94,8 +94,9 @@ __device__ inline void pair_coef_elem(const double* __restrict__ cov, int64_t m,
 // Stage 4: the pairwise-moment kernel.
 //
 // Work item = (micro-tile of kT x kT variables {I, J} with bi <= bj, sample chunk).  One wave
-// per item; lanes run over samples (4 consecutive samples per lane per step, float4 loads of
-// the variable-major Xs), the kT*kT pair coefficients are wave-uniform (scalar registers).
+// per item; lanes run over samples (2 consecutive samples per lane per step, float2 loads of
+// the variable-major Xs; pairs outermost within a step), the kT*kT pair coefficients are
+// wave-uniform (scalar registers).
 // Per pair, sample and direction (w = c u):
 //     q = w*w;  e = exp2(-q)  (= exp(-u^2/2));        Bacc += w * e
 //     t = exp2(kTScale * |w|) (= exp(-2|u|));         P    *= (1 + t)
@@ -137,8 +138,9 @@ __device__ __forceinline__ void moment_step(float w, float& U, float& P, float& 
   U += aw;
 }
 
-// One wave's work item (tile, chunk); item < items is the caller's check.
-__device__ inline void pairwise_moments_item(
+// One wave's work item (tile, chunk); item < items is the caller's check.  Always inlined:
+// as a call its register use rises from 168 to 248 and the occupancy falls to 2 waves/SIMD.
+__device__ __attribute__((always_inline)) inline void pairwise_moments_item(
     const float* __restrict__ Xs, int64_t n_pad, const float2* __restrict__ coef, int64_t m_pad,
     int64_t m, int nt, int64_t tiles, int chunk_len, int64_t item,
     float* __restrict__ partU, float* __restrict__ partB) {
@@ -176,8 +178,9 @@ __device__ inline void pairwise_moments_item(
         B[d][ii][jj] = 0.f;
       }
 
-  // uniform row bases (scalar registers) and one 32-bit per-lane sample offset
-  const uint32_t tb = (uint32_t)(chunk * chunk_len) + 4u * (uint32_t)lane;
+  // uniform row bases (scalar registers) and one 32-bit per-lane sample offset; 2 consecutive
+  // samples per lane per step keep the live state at 168 VGPRs (3 waves per SIMD)
+  const uint32_t tb = (uint32_t)(chunk * chunk_len) + 2u * (uint32_t)lane;
   const float* xi_r[kT];
   const float* xj_r[kT];
 #pragma unroll
@@ -186,24 +189,24 @@ __device__ inline void pairwise_moments_item(
     xj_r[k] = Xs + (j0 + k) * n_pad;
   }
   const float cln2 = (float)(kWScale * kLn2);
-  const int steps = chunk_len / 256;                // 4 samples per lane per step
+  const int steps = chunk_len / 128;                // 2 samples per lane per step
   int since_flush = 0;
   for (int s = 0; s < steps; ++s) {
-    float4 xi[kT], xj[kT];
+    float2 xi[kT], xj[kT];
 #pragma unroll
     for (int k = 0; k < kT; ++k) {
-      const uint32_t o = tb + 256u * (uint32_t)s;
-      xi[k] = *reinterpret_cast<const float4*>(xi_r[k] + o);
-      xj[k] = *reinterpret_cast<const float4*>(xj_r[k] + o);
+      const uint32_t o = tb + 128u * (uint32_t)s;
+      xi[k] = *reinterpret_cast<const float2*>(xi_r[k] + o);
+      xj[k] = *reinterpret_cast<const float2*>(xj_r[k] + o);
     }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int ii = 0; ii < kT; ++ii) {
 #pragma unroll
-      for (int ii = 0; ii < kT; ++ii) {
-        const float xv = e == 0 ? xi[ii].x : e == 1 ? xi[ii].y : e == 2 ? xi[ii].z : xi[ii].w;
+      for (int jj = 0; jj < kT; ++jj) {
 #pragma unroll
-        for (int jj = 0; jj < kT; ++jj) {
-          const float yv = e == 0 ? xj[jj].x : e == 1 ? xj[jj].y : e == 2 ? xj[jj].z : xj[jj].w;
+        for (int e = 0; e < 2; ++e) {
+          const float xv = e ? xi[ii].y : xi[ii].x;
+          const float yv = e ? xj[jj].y : xj[jj].x;
           const float w0 = fmaf(xv, ca[ii][jj], -(yv * cb[ii][jj]));
           const float w1 = fmaf(yv, ca[ii][jj], -(xv * cb[ii][jj]));
           moment_step(w0, U[0][ii][jj], P[0][ii][jj], B[0][ii][jj]);
@@ -211,7 +214,7 @@ __device__ inline void pairwise_moments_item(
         }
       }
     }
-    since_flush += 4;
+    since_flush += 2;
     if (since_flush == 64 || s == steps - 1) {
       const float cnt = (float)since_flush;
 #pragma unroll
