@@ -248,12 +248,10 @@ __global__ __launch_bounds__(256) void bat_prep_kernel(BTables T, int32_t* st0) 
     pair_coef_elem(d.cov, d.m, d.m_pad, d.coef, st0 + b, (lb - d.m) * 256 + threadIdx.x);
 }
 
-// The pairwise-moment items of all problems; the grid (a multiple of 8 blocks) is remapped so
-// that each XCD takes a contiguous range of blocks, i.e. mostly whole problems per L2.
-__global__ __launch_bounds__(256) void bat_moments_kernel(
-    BTables T, int64_t total) {
-  const int64_t nb = gridDim.x;
-  const int64_t g = (int64_t)(blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
+// The pairwise-moment items of all problems, in the table's longest-first order (no XCD
+// remap: that would hand one XCD all the long items).
+__global__ __launch_bounds__(256) void bat_moments_kernel(BTables T, int64_t total) {
+  const int64_t g = blockIdx.x;
   if (g >= total) return;
   int64_t lb;
   const int b = bat_locate(T, kMapMom, g, lb);
@@ -505,17 +503,26 @@ int upload(vl_batch* B, void* ws, hipStream_t stream) {
     d.items = L.items;
     I[b] = d;
   }
+  // Longest blocks first: a block's duration grows with its problem's sample count (Gram,
+  // residual, column means, moment items) or its variable count, so the problems are laid out
+  // in the launch by decreasing n_eff, then m; the short blocks of small problems fill the tail.
+  std::vector<int> lpt(n);
+  for (int b = 0; b < n; ++b) lpt[b] = b;
+  std::stable_sort(lpt.begin(), lpt.end(), [&](int a, int c) {
+    const int64_t na = B->inst[a].n - B->inst[a].p, nc_ = B->inst[c].n - B->inst[c].p;
+    return na != nc_ ? na > nc_ : B->inst[a].m > B->inst[c].m;
+  });
   for (int k = 0; k < kNumMaps; ++k) {
     int32_t* bm = reinterpret_cast<int32_t*>(host.data() + B->tab_off[2 * k]);
     int64_t* first = reinterpret_cast<int64_t*>(host.data() + B->tab_off[2 * k + 1]);
     int64_t pos = 0;
-    for (int b = 0; b < n; ++b) {
+    for (int b : lpt) {
       first[b] = pos;
       const int64_t nb = blocks_for(k, B->inst[b], B->lay[b]);
       for (int64_t q = 0; q < nb; ++q) bm[pos + q] = b;
       pos += nb;
     }
-    for (int64_t q = pos; q < B->total[k] + 8; ++q) bm[q] = n - 1;   // padding blocks
+    for (int64_t q = pos; q < B->total[k] + 8; ++q) bm[q] = lpt[n - 1];   // padding blocks
   }
   if (hipMemcpyAsync(ws, host.data(), host.size(), hipMemcpyHostToDevice, stream) != hipSuccess)
     return VL_ERR_HIP;
