@@ -158,11 +158,21 @@ def bench_backward(api, _lib, torch, steps: int, seed: int):
                                             "pairwise_combine", "backward_prep",
                                             "backward_owner", "backward_tail")}
     _lib.profile_enable(None)
+    # with the forward's saved statistics (the autograd path): no recompute of the moments
+    saved = api.pairwise_stats_save(E)[4]
+    api.pairwise_stats_backward(E, G, saved=saved)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        api.pairwise_stats_backward(E, G, saved=saved)
+    torch.cuda.synchronize()
+    dt_saved = (time.perf_counter() - t0) / steps
     ms = {k: v[0] / max(v[1], 1) for k, v in st.items()}
     owner_s = ms["backward_owner"] / 1e3
     alg = 3.0 * m * (m - 1) * n_eff
     return {"workload": f"{wl.name}, residuals of the GPU VAR fit, N(0,1) cotangent",
             "m": m, "n_eff": n_eff, "backward_ms": dt * 1e3,
+            "backward_with_saved_ms": dt_saved * 1e3,
             "forward_recompute_ms": sum(ms[k] for k in ("pairwise_cov", "pairwise_prep",
                                                         "pairwise_moments", "pairwise_combine")),
             "stage_ms": {k: round(v, 4) for k, v in ms.items()},

@@ -104,9 +104,14 @@ int pairwise_stats(const float* E, int64_t n_eff, int64_t m, int64_t lde, int pr
 /* Gradient of the pairwise score (the precompute of Sec. 4.2 steps 1-2 with Eq. 1-2 made  */
 /* differentiable): dE = d<G, S(E)>/dE for an m x m cotangent G.                           */
 /*                                                                                        */
-/* E     in, n_eff x m float32, leading dimension lde >= m (the same input as              */
-/*       pairwise_stats; the forward statistics are recomputed inside the call, nothing of  */
-/*       size m^2 n is stored).                                                            */
+/* pairwise_stats_save() is pairwise_stats() that also writes `saved`, the statistics the  */
+/* backward needs (pairwise_stats_saved_doubles(m) = 3 m^2 + 3 m doubles, device memory):  */
+/* the moments (A, B) of every ordered pair, of every variable, the covariance and the     */
+/* column means.  Its workspace is pairwise_stats_workspace_bytes().                        */
+/*                                                                                        */
+/* E     in, n_eff x m float32, leading dimension lde >= m (the same input as the forward). */
+/* saved in, nullable: the block pairwise_stats_save() wrote for this E; with NULL the      */
+/*       forward statistics are recomputed inside the call.  Nothing of size m^2 n is kept. */
 /* G     in, m x m float64 row-major cotangent of S (only G - G^T matters: S is            */
 /*       antisymmetric; the diagonal is ignored).                                          */
 /* dE    out, n_eff x m float32, leading dimension ldde >= m.                              */
@@ -116,10 +121,14 @@ int pairwise_stats(const float* E, int64_t n_eff, int64_t m, int64_t lde, int pr
 /* Host errors: m < 2, n_eff < 2, m > 65536 -> VL_ERR_SHAPE.                                */
 /* Device errors: as pairwise_stats (VL_ERR_NONFINITE, VL_ERR_DEGENERATE).                  */
 /* ------------------------------------------------------------------------------------- */
+size_t pairwise_stats_saved_doubles(int64_t m);
+int pairwise_stats_save(const float* E, int64_t n_eff, int64_t m, int64_t lde, int prec,
+                        double* Hx, double* Hr, double* S, double* Cov, double* saved, void* ws,
+                        size_t ws_bytes, int32_t* dev_status, void* stream);
 size_t pairwise_stats_backward_workspace_bytes(int64_t n_eff, int64_t m, int prec);
 int pairwise_stats_backward(const float* E, int64_t n_eff, int64_t m, int64_t lde, int prec,
-                            const double* G, float* dE, int64_t ldde, void* ws, size_t ws_bytes,
-                            int32_t* dev_status, void* stream);
+                            const double* saved, const double* G, float* dE, int64_t ldde,
+                            void* ws, size_t ws_bytes, int32_t* dev_status, void* stream);
 
 /* ------------------------------------------------------------------------------------- */
 /* Lookup-only causal ordering (Alg. 1 main loop with Eq. 3): m steps over the static S.  */

@@ -6,7 +6,7 @@ C ABI (include/varlingam.h).
 API (`paper_2409_05500_amd.api`), which raises if libvarlingam.so has not been built.
 """
 _API = ("fit", "fit_var", "pairwise_stats", "approx_order", "estimate_B", "FitResult",
-        "DeviceStatus", "pairwise_stats_backward", "pairwise_score", "PairwiseScore",
+        "DeviceStatus", "pairwise_stats_backward", "pairwise_stats_save", "pairwise_score", "PairwiseScore",
         "BatchFitter", "fit_batched")
 
 

@@ -41,8 +41,11 @@ SIGNATURES = {
     "pairwise_stats_workspace_bytes": (_sz, [_i64, _i64, _i32]),
     "pairwise_stats": (_i32, [_p, _i64, _i64, _i64, _i32, _p, _p, _p, _p, _p, _sz, _p, _p]),
     "pairwise_stats_backward_workspace_bytes": (_sz, [_i64, _i64, _i32]),
-    "pairwise_stats_backward": (_i32, [_p, _i64, _i64, _i64, _i32, _p, _p, _i64, _p, _sz, _p,
-                                       _p]),
+    "pairwise_stats_saved_doubles": (_sz, [_i64]),
+    "pairwise_stats_save": (_i32, [_p, _i64, _i64, _i64, _i32, _p, _p, _p, _p, _p, _p, _sz, _p,
+                                   _p]),
+    "pairwise_stats_backward": (_i32, [_p, _i64, _i64, _i64, _i32, _p, _p, _p, _i64, _p, _sz,
+                                       _p, _p]),
     "approx_order_workspace_bytes": (_sz, [_i64]),
     "approx_order": (_i32, [_p, _i64, _p, _p, _p, _sz, _p, _p]),
     "estimate_B_workspace_bytes": (_sz, [_i64, _i32]),

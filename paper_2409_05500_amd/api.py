@@ -93,20 +93,48 @@ def pairwise_stats(E: torch.Tensor, prec="mixed", status: "DeviceStatus | None" 
     return Hx, Hr, S, Cov
 
 
+def pairwise_stats_save(E: torch.Tensor, prec="mixed", status: "DeviceStatus | None" = None):
+    """pairwise_stats plus the block of forward statistics the backward can reuse:
+    (Hx, Hr, S, Cov, saved) with saved [3 m^2 + 3 m] f64."""
+    _require(E, torch.float32, "E")
+    n_eff, m = E.shape
+    dev = E.device
+    Hx = torch.empty(m, dtype=torch.float64, device=dev)
+    Hr = torch.empty((m, m), dtype=torch.float64, device=dev)
+    S = torch.empty((m, m), dtype=torch.float64, device=dev)
+    Cov = torch.empty((m, m), dtype=torch.float64, device=dev)
+    saved = torch.empty(lib.pairwise_stats_saved_doubles(m), dtype=torch.float64, device=dev)
+    ws = _workspace(lib.pairwise_stats_workspace_bytes(n_eff, m, _prec(prec)), dev)
+    st = status if status is not None else DeviceStatus(dev)
+    check(lib.pairwise_stats_save(E.data_ptr(), n_eff, m, E.stride(0), _prec(prec),
+                                  Hx.data_ptr(), Hr.data_ptr(), S.data_ptr(), Cov.data_ptr(),
+                                  saved.data_ptr(), ws.data_ptr(), ws.numel(), st.ptr,
+                                  _stream_ptr(dev)), "pairwise_stats_save")
+    if status is None:
+        st.read("pairwise_stats_save")
+    return Hx, Hr, S, Cov, saved
+
+
 def pairwise_stats_backward(E: torch.Tensor, G: torch.Tensor, prec="mixed",
-                            status: "DeviceStatus | None" = None) -> torch.Tensor:
-    """dE = d<G, S(E)>/dE (n_eff x m f32) for the m x m f64 cotangent G of the score matrix."""
+                            status: "DeviceStatus | None" = None,
+                            saved: "torch.Tensor | None" = None) -> torch.Tensor:
+    """dE = d<G, S(E)>/dE (n_eff x m f32) for the m x m f64 cotangent G of the score matrix;
+    `saved` (from pairwise_stats_save on the same E) skips the forward recompute."""
     _require(E, torch.float32, "E")
     n_eff, m = E.shape
     dev = E.device
     G = G.to(device=dev, dtype=torch.float64).contiguous()
     if G.shape != (m, m):
         raise ValueError(f"G must be {m} x {m}, got {tuple(G.shape)}")
+    if saved is not None and (saved.dtype != torch.float64 or not saved.is_cuda or
+                              saved.numel() != lib.pairwise_stats_saved_doubles(m)):
+        raise ValueError("saved must be the f64 device block of pairwise_stats_save")
     dE = torch.empty((n_eff, m), dtype=torch.float32, device=dev)
     nb = lib.pairwise_stats_backward_workspace_bytes(n_eff, m, _prec(prec))
     ws = _workspace(nb, dev)
     st = status if status is not None else DeviceStatus(dev)
     check(lib.pairwise_stats_backward(E.data_ptr(), n_eff, m, E.stride(0), _prec(prec),
+                                      saved.data_ptr() if saved is not None else None,
                                       G.data_ptr(), dE.data_ptr(), dE.stride(0), ws.data_ptr(),
                                       ws.numel(), st.ptr, _stream_ptr(dev)),
           "pairwise_stats_backward")
@@ -116,19 +144,20 @@ def pairwise_stats_backward(E: torch.Tensor, G: torch.Tensor, prec="mixed",
 
 
 class PairwiseScore(torch.autograd.Function):
-    """S = score(E) with a backward through the HIP gradient kernels (the forward statistics
-    are recomputed in the backward; only E is saved)."""
+    """S = score(E) with a backward through the HIP gradient kernels; the forward keeps the
+    O(m^2) block of statistics the backward needs (no recompute of the moments)."""
 
     @staticmethod
     def forward(ctx, E, prec="mixed"):
         ctx.prec = prec
-        ctx.save_for_backward(E)
-        return pairwise_stats(E.detach(), prec)[2]
+        _, _, S, _, saved = pairwise_stats_save(E.detach(), prec)
+        ctx.save_for_backward(E, saved)
+        return S
 
     @staticmethod
     def backward(ctx, G):
-        (E,) = ctx.saved_tensors
-        return pairwise_stats_backward(E.detach(), G, ctx.prec), None
+        E, saved = ctx.saved_tensors
+        return pairwise_stats_backward(E.detach(), G, ctx.prec, saved=saved), None
 
 
 def pairwise_score(E: torch.Tensor, prec="mixed") -> torch.Tensor:

@@ -338,21 +338,32 @@ size_t bwd_ws_bytes(const BwdPlan& b, void* base, BwdWs* out) {
 }
 
 int run_backward(const BwdPlan& b, const BwdWs& w, const float* E, int64_t lde, int prec,
-                 const double* G, float* dE, int64_t ldde, int32_t* st, hipStream_t stream) {
+                 const double* saved, const double* G, float* dE, int64_t ldde, int32_t* st,
+                 hipStream_t stream) {
   const int64_t m = b.fwd.m, n_eff = b.fwd.n_eff;
-  // forward recompute: covariance, moments of every ordered pair, Hx moments
-  int rc = run_pairwise(b.fwd, w.fwd, E, lde, prec, w.Hx, w.Hr, w.S, w.cov, w.mom, st, stream);
-  if (rc) return rc;
+  int rc = VL_OK;
+  // the forward's statistics: the saved block [A,B per ordered pair | A,B per variable |
+  // covariance | means], else recomputed here
+  const double *mom = w.mom, *momx = w.fwd.momx, *cov = w.cov, *mu = w.fwd.mu;
+  if (saved) {
+    mom = saved;
+    momx = saved + 2 * m * m;
+    cov = saved + 2 * m * m + 2 * m;
+    mu = saved + 3 * m * m + 2 * m;
+  } else {
+    rc = run_pairwise(b.fwd, w.fwd, E, lde, prec, w.Hx, w.Hr, w.S, w.cov, w.mom, st, stream);
+    if (rc) return rc;
+  }
   {
     ProfileScope ps("backward_prep", stream);
     // standardised variable-major copy in this pass's chunking (zero padded)
-    rc = standardize_to(E, lde, n_eff, m, w.fwd.mu, w.cov, w.Xs, b.n_pad, b.m_pad, st, stream);
+    rc = standardize_to(E, lde, n_eff, m, mu, cov, w.Xs, b.n_pad, b.m_pad, st, stream);
     if (rc) return rc;
     bwd_pair_kernel<<<(unsigned)ceil_div(b.m_pad * b.m_pad, 256), 256, 0, stream>>>(
-        w.cov, w.mom, G, m, b.m_pad, n_eff, w.bp);
+        cov, mom, G, m, b.m_pad, n_eff, w.bp);
     VL_LAUNCH_CHECK();
-    bwd_var_kernel<<<(unsigned)ceil_div(b.m_pad, 256), 256, 0, stream>>>(w.fwd.momx, G, m,
-                                                                        b.m_pad, n_eff, w.vx);
+    bwd_var_kernel<<<(unsigned)ceil_div(b.m_pad, 256), 256, 0, stream>>>(momx, G, m, b.m_pad,
+                                                                        n_eff, w.vx);
     VL_LAUNCH_CHECK();
   }
   {
@@ -365,7 +376,7 @@ int run_backward(const BwdPlan& b, const BwdWs& w, const float* E, int64_t lde, 
   {
     ProfileScope ps("backward_tail", stream);
     bwd_r_combine_kernel<<<(unsigned)ceil_div(b.m_pad * b.m_pad, 256), 256, 0, stream>>>(
-        w.Rp, b.nchunk, w.cov, m, b.m_pad, n_eff, w.Rf);
+        w.Rp, b.nchunk, cov, m, b.m_pad, n_eff, w.Rf);
     VL_LAUNCH_CHECK();
     dim3 grx((unsigned)ceil_div(b.n_pad, 64), (unsigned)ceil_div(b.m_pad, 64));
     bwd_rx_kernel<<<grx, 256, 0, stream>>>(w.Rf, w.Xs, b.m_pad, b.n_pad, w.dx);
@@ -373,7 +384,7 @@ int run_backward(const BwdPlan& b, const BwdWs& w, const float* E, int64_t lde, 
     bwd_colsum_kernel<<<(unsigned)m, 256, 0, stream>>>(w.dx, w.Xs, b.n_pad, n_eff, w.sums);
     VL_LAUNCH_CHECK();
     dim3 gs((unsigned)ceil_div(n_eff, 64), (unsigned)ceil_div(m, 64));
-    bwd_std_kernel<<<gs, 256, 0, stream>>>(w.dx, w.Xs, w.sums, w.cov, m, b.n_pad, n_eff, dE,
+    bwd_std_kernel<<<gs, 256, 0, stream>>>(w.dx, w.Xs, w.sums, cov, m, b.n_pad, n_eff, dE,
                                            ldde);
     VL_LAUNCH_CHECK();
   }

@@ -33,7 +33,10 @@ struct BwdWs {
 
 BwdPlan plan_backward(int64_t n_eff, int64_t m);
 size_t bwd_ws_bytes(const BwdPlan& b, void* base, BwdWs* out);
+// saved (nullable): the forward's statistics, [A,B per ordered pair (2 m^2) | A,B per
+// variable (2 m) | covariance (m^2) | means (m)]; NULL recomputes them.
 int run_backward(const BwdPlan& b, const BwdWs& w, const float* E, int64_t lde, int prec,
-                 const double* G, float* dE, int64_t ldde, int32_t* st, hipStream_t stream);
+                 const double* saved, const double* G, float* dE, int64_t ldde, int32_t* st,
+                 hipStream_t stream);
 
 }  // namespace vl

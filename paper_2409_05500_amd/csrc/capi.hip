@@ -93,9 +93,40 @@ size_t pairwise_stats_backward_workspace_bytes(int64_t n_eff, int64_t m, int pre
   return bwd_ws_bytes(plan_backward(n_eff, m), nullptr, nullptr);
 }
 
+size_t pairwise_stats_saved_doubles(int64_t m) {
+  if (m < 2 || m > 65536) return 0;
+  return (size_t)(3 * m * m + 3 * m);
+}
+
+int pairwise_stats_save(const float* E, int64_t n_eff, int64_t m, int64_t lde, int prec,
+                        double* Hx, double* Hr, double* S, double* Cov, double* saved, void* ws,
+                        size_t ws_bytes, int32_t* dev_status, void* stream) {
+  if (!E || !Hx || !Hr || !S || !saved || !dev_status || !valid_prec(prec))
+    return VL_ERR_INVALID_ARG;
+  if (m < 2 || n_eff < 2 || m > 65536) return VL_ERR_SHAPE;
+  if (lde < m) return VL_ERR_INVALID_ARG;
+  const PairwisePlan p = plan_pairwise(n_eff, m);
+  const size_t need = pairwise_ws_bytes(p, nullptr, nullptr);
+  if (!ws || ws_bytes < need || !aligned256(ws)) return VL_ERR_WORKSPACE;
+  PairwiseWs w;
+  pairwise_ws_bytes(p, ws, &w);
+  hipStream_t s = as_stream(stream);
+  int rc = begin(dev_status, s);
+  if (rc) return rc;
+  double* cov = saved + 2 * m * m + 2 * m;
+  rc = run_pairwise(p, w, E, lde, prec, Hx, Hr, S, cov, saved, dev_status, s);
+  if (rc) return rc;
+  const size_t d = sizeof(double);
+  if (hipMemcpyAsync(saved + 2 * m * m, w.momx, 2 * m * d, hipMemcpyDeviceToDevice, s) ||
+      hipMemcpyAsync(saved + 3 * m * m + 2 * m, w.mu, m * d, hipMemcpyDeviceToDevice, s) ||
+      (Cov && hipMemcpyAsync(Cov, cov, m * m * d, hipMemcpyDeviceToDevice, s)))
+    return VL_ERR_HIP;
+  return VL_OK;
+}
+
 int pairwise_stats_backward(const float* E, int64_t n_eff, int64_t m, int64_t lde, int prec,
-                            const double* G, float* dE, int64_t ldde, void* ws, size_t ws_bytes,
-                            int32_t* dev_status, void* stream) {
+                            const double* saved, const double* G, float* dE, int64_t ldde,
+                            void* ws, size_t ws_bytes, int32_t* dev_status, void* stream) {
   if (!E || !G || !dE || !dev_status || !valid_prec(prec)) return VL_ERR_INVALID_ARG;
   if (m < 2 || n_eff < 2 || m > 65536) return VL_ERR_SHAPE;
   if (lde < m || ldde < m) return VL_ERR_INVALID_ARG;
@@ -107,7 +138,7 @@ int pairwise_stats_backward(const float* E, int64_t n_eff, int64_t m, int64_t ld
   hipStream_t s = as_stream(stream);
   int rc = begin(dev_status, s);
   if (rc) return rc;
-  return run_backward(b, w, E, lde, prec, G, dE, ldde, dev_status, s);
+  return run_backward(b, w, E, lde, prec, saved, G, dE, ldde, dev_status, s);
 }
 
 // ----------------------------------------------------------------------------------------

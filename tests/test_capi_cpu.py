@@ -90,12 +90,23 @@ def test_host_validation_without_gpu(L):
     assert lib.approx_order(FAKE, 4, FAKE, FAKE, FAKE, 8, FAKE, None) == L.VL_ERR_WORKSPACE
     # backward: null cotangent, shape, leading dimension of dE, workspace
     bw = lib.pairwise_stats_backward
-    assert bw(FAKE, 100, 4, 4, 1, None, FAKE, 4, FAKE, 1 << 30, FAKE, None) == L.VL_ERR_INVALID_ARG
-    assert bw(FAKE, 100, 1, 4, 1, FAKE, FAKE, 4, FAKE, 1 << 30, FAKE, None) == L.VL_ERR_SHAPE
-    assert bw(FAKE, 1, 4, 4, 1, FAKE, FAKE, 4, FAKE, 1 << 30, FAKE, None) == L.VL_ERR_SHAPE
-    assert bw(FAKE, 100, 4, 4, 1, FAKE, FAKE, 3, FAKE, 1 << 30, FAKE, None) == L.VL_ERR_INVALID_ARG
-    assert bw(FAKE, 100, 4, 4, 2, FAKE, FAKE, 4, FAKE, 1 << 30, FAKE, None) == L.VL_ERR_INVALID_ARG
-    assert bw(FAKE, 100, 4, 4, 1, FAKE, FAKE, 4, FAKE, 64, FAKE, None) == L.VL_ERR_WORKSPACE
+    big = 1 << 30
+    assert bw(FAKE, 100, 4, 4, 1, None, None, FAKE, 4, FAKE, big, FAKE, None) == \
+        L.VL_ERR_INVALID_ARG
+    assert bw(FAKE, 100, 1, 4, 1, None, FAKE, FAKE, 4, FAKE, big, FAKE, None) == L.VL_ERR_SHAPE
+    assert bw(FAKE, 1, 4, 4, 1, FAKE, FAKE, FAKE, 4, FAKE, big, FAKE, None) == L.VL_ERR_SHAPE
+    assert bw(FAKE, 100, 4, 4, 1, None, FAKE, FAKE, 3, FAKE, big, FAKE, None) == \
+        L.VL_ERR_INVALID_ARG
+    assert bw(FAKE, 100, 4, 4, 2, None, FAKE, FAKE, 4, FAKE, big, FAKE, None) == \
+        L.VL_ERR_INVALID_ARG
+    assert bw(FAKE, 100, 4, 4, 1, None, FAKE, FAKE, 4, FAKE, 64, FAKE, None) == L.VL_ERR_WORKSPACE
+    sv = lib.pairwise_stats_save
+    assert lib.pairwise_stats_saved_doubles(400) == 3 * 400 * 400 + 3 * 400
+    assert lib.pairwise_stats_saved_doubles(1) == 0
+    assert sv(FAKE, 100, 4, 4, 1, FAKE, FAKE, FAKE, None, None, FAKE, big, FAKE, None) == \
+        L.VL_ERR_INVALID_ARG
+    assert sv(FAKE, 100, 4, 4, 1, FAKE, FAKE, FAKE, None, FAKE, FAKE, 16, FAKE, None) == \
+        L.VL_ERR_WORKSPACE
 
 
 def test_build_flags_disable_packed_fp32():

@@ -129,6 +129,19 @@ def test_backward_deterministic(api, dev):
     assert torch.equal(a, b)
 
 
+def test_backward_with_saved_statistics(api, dev):
+    """The saved block of the forward gives the same bits as the recompute, and the forward
+    that writes it returns the same statistics as pairwise_stats."""
+    E = _dev(_residuals(29, 2500, 6), dev)
+    G = _dev(np.random.default_rng(6).normal(size=(29, 29)), dev)
+    Hx, Hr, S, Cov, saved = api.pairwise_stats_save(E)
+    Hx0, Hr0, S0, Cov0 = api.pairwise_stats(E)
+    for a, b in ((Hx, Hx0), (Hr, Hr0), (S, S0), (Cov, Cov0)):
+        assert torch.equal(a, b)
+    assert torch.equal(api.pairwise_stats_backward(E, G, saved=saved),
+                       api.pairwise_stats_backward(E, G))
+
+
 def test_autograd_function(api, dev):
     m, n = 9, 900
     E32 = _residuals(m, n, 4)
@@ -154,7 +167,7 @@ def test_backward_strided_input_output(api, dev):
     nb = lib.pairwise_stats_backward_workspace_bytes(n, m, 1)
     ws = torch.empty(nb, dtype=torch.uint8, device=dev)
     st = torch.zeros(1, dtype=torch.int32, device=dev)
-    rc = lib.pairwise_stats_backward(big.data_ptr(), n, m, m + 5, 1, Gd.data_ptr(),
+    rc = lib.pairwise_stats_backward(big.data_ptr(), n, m, m + 5, 1, None, Gd.data_ptr(),
                                      out.data_ptr(), m + 3, ws.data_ptr(), nb, st.data_ptr(),
                                      torch.cuda.current_stream().cuda_stream)
     assert rc == 0
