@@ -262,6 +262,26 @@ def main():
         f32.run(X)
     fp32_s = time_steps(f32, X, args.steps, torch)
 
+    # the BF16-Gram form with FP64 refinement, its VAR stages, and its distance from MIXED
+    bf = api.Fitter(n, m, p, "bf16", dev)
+    for _ in range(args.warmup):
+        bf.run(X)
+    bf16_s = time_steps(bf, X, args.steps, torch)
+    bf.check()
+    _lib.profile_enable("*")
+    time_steps(bf, X, 3, torch)
+    bf16_stage_ms = {}
+    for st in ("var_gram", "var_solve", "var_refine", "var_residual"):
+        ms, cnt = _lib.profile_read(st)
+        if cnt:
+            bf16_stage_ms[st] = round(ms / cnt, 4)
+    _lib.profile_enable(None)
+
+    def b_rel(a, b):
+        return float((a - b).abs().max() / max(float(b.abs().max()), 1e-2))
+    bf16_dev = {"B0_rel": b_rel(bf.B0, fit.B0), "B_lags_rel": b_rel(bf.B_lags, fit.B_lags),
+                "same_order": bool(torch.equal(bf.order, fit.order))}
+
     achieved = TRANS_PER_EVAL * evals / k_s
     out = {
         "metric": METRIC,
@@ -287,6 +307,9 @@ def main():
         "sample_evals_per_step": evals,
         "fit_ms_mixed": step_s * 1e3,
         "fit_ms_fp32": fp32_s * 1e3,
+        "fit_ms_bf16": bf16_s * 1e3,
+        "bf16_stage_ms": bf16_stage_ms,
+        "bf16_vs_mixed": bf16_dev,
         "stage_ms": stage_ms,
     }
     if not args.no_batch:

@@ -51,8 +51,11 @@ typedef enum {
  *                  with FP32 sums; FP64 Cholesky of the FP32 Gram.
  *   VL_PREC_MIXED: the same three products by FP64 MFMA on the widened FP32 data (exact
  *                  products, FP64 sums); FP64 Cholesky.
- *   VL_PREC_BF16:  reserved (BF16 VAR Gram repaired by FP64 refinement); currently rejected with
- *                  VL_ERR_INVALID_ARG. */
+ *   VL_PREC_BF16:  VAR Gram matrices by BF16 MFMA (FP32 partial sums added in FP64), FP64
+ *                  Cholesky of that Gram, then three FP64 refinement steps (the residual and
+ *                  its correlation with the lags formed in FP64); residual GEMM and covariance
+ *                  as MIXED.  Meant for well-conditioned lag designs (cond(G) well below 256).
+ *                  The batched fit takes FP32 and MIXED only. */
 typedef enum { VL_PREC_FP32 = 0, VL_PREC_MIXED = 1, VL_PREC_BF16 = 2 } vl_precision;
 
 /* Human-readable name of a status code (static string, never NULL). */

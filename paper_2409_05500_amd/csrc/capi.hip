@@ -11,7 +11,9 @@ namespace {
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
-inline bool valid_prec(int prec) { return prec == VL_PREC_FP32 || prec == VL_PREC_MIXED; }
+inline bool valid_prec(int prec) {
+  return prec == VL_PREC_FP32 || prec == VL_PREC_MIXED || prec == VL_PREC_BF16;
+}
 
 inline bool aligned256(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
 

@@ -88,6 +88,17 @@ __global__ __launch_bounds__(256) void gram_tn_kernel(
                         1.0);
 }
 
+__global__ __launch_bounds__(256) void gram_tn_bf16_kernel(
+    const float* __restrict__ A, int64_t lda, const int64_t* __restrict__ mapA,
+    const double* __restrict__ muA, int64_t M, const float* __restrict__ B, int64_t ldb,
+    const int64_t* __restrict__ mapB, const double* __restrict__ muB, int64_t N, int64_t K,
+    int64_t kchunk, double* __restrict__ P) {
+  const int64_t kb = (int64_t)blockIdx.z * kchunk;
+  const int64_t ke = kb + kchunk < K ? kb + kchunk : K;
+  gram_tile_bf16(A, lda, mapA, muA, M, B, ldb, mapB, muB, N, (int64_t)blockIdx.y * kGT,
+                 (int64_t)blockIdx.x * kGT, kb, ke, P + (int64_t)blockIdx.z * M * N, N, 1.0);
+}
+
 __global__ __launch_bounds__(256) void gram_tn_f64_kernel(
     const float* __restrict__ A, int64_t lda, const int64_t* __restrict__ mapA,
     const double* __restrict__ muA, int64_t M, const float* __restrict__ B, int64_t ldb,
@@ -199,6 +210,9 @@ int gram_tn(const float* A, int64_t lda, const int64_t* mapA, const double* muA,
   if (mode == GramMode::kFp64)
     gram_tn_f64_kernel<<<grid, 256, 0, stream>>>(A, lda, mapA, muA, M, B, ldb, mapB, muB, N, K,
                                                  kchunk, scratch);
+  else if (mode == GramMode::kBf16)
+    gram_tn_bf16_kernel<<<grid, 256, 0, stream>>>(A, lda, mapA, muA, M, B, ldb, mapB, muB, N, K,
+                                                  kchunk, scratch);
   else if (mode == GramMode::kFp32Flush64)
     gram_tn_kernel<4><<<grid, 256, 0, stream>>>(A, lda, mapA, muA, M, B, ldb, mapB, muB, N, K,
                                                 kchunk, scratch);

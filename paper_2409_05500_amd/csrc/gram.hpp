@@ -28,8 +28,10 @@ inline int gram_splits(int64_t M, int64_t N, int64_t K) {
 // Arithmetic of gram_tn():
 //   kFp32        FP32 MFMA, FP32 accumulation over the whole split;
 //   kFp32Flush64 FP32 MFMA partial sums over 128-sample blocks accumulated in FP64;
-//   kFp64        FP64 MFMA on the widened FP32 inputs (exact products, FP64 sums).
-enum class GramMode { kFp32, kFp32Flush64, kFp64 };
+//   kFp64        FP64 MFMA on the widened FP32 inputs (exact products, FP64 sums);
+//   kBf16        BF16 MFMA on the centred inputs rounded to BF16 (relative error 2^-9 per
+//                input), FP32 partial sums added into FP64 every 128 samples.
+enum class GramMode { kFp32, kFp32Flush64, kFp64, kBf16 };
 
 // C[i*ldc + j] = scale * sum_{t<K} (A(t,i) - muA[i]) (B(t,j) - muB[j]),
 //   A(t,i) = A[mapA[i] + t*lda] (mapA == nullptr: mapA[i] = i); likewise B.

@@ -99,6 +99,90 @@ __device__ inline void gram_tile_f32(
 }
 
 // ------------------------------------------------------------------------------------------
+// BF16 variant (the low-precision Gram that iterative refinement repairs): the centred FP32
+// values staged in LDS are rounded to BF16 (nearest, ties to even) when read; the products of
+// two BF16 values are exact in FP32; v_mfma_f32_32x32x8bf16_1k (lane l holds A[l % 32][4 (l /
+// 32) + 0..3] and B[4 (l / 32) + 0..3][l % 32]; the output layout of the FP32 32x32 MFMA); FP32
+// partial sums added into FP64 every 4 stages (128 samples).
+// ------------------------------------------------------------------------------------------
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline short to_bf16(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+
+__device__ inline void gram_tile_bf16(
+    const float* __restrict__ A, int64_t lda, const int64_t* __restrict__ mapA,
+    const double* __restrict__ muA, int64_t M, const float* __restrict__ B, int64_t ldb,
+    const int64_t* __restrict__ mapB, const double* __restrict__ muB, int64_t N, int64_t i0,
+    int64_t j0, int64_t kb, int64_t ke, double* __restrict__ out, int64_t ldo, double scale) {
+  __shared__ float As[kGK * kGLd];
+  __shared__ float Bs[kGK * kGLd];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int cc = tid & 63, rg = tid >> 6;
+  const int64_t ia = i0 + cc, jb = j0 + cc;
+  const bool va = ia < M, vb = jb < N;
+  const float* pa = A + (va ? (mapA ? mapA[ia] : ia) : 0);
+  const float* pb = B + (vb ? (mapB ? mapB[jb] : jb) : 0);
+  const float ma = va ? (float)muA[ia] : 0.f;
+  const float mb = vb ? (float)muB[jb] : 0.f;
+  const int wi = wave >> 1, wj = wave & 1;
+  f32x16 acc = {};
+  double acc64[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc64[r] = 0.0;
+  float ra[kGK / 4], rb[kGK / 4];
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int r = 0; r < kGK / 4; ++r) {
+      const int64_t t = k0 + rg + 4 * r;
+      const bool in = t < ke;
+      ra[r] = (va && in) ? pa[t * lda] - ma : 0.f;
+      rb[r] = (vb && in) ? pb[t * ldb] - mb : 0.f;
+    }
+  };
+  load(kb);
+  int stage = 0;
+  for (int64_t k0 = kb; k0 < ke; k0 += kGK, ++stage) {
+#pragma unroll
+    for (int r = 0; r < kGK / 4; ++r) {
+      As[(rg + 4 * r) * kGLd + cc] = ra[r];
+      Bs[(rg + 4 * r) * kGLd + cc] = rb[r];
+    }
+    __syncthreads();
+    if (k0 + kGK < ke) load(k0 + kGK);
+#pragma unroll
+    for (int kk = 0; kk < kGK; kk += 8) {
+      s16x4 a, b;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = kk + 4 * (lane >> 5) + q;
+        a[q] = to_bf16(As[k * kGLd + wi * 32 + (lane & 31)]);
+        b[q] = to_bf16(Bs[k * kGLd + wj * 32 + (lane & 31)]);
+      }
+      acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+    }
+    __syncthreads();
+    if ((stage & 3) == 3) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        acc64[r] += (double)acc[r];
+        acc[r] = 0.f;
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    acc64[r] += (double)acc[r];
+    const int64_t i = i0 + wi * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    const int64_t j = j0 + wj * 32 + (lane & 31);
+    if (i < M && j < N) out[i * ldo + j] = scale * acc64[r];
+  }
+}
+
+// ------------------------------------------------------------------------------------------
 // FP64 variant: same tiling, v_mfma_f64_16x16x4f64.  FP32 inputs are widened when read from
 // LDS, so every product is exact and the sum is FP64 throughout.  Wave tile 32 x 32 = 2 x 2
 // blocks of 16 x 16; 16 samples per LDS stage.

@@ -9,8 +9,10 @@
 //   MIXED: Gram matrices by FP64 MFMA on the widened FP32 data (exact products, FP64 sums), FP64
 //          Cholesky solve, residual GEMM by FP64 MFMA, E rounded to FP32 once.
 //   FP32:  Gram and residual GEMM by FP32 MFMA with FP32 sums; FP64 Cholesky; no refinement.
-//   Low-precision Gram (BF16 mode): solve, then one refinement step Coef += G^{-1} Zc^T E64
-//          with the residual E64 and its correlation with Zc formed in FP64.
+//   BF16:  Gram matrices by BF16 MFMA (FP32 sums flushed to FP64), FP64 Cholesky of that Gram,
+//          then kBf16RefineSteps refinement steps Coef += G^{-1} Zc^T E64 with the residual
+//          E64 = Yc - Zc Coef and its correlation with Zc formed in FP64 (exact products of the
+//          FP32 data); each step shrinks the error by about cond(G) 2^-8.
 #include "gram.hpp"
 #include "linalg.hpp"
 #include "var_fit.hpp"
@@ -18,6 +20,9 @@
 #include "profile.hpp"
 
 namespace vl {
+
+// Refinement steps after the BF16 Gram solve (contraction ~cond(G) 2^-8 per step).
+constexpr int kBf16RefineSteps = 3;
 
 
 // colmap[tau*m + i] = (p - tau) * ldx + i  for tau = 0..p  (tau = 0 is Y, tau >= 1 is Z)
@@ -143,7 +148,7 @@ int run_var(const VarPlan& v, const VarWs& w, const float* X, int64_t ldx, int p
   const int64_t nc = m * (v.p + 1);
   const bool plain = prec == VL_PREC_FP32;
   const bool refine = prec == VL_PREC_BF16;
-  const GramMode gmode = plain ? GramMode::kFp32 : refine ? GramMode::kFp32Flush64 : GramMode::kFp64;
+  const GramMode gmode = plain ? GramMode::kFp32 : refine ? GramMode::kBf16 : GramMode::kFp64;
   const int64_t* mapZ = w.colmap + m;
   const double* muZ = w.mu + m;
   int rc;
@@ -172,30 +177,28 @@ int run_var(const VarPlan& v, const VarWs& w, const float* X, int64_t ldx, int p
     rc = trsm_lower(w.L, dz, dz, w.chol, true, w.Tmp, m, m, w.Coef, m, stream);
     if (rc) return rc;
   }
+  if (refine) {
+    ProfileScope ps("var_refine", stream);
+    for (int it = 0; it < kBf16RefineSteps; ++it) {
+      {
+        dim3 grid((unsigned)ceil_div(m, 64), (unsigned)ceil_div(n_eff, 64));
+        var_residual_f64_kernel<double><<<grid, 256, 0, stream>>>(X, ldx, w.colmap, w.mu, m, v.p,
+                                                                  n_eff, w.Coef, w.E64, m);
+        VL_LAUNCH_CHECK();
+      }
+      rc = gram_tn_f64b(X, ldx, mapZ, muZ, dz, w.E64, m, m, n_eff, w.Rres, m, w.scratch, stream);
+      if (rc) return rc;
+      rc = trsm_lower(w.L, dz, dz, w.chol, false, w.Rres, m, m, w.Tmp, m, stream);
+      if (rc) return rc;
+      rc = trsm_lower(w.L, dz, dz, w.chol, true, w.Tmp, m, m, w.Rres, m, stream);
+      if (rc) return rc;
+      add_f64_kernel<<<(unsigned)ceil_div(dz * m, 256), 256, 0, stream>>>(w.Coef, w.Rres, dz * m);
+      VL_LAUNCH_CHECK();
+    }
+  }
   {
     ProfileScope ps("var_residual", stream);
     rc = var_residual(v, w, X, ldx, E, lde, !plain, stream);
-    if (rc) return rc;
-  }
-  if (refine) {
-    ProfileScope ps("var_refine", stream);
-    // one refinement step: Coef += G^{-1} Zc^T E64 with the residual E64 = Yc - Zc Coef and
-    // its correlation with Zc both formed in FP64 (exact products of the FP32 data), then E
-    {
-      dim3 grid((unsigned)ceil_div(m, 64), (unsigned)ceil_div(n_eff, 64));
-      var_residual_f64_kernel<double><<<grid, 256, 0, stream>>>(X, ldx, w.colmap, w.mu, m, v.p,
-                                                                n_eff, w.Coef, w.E64, m);
-      VL_LAUNCH_CHECK();
-    }
-    rc = gram_tn_f64b(X, ldx, mapZ, muZ, dz, w.E64, m, m, n_eff, w.Rres, m, w.scratch, stream);
-    if (rc) return rc;
-    rc = trsm_lower(w.L, dz, dz, w.chol, false, w.Rres, m, m, w.Tmp, m, stream);
-    if (rc) return rc;
-    rc = trsm_lower(w.L, dz, dz, w.chol, true, w.Tmp, m, m, w.Rres, m, stream);
-    if (rc) return rc;
-    add_f64_kernel<<<(unsigned)ceil_div(dz * m, 256), 256, 0, stream>>>(w.Coef, w.Rres, dz * m);
-    VL_LAUNCH_CHECK();
-    rc = var_residual(v, w, X, ldx, E, lde, true, stream);
     if (rc) return rc;
   }
   var_lag_matrices_kernel<<<(unsigned)ceil_div(dz * m, 256), 256, 0, stream>>>(w.Coef, m, v.p, M);

@@ -97,7 +97,7 @@ def test_host_validation_without_gpu(L):
     assert bw(FAKE, 1, 4, 4, 1, FAKE, FAKE, FAKE, 4, FAKE, big, FAKE, None) == L.VL_ERR_SHAPE
     assert bw(FAKE, 100, 4, 4, 1, None, FAKE, FAKE, 3, FAKE, big, FAKE, None) == \
         L.VL_ERR_INVALID_ARG
-    assert bw(FAKE, 100, 4, 4, 2, None, FAKE, FAKE, 4, FAKE, big, FAKE, None) == \
+    assert bw(FAKE, 100, 4, 4, 7, None, FAKE, FAKE, 4, FAKE, big, FAKE, None) == \
         L.VL_ERR_INVALID_ARG
     assert bw(FAKE, 100, 4, 4, 1, None, FAKE, FAKE, 4, FAKE, 64, FAKE, None) == L.VL_ERR_WORKSPACE
     sv = lib.pairwise_stats_save

@@ -215,6 +215,20 @@ def test_var_fit_parity(api, dev, wl, seed):
     assert np.max(np.abs(E - oE)) <= 2.0 ** -23 * np.abs(oE).max() + 1e-7
 
 
+@pytest.mark.parametrize("wl,seed", [(synth.SMALL, 1), (synth.MEDIUM, 0), (synth.FINANCE, 0)])
+def test_var_fit_bf16_refined(api, dev, wl, seed):
+    """BF16 Gram matrices + FP64 refinement: after the refinement steps the coefficients are
+    those of the FP64 solve up to the step's contraction; bounded here by 1e-6 relative."""
+    inst = synth.make_instance(wl, seed)
+    oM, oc, oE = O.fit_var(inst.X_parity, wl.p)
+    M, c, E = [t.cpu().numpy() for t in api.fit_var(_dev(inst.X32, dev), wl.p, "bf16")]
+    eM = np.max(np.abs(M - oM)) / max(1.0, np.abs(oM).max())
+    eE = np.max(np.abs(E - oE)) / np.abs(oE).max()
+    print(f"bf16 var fit {wl.name}: M rel err {eM:.1e}, E rel err {eE:.1e}", flush=True)
+    assert eM <= 1e-6
+    assert eE <= 1e-6
+
+
 def test_var_fit_ragged(api, dev):
     for m, n, p in [(1, 50, 1), (3, 40, 3), (7, 500, 2), (70, 700, 1)]:
         inst = synth.make_custom(m, n, p, "laplace", m + n)
@@ -266,6 +280,20 @@ def test_fit_plain_fp32_accuracy(api, dev, wl):
     """Plain FP32 mode (FP32 MFMA sums, no refinement) against the oracle, at its own bound."""
     e0, e1 = _fit_and_compare(api, dev, synth.make_instance(wl, 0), 1, "fp32", PA.B_TOL_PLAIN)
     print(f"plain fp32 {wl.name}: B rel err {e0:.1e} {e1:.1e}", flush=True)
+
+
+@pytest.mark.parametrize("inst", [synth.make_instance(synth.SMALL, 0),
+                                  synth.make_instance(synth.SMALL, 2),
+                                  synth.make_instance(synth.MEDIUM, 0),
+                                  synth.make_custom(60, 3000, 2, "t4", 5, edge_prob=0.05,
+                                                    w_lo=0.05, w_hi=0.4, lag_radius=0.4)],
+                         ids=lambda i: i.workload.name)
+def test_fit_bf16_mode(api, dev, inst):
+    """BF16 precision mode end to end against the oracle at the BF16 tolerance (the last case
+    follows the two-lag heavy-tailed law at a size the oracle finishes in seconds)."""
+    p = inst.workload.p
+    e0, e1 = _fit_and_compare(api, dev, inst, p, "bf16", PA.B_TOL_BF16)
+    print(f"bf16 {inst.workload.name}: B rel err {e0:.1e} {e1:.1e}", flush=True)
 
 
 def test_fit_deterministic(api, dev):
