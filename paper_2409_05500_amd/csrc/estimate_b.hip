@@ -5,7 +5,8 @@
 // factorisation of the order-permuted covariance:  Sigma_KK = L D L^T with L unit lower-
 // triangular, and the regression coefficients are B0_KK = I - L^{-1} (row k holds the
 // coefficients of variable K_k on K_0 .. K_{k-1}).  With the Cholesky factor Lc = L D^{1/2},
-// L^{-1} = diag(Lc) Lc^{-1}.  Then B_tau = (I - B0) M_tau.
+// L^{-1} = diag(Lc) Lc^{-1}, and diag(Lc) = 1 / diag(Lc^{-1}): only Lc^{-1} is formed (by the
+// fused factorisation).  Then B_tau = (I - B0) M_tau.
 #include "estimate_b.hpp"
 #include "linalg.hpp"
 #include "profile.hpp"
@@ -39,21 +40,16 @@ __global__ void zero_i32_kernel(int32_t* __restrict__ a, int64_t n) {
   if (e < n) a[e] = 0;
 }
 
-__global__ void identity_kernel(double* __restrict__ a, int64_t m) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < m * m) a[e] = (e / m == e % m) ? 1.0 : 0.0;
-}
-
-// B0[K_a][K_b] = -Lc[a][a] * Linv[a][b] for b < a; 0 otherwise (zero diagonal).
-__global__ void assemble_b0_kernel(const double* __restrict__ Lc, const double* __restrict__ Linv,
-                                   const int32_t* __restrict__ K, int64_t m,
-                                   double* __restrict__ B0) {
+// B0[K_a][K_b] = -Linv[a][b] / Linv[a][a] for b < a (Lc[a][a] = 1 / Linv[a][a]); 0 otherwise
+// (zero diagonal).
+__global__ void assemble_b0_kernel(const double* __restrict__ Linv, const int32_t* __restrict__ K,
+                                   int64_t m, double* __restrict__ B0) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= m * m) return;
   const int64_t a = e / m, b = e % m;
   int32_t ka = K[a], kb = K[b];
   if (ka < 0 || ka >= m || kb < 0 || kb >= m) return;
-  B0[(int64_t)ka * m + kb] = b < a ? -Lc[a * m + a] * Linv[a * m + b] : 0.0;
+  B0[(int64_t)ka * m + kb] = b < a ? -Linv[a * m + b] / Linv[a * m + a] : 0.0;
 }
 
 __global__ void copy_f64_kernel(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
@@ -67,8 +63,6 @@ size_t b_ws_bytes(int64_t m, void* base, BWs* out) {
   w.P = c.take<double>(m * m);
   w.Linv = c.take<double>(m * m);
   w.seen = c.take<int32_t>(m);
-  w.Lc = c.take<double>(m * m);
-  w.Id = c.take<double>(m * m);
   w.chol = c.take<double>(chol_ws_doubles(m));
   if (out) *out = w;
   return c.used;
@@ -84,13 +78,9 @@ int run_estimate_b(const BWs& w, const double* Cov, const double* M, const int32
   VL_LAUNCH_CHECK();
   check_perm_kernel<<<(unsigned)ceil_div(m, 256), 256, 0, stream>>>(w.seen, m, st);
   VL_LAUNCH_CHECK();
-  int rc = potrf_lower(w.P, m, m, w.Lc, m, w.chol, st, stream);
+  int rc = chol_solve_lower(w.P, m, m, nullptr, 0, 0, w.Linv, m, w.chol, st, stream);
   if (rc) return rc;
-  identity_kernel<<<g, 256, 0, stream>>>(w.Id, m);
-  VL_LAUNCH_CHECK();
-  rc = trsm_lower(w.Lc, m, m, w.chol, false, w.Id, m, m, w.Linv, m, stream);
-  if (rc) return rc;
-  assemble_b0_kernel<<<g, 256, 0, stream>>>(w.Lc, w.Linv, K, m, B0);
+  assemble_b0_kernel<<<g, 256, 0, stream>>>(w.Linv, K, m, B0);
   VL_LAUNCH_CHECK();
   for (int tau = 0; tau < p; ++tau) {
     const double* Mt = M + (int64_t)tau * m * m;

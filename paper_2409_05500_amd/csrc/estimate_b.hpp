@@ -6,8 +6,6 @@ namespace vl {
 
 struct BWs {
   double* P = nullptr;     // m x m permuted covariance (destroyed by the factorisation)
-  double* Lc = nullptr;    // m x m Cholesky factor
-  double* Id = nullptr;    // m x m identity, consumed by the solve
   double* Linv = nullptr;  // m x m inverse of the factor
   int32_t* seen = nullptr; // m permutation counters
   double* chol = nullptr;  // factorisation scratch

@@ -1,7 +1,6 @@
-// FP64 dense linear algebra for the VAR normal equations and the B0 estimator:
-// blocked right-looking Cholesky whose 64 x 64 diagonal blocks are factored and inverted by one
-// wave each, triangular solves with many right-hand sides as GEMMs against those inverted
-// blocks, and a tiled FP64 GEMM.  Matrices are row-major with explicit leading dimensions.
+// FP64 dense linear algebra for the VAR normal equations and the B0 estimator: a blocked
+// right-looking Cholesky fused with the forward substitution (one launch per 64-wide panel),
+// and a tiled FP64 GEMM.  Matrices are row-major with explicit leading dimensions.
 #include "linalg.hpp"
 #include "linalg_dev.hpp"
 
@@ -9,105 +8,343 @@
 
 namespace vl {
 
-__global__ __launch_bounds__(256) void potf2_inv_kernel(const double* __restrict__ A, int64_t lda,
-                                                        int kb, const double* __restrict__ diag0,
-                                                        double* __restrict__ L, int64_t ldl,
-                                                        double* __restrict__ Linv, int32_t* st) {
-  potf2_inv_block(A, lda, kb, diag0, L, ldl, Linv, st);
-}
-
 __global__ __launch_bounds__(256) void gemm_f64_kernel(int64_t M, int64_t N, int64_t K,
                                                        double alpha, const double* __restrict__ A,
                                                        int64_t lda, int transA,
                                                        const double* __restrict__ Bm,
                                                        int64_t ldb, int transB, double beta,
                                                        double* __restrict__ C, int64_t ldc,
-                                                       int lower_only) {
+                                                       int lower_only, int tri) {
   gemm_f64_tile(M, N, K, alpha, A, lda, transA, Bm, ldb, transB, beta, C, ldc, lower_only,
-                (int64_t)blockIdx.y * 64, (int64_t)blockIdx.x * 64);
+                (int64_t)blockIdx.y * 64, (int64_t)blockIdx.x * 64, tri);
 }
 
 int gemm_f64(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
              bool transA, const double* B, int64_t ldb, bool transB, double beta, double* C,
-             int64_t ldc, bool lower_only, hipStream_t stream) {
+             int64_t ldc, bool lower_only, hipStream_t stream, int tri) {
   if (M <= 0 || N <= 0) return VL_OK;
   dim3 grid((unsigned)ceil_div(N, 64), (unsigned)ceil_div(M, 64));
   gemm_f64_kernel<<<grid, 256, 0, stream>>>(M, N, K, alpha, A, lda, transA ? 1 : 0, B, ldb,
-                                            transB ? 1 : 0, beta, C, ldc, lower_only ? 1 : 0);
+                                            transB ? 1 : 0, beta, C, ldc, lower_only ? 1 : 0,
+                                            tri);
   VL_LAUNCH_CHECK();
   return VL_OK;
 }
 
-__global__ void diag_copy_kernel(const double* __restrict__ A, int64_t n, int64_t lda,
-                                 double* __restrict__ d) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) d[i] = A[i * lda + i];
-}
+// ------------------------------------------------------------------------------------------
+// Fused blocked Cholesky + forward substitution.  Panel width 64; nb = ceil(n / 64) block rows.
+// Per block k the workspace keeps Y_k = L_kk^{-1} and W_k = Y_k^T Y_k = (A_kk^{(k)})^{-1}, the
+// inverse of the diagonal block after the updates of panels < k.  Right-looking step k applies
+// panel k everywhere at once, each workgroup recomputing the panel product it needs:
+//   trailing tile (i, j), k < j <= i:   A_ij -= (A_ik W_k) A_jk^T      (= L_ik L_jk^T)
+//   right-hand tile (i, c), i > k:      R_ic -= (A_ik W_k) R_kc         (= L_ik (L^{-1} R)_kc)
+// and the workgroup of tile (k+1, k+1) goes on to factor and invert it (Y_{k+1}, W_{k+1}), so
+// one launch per panel covers the factorisation and the substitution.  Block row k of the
+// right-hand sides is final after step k - 1; step k + 1 (or the last step) scales it in place:
+//   (L^{-1} R)_kc = Y_k R_kc.
+// L^{-1} itself is the substitution applied to R = I, whose column tile c stays zero above
+// block row c (those tiles are skipped).
+// ------------------------------------------------------------------------------------------
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-size_t chol_ws_doubles(int64_t n) { return (size_t)n + (size_t)ceil_div(n, kNb) * kNb * kNb; }
+constexpr int kTL = kLd;  // LDS tile leading dimension (65: rows land on different banks)
 
-int potrf_lower(double* A, int64_t n, int64_t lda, double* L, int64_t ldl, double* ws,
-                int32_t* st, hipStream_t stream) {
-  double* diag0 = ws;
-  double* inv = ws + n;
-  diag_copy_kernel<<<(unsigned)ceil_div(n, 256), 256, 0, stream>>>(A, n, lda, diag0);
-  VL_LAUNCH_CHECK();
-  for (int64_t k0 = 0; k0 < n; k0 += kNb) {
-    const int kb = (int)(n - k0 < kNb ? n - k0 : kNb);
-    double* invk = inv + (k0 / kNb) * kNb * kNb;
-    potf2_inv_kernel<<<1, 256, 0, stream>>>(A + k0 * lda + k0, lda, kb, diag0 + k0,
-                                            L + k0 * ldl + k0, ldl, invk, st);
-    VL_LAUNCH_CHECK();
-    const int64_t rest = n - k0 - kb;
-    if (rest <= 0) break;
-    // L21 = A21 L11^{-T}
-    int rc = gemm_f64(rest, kb, kb, 1.0, A + (k0 + kb) * lda + k0, lda, false, invk, kNb, true,
-                      0.0, L + (k0 + kb) * ldl + k0, ldl, false, stream);
-    if (rc) return rc;
-    // A22 -= L21 L21^T (lower triangle)
-    rc = gemm_f64(rest, rest, kb, -1.0, L + (k0 + kb) * ldl + k0, ldl, false,
-                  L + (k0 + kb) * ldl + k0, ldl, true, 1.0, A + (k0 + kb) * lda + (k0 + kb), lda,
-                  true, stream);
-    if (rc) return rc;
+// D[r][c] = src[r * ld + c] for r < rows, c < cols; 0 elsewhere
+__device__ inline void tile_load(double (*D)[kTL], const double* __restrict__ src, int64_t ld,
+                                 int rows, int cols) {
+#pragma unroll 4
+  for (int e = threadIdx.x; e < kNb * kNb; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    D[r][c] = (r < rows && c < cols) ? src[(int64_t)r * ld + c] : 0.0;
   }
-  return VL_OK;
 }
 
-int trsm_lower(const double* L, int64_t n, int64_t ldl, const double* ws, bool trans, double* B,
-               int64_t nrhs, int64_t ldb, double* X, int64_t ldx, hipStream_t stream) {
-  const double* inv = ws + n;
-  const int64_t nblk = ceil_div(n, kNb);
-  if (!trans) {
-    for (int64_t b = 0; b < nblk; ++b) {
-      const int64_t k0 = b * kNb;
-      const int kb = (int)(n - k0 < kNb ? n - k0 : kNb);
-      // X_k = L_kk^{-1} B_k
-      int rc = gemm_f64(kb, nrhs, kb, 1.0, inv + b * kNb * kNb, kNb, false, B + k0 * ldb, ldb,
-                        false, 0.0, X + k0 * ldx, ldx, false, stream);
-      if (rc) return rc;
-      const int64_t rest = n - k0 - kb;
-      if (rest > 0) {
-        // B_rest -= L_rest,k X_k
-        rc = gemm_f64(rest, nrhs, kb, -1.0, L + (k0 + kb) * ldl + k0, ldl, false, X + k0 * ldx,
-                      ldx, false, 1.0, B + (k0 + kb) * ldb, ldb, false, stream);
-        if (rc) return rc;
-      }
+// acc += op(P) op(Q) over 64 terms, P and Q 64 x 64 tiles in LDS (op = transpose when kTP /
+// kTQ).  Wave w owns rows 32 (w >> 1) .. +31 and columns 32 (w & 1) .. +31 as 2 x 2 blocks of
+// v_mfma_f64_16x16x4f64: A operand lane l -> (row l % 16, k l / 16), B operand -> (k l / 16,
+// column l % 16), result register r -> (row l / 16 + 4 r, column l % 16).
+template <bool kTP, bool kTQ>
+__device__ inline void mm64(const double (*P)[kTL], const double (*Q)[kTL], f64x4 (&acc)[2][2]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wi = w >> 1, wj = w & 1, lr = lane & 15, lk = lane >> 4;
+#pragma unroll 4
+  for (int kk = 0; kk < kNb; kk += 4) {
+    double a[2], b[2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      const int row = wi * 32 + x * 16 + lr, col = wj * 32 + x * 16 + lr;
+      a[x] = kTP ? P[kk + lk][row] : P[row][kk + lk];
+      b[x] = kTQ ? Q[col][kk + lk] : Q[kk + lk][col];
     }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+        acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+  }
+}
+
+__device__ inline void acc_zero(f64x4 (&acc)[2][2]) {
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = f64x4{0.0, 0.0, 0.0, 0.0};
+}
+
+// f(row, col, value) for every result element this thread holds
+template <class F>
+__device__ inline void acc_each(const f64x4 (&acc)[2][2], F f) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wi = w >> 1, wj = w & 1;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        f(wi * 32 + x * 16 + (lane >> 4) + 4 * r, wj * 32 + y * 16 + (lane & 15), acc[x][y][r]);
+}
+
+struct CholArgs {
+  double* A;
+  int64_t n, lda;
+  double* R;          // right-hand sides (n x nrhs) or null
+  int64_t nrhs, ldr;
+  double* Li;         // L^{-1} (n x n) or null
+  int64_t ldli;
+  double* diag0;      // n: diagonal before elimination (pivot test)
+  double* Yb;         // nb x 64 x 64: Y_k
+  double* Wb;         // nb x 64 x 64: W_k
+  int32_t* st;
+};
+
+__host__ __device__ inline int64_t blk_rows(int64_t n, int64_t b) {
+  return n - b * kNb < kNb ? n - b * kNb : kNb;
+}
+
+// Work items of step k, in launch order: trailing tiles (the critical tile (k+1, k+1) first),
+// right-hand updates, L^{-1} updates, then the in-place scalings of block rows k - 1 and (last
+// step) k for the right-hand sides and for L^{-1}.
+struct StepItems {
+  int64_t trail, upd_r, upd_i, fin_r, fin_i;
+  __host__ __device__ int64_t total() const { return trail + upd_r + upd_i + fin_r + fin_i; }
+};
+
+__host__ __device__ inline StepItems step_items(int64_t nb, int64_t k, int64_t cr, bool li) {
+  StepItems s;
+  const int64_t t = nb - 1 - k;
+  s.trail = t * (t + 1) / 2;
+  s.upd_r = t * cr;
+  s.upd_i = li ? t * (k + 1) : 0;
+  const int64_t nfin = (k >= 1 ? 1 : 0) + (k == nb - 1 ? 1 : 0);
+  s.fin_r = nfin * cr;
+  s.fin_i = li ? (k >= 1 ? k : 0) + (k == nb - 1 ? k + 1 : 0) : 0;
+  return s;
+}
+
+// The critical tile's epilogue: S = the updated diagonal block (identity-padded) is factored;
+// Y_b and W_b = Y_b^T Y_b go to the workspace.
+__device__ inline void factor_diag_store(double (*S)[kTL], double (*Y)[kTL], double* buf,
+                                         double* D0, const CholArgs& a, int64_t b) {
+  const int64_t kb = blk_rows(a.n, b);
+  if (threadIdx.x < kNb) D0[threadIdx.x] = threadIdx.x < kb ? a.diag0[b * kNb + threadIdx.x] : 1.0;
+  block_factor_inv(S, Y, buf, D0, a.st);
+  double* Yo = a.Yb + b * kNb * kNb;
+  for (int e = threadIdx.x; e < kNb * kNb; e += 256) {
+    const int r = e >> 6, q = e & 63;
+    Yo[e] = q <= r ? Y[r][q] : 0.0;
+  }
+  f64x4 acc[2][2];
+  acc_zero(acc);
+  mm64<true, false>(Y, Y, acc);      // Y has exact zeros above the diagonal
+  double* Wo = a.Wb + b * kNb * kNb;
+  acc_each(acc, [&](int r, int c, double v) { Wo[r * kNb + c] = v; });
+}
+
+__global__ __launch_bounds__(256) void chol_prologue_kernel(CholArgs a) {
+  __shared__ double S[kNb][kTL];
+  __shared__ double Y[kNb][kTL];
+  __shared__ double buf[kFactorBuf];
+  __shared__ double D0[kNb];
+  if (blockIdx.x > 0) {
+    // L^{-1} starts as the identity (the substitution works on it in place)
+    const int64_t e = (int64_t)(blockIdx.x - 1) * 256 + threadIdx.x;
+    if (a.Li && e < a.n * a.n) {
+      const int64_t r = e / a.n, c = e % a.n;
+      a.Li[r * a.ldli + c] = r == c ? 1.0 : 0.0;
+    }
+    return;
+  }
+  for (int64_t i = threadIdx.x; i < a.n; i += 256) a.diag0[i] = a.A[i * a.lda + i];
+  const int kb = (int)blk_rows(a.n, 0);
+  for (int e = threadIdx.x; e < kNb * kNb; e += 256) {
+    const int r = e >> 6, q = e & 63;
+    S[r][q] = (r < kb && q < kb) ? a.A[(int64_t)r * a.lda + q] : (r == q ? 1.0 : 0.0);
+  }
+  if (threadIdx.x < kNb) D0[threadIdx.x] = threadIdx.x < kb ? a.A[threadIdx.x * (a.lda + 1)] : 1.0;
+  block_factor_inv(S, Y, buf, D0, a.st);
+  double* Yo = a.Yb;
+  for (int e = threadIdx.x; e < kNb * kNb; e += 256) {
+    const int r = e >> 6, q = e & 63;
+    Yo[e] = q <= r ? Y[r][q] : 0.0;
+  }
+  f64x4 acc[2][2];
+  acc_zero(acc);
+  mm64<true, false>(Y, Y, acc);
+  acc_each(acc, [&](int r, int c, double v) { a.Wb[r * kNb + c] = v; });
+}
+
+__global__ __launch_bounds__(256) void chol_step_kernel(CholArgs a, int64_t k) {
+  __shared__ double X[kNb][kTL];
+  __shared__ double Z[kNb][kTL];
+  __shared__ double buf[kFactorBuf];
+  __shared__ double D0[kNb];
+  const int64_t nb = ceil_div(a.n, (int64_t)kNb);
+  const int64_t cr = a.R ? ceil_div(a.nrhs, (int64_t)kNb) : 0;
+  const StepItems s = step_items(nb, k, cr, a.Li != nullptr);
+  int64_t e = blockIdx.x;
+  const int64_t t = nb - 1 - k;
+  const double* Ak = a.A + k * kNb;                 // column block k of A
+  const double* Wk = a.Wb + k * kNb * kNb;
+  f64x4 acc[2][2];
+  if (e < s.trail + s.upd_r + s.upd_i) {
+    // row block i of the panel product P = A_ik W_k, into X
+    int64_t i, j = -1, c = -1;
+    bool inv_side = false;
+    if (e < s.trail) {
+      int64_t ii = (int64_t)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
+      while (ii * (ii + 1) / 2 > e) --ii;
+      while ((ii + 1) * (ii + 2) / 2 <= e) ++ii;
+      i = k + 1 + ii;
+      j = k + 1 + (e - ii * (ii + 1) / 2);
+    } else if (e < s.trail + s.upd_r) {
+      e -= s.trail;
+      i = k + 1 + e / cr;
+      c = e % cr;
+    } else {
+      e -= s.trail + s.upd_r;
+      i = k + 1 + e / (k + 1);
+      c = e % (k + 1);
+      inv_side = true;
+    }
+    (void)t;
+    const int64_t ri = blk_rows(a.n, i);
+    tile_load(X, Ak + i * kNb * a.lda, a.lda, (int)ri, kNb);
+    tile_load(Z, Wk, kNb, kNb, kNb);
+    __syncthreads();
+    acc_zero(acc);
+    mm64<false, false>(X, Z, acc);
+    __syncthreads();
+    acc_each(acc, [&](int r, int q, double v) { X[r][q] = v; });
+    // second operand into Z: A_jk (trailing) or the right-hand tile of block row k
+    double* out;
+    int64_t ldo, cols;
+    if (j >= 0) {
+      tile_load(Z, Ak + j * kNb * a.lda, a.lda, (int)blk_rows(a.n, j), kNb);
+      out = a.A + i * kNb * a.lda + j * kNb;
+      ldo = a.lda;
+      cols = blk_rows(a.n, j);
+    } else if (!inv_side) {
+      cols = a.nrhs - c * kNb < kNb ? a.nrhs - c * kNb : kNb;
+      tile_load(Z, a.R + k * kNb * a.ldr + c * kNb, a.ldr, kNb, (int)cols);
+      out = a.R + i * kNb * a.ldr + c * kNb;
+      ldo = a.ldr;
+    } else {
+      cols = blk_rows(a.n, c);
+      tile_load(Z, a.Li + k * kNb * a.ldli + c * kNb, a.ldli, kNb, (int)cols);
+      out = a.Li + i * kNb * a.ldli + c * kNb;
+      ldo = a.ldli;
+    }
+    __syncthreads();
+    acc_zero(acc);
+    if (j >= 0) mm64<false, true>(X, Z, acc);
+    else mm64<false, false>(X, Z, acc);
+    if (j == k + 1 && i == k + 1) {
+      // the critical tile: updated block into X (identity-padded), then factor and invert
+      __syncthreads();
+      acc_each(acc, [&](int r, int q, double v) {
+        X[r][q] = (r < ri && q < ri) ? out[(int64_t)r * ldo + q] - v : (r == q ? 1.0 : 0.0);
+      });
+      factor_diag_store(X, Z, buf, D0, a, k + 1);
+      return;
+    }
+    acc_each(acc, [&](int r, int q, double v) {
+      if (r < ri && q < cols) out[(int64_t)r * ldo + q] -= v;
+    });
+    return;
+  }
+  // in-place scaling of a finished block row f: tile <- Y_f tile
+  e -= s.trail + s.upd_r + s.upd_i;
+  int64_t f, c;
+  bool inv_side;
+  if (e < s.fin_r) {
+    const int64_t first = k >= 1 ? cr : 0;         // items of block row k - 1 come first
+    f = e < first ? k - 1 : k;
+    c = e < first ? e : e - first;
+    inv_side = false;
   } else {
-    for (int64_t b = nblk - 1; b >= 0; --b) {
-      const int64_t k0 = b * kNb;
-      const int kb = (int)(n - k0 < kNb ? n - k0 : kNb);
-      // X_k = L_kk^{-T} B_k
-      int rc = gemm_f64(kb, nrhs, kb, 1.0, inv + b * kNb * kNb, kNb, true, B + k0 * ldb, ldb,
-                        false, 0.0, X + k0 * ldx, ldx, false, stream);
-      if (rc) return rc;
-      if (k0 > 0) {
-        // B_0:k -= L_k,0:k^T X_k
-        rc = gemm_f64(k0, nrhs, kb, -1.0, L + k0 * ldl, ldl, true, X + k0 * ldx, ldx, false, 1.0,
-                      B, ldb, false, stream);
-        if (rc) return rc;
-      }
+    e -= s.fin_r;
+    if (k >= 1 && e < k) {
+      f = k - 1;
+      c = e;
+    } else {
+      f = k;
+      c = e - (k >= 1 ? k : 0);
     }
+    inv_side = true;
+  }
+  double* tile;
+  int64_t ld, cols;
+  if (!inv_side) {
+    tile = a.R + f * kNb * a.ldr + c * kNb;
+    ld = a.ldr;
+    cols = a.nrhs - c * kNb < kNb ? a.nrhs - c * kNb : kNb;
+  } else {
+    tile = a.Li + f * kNb * a.ldli + c * kNb;
+    ld = a.ldli;
+    cols = blk_rows(a.n, c);
+  }
+  const int64_t rf = blk_rows(a.n, f);
+  tile_load(X, a.Yb + f * kNb * kNb, kNb, kNb, kNb);
+  tile_load(Z, tile, ld, (int)rf, (int)cols);
+  __syncthreads();
+  acc_zero(acc);
+  mm64<false, false>(X, Z, acc);
+  acc_each(acc, [&](int r, int q, double v) {
+    if (r < rf && q < cols) tile[(int64_t)r * ld + q] = v;
+  });
+}
+
+size_t chol_ws_doubles(int64_t n) {
+  return (size_t)n + 2 * (size_t)ceil_div(n, (int64_t)kNb) * kNb * kNb;
+}
+
+int chol_solve_lower(double* A, int64_t n, int64_t lda, double* R, int64_t nrhs, int64_t ldr,
+                     double* Linv, int64_t ldli, double* ws, int32_t* st, hipStream_t stream) {
+  if (n <= 0) return VL_OK;
+  const int64_t nb = ceil_div(n, (int64_t)kNb);
+  CholArgs a;
+  a.A = A;
+  a.n = n;
+  a.lda = lda;
+  a.R = nrhs > 0 ? R : nullptr;
+  a.nrhs = nrhs;
+  a.ldr = ldr;
+  a.Li = Linv;
+  a.ldli = ldli;
+  a.diag0 = ws;
+  a.Yb = ws + n;
+  a.Wb = ws + n + nb * kNb * kNb;
+  a.st = st;
+  const int64_t cr = a.R ? ceil_div(nrhs, (int64_t)kNb) : 0;
+  const unsigned init = Linv ? (unsigned)ceil_div(n * n, (int64_t)256) : 0u;
+  chol_prologue_kernel<<<1 + init, 256, 0, stream>>>(a);
+  VL_LAUNCH_CHECK();
+  for (int64_t k = 0; k < nb; ++k) {
+    const int64_t items = step_items(nb, k, cr, Linv != nullptr).total();
+    if (items == 0) continue;
+    chol_step_kernel<<<(unsigned)items, 256, 0, stream>>>(a, k);
+    VL_LAUNCH_CHECK();
   }
   return VL_OK;
 }

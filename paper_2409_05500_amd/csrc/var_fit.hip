@@ -164,17 +164,17 @@ int run_var(const VarPlan& v, const VarWs& w, const float* X, int64_t ldx, int p
     rc = gram_tn(X, ldx, mapZ, muZ, dz, X, ldx, mapZ, muZ, dz, n_eff, gmode, 1.0, w.G, dz,
                  w.scratch, stream);
     if (rc) return rc;
-    rc = gram_tn(X, ldx, mapZ, muZ, dz, X, ldx, w.colmap, w.mu, m, n_eff, gmode, 1.0, w.Coef, m,
+    rc = gram_tn(X, ldx, mapZ, muZ, dz, X, ldx, w.colmap, w.mu, m, n_eff, gmode, 1.0, w.Tmp, m,
                  w.scratch, stream);
     if (rc) return rc;
   }
   {
+    // G = L L^T with Tmp <- L^{-1} R and Linv = L^{-1} in the same pass; Coef = L^{-T} Tmp
     ProfileScope ps("var_solve", stream);
-    rc = potrf_lower(w.G, dz, dz, w.L, dz, w.chol, st, stream);
+    rc = chol_solve_lower(w.G, dz, dz, w.Tmp, m, m, w.L, dz, w.chol, st, stream);
     if (rc) return rc;
-    rc = trsm_lower(w.L, dz, dz, w.chol, false, w.Coef, m, m, w.Tmp, m, stream);
-    if (rc) return rc;
-    rc = trsm_lower(w.L, dz, dz, w.chol, true, w.Tmp, m, m, w.Coef, m, stream);
+    rc = gemm_f64(dz, m, dz, 1.0, w.L, dz, true, w.Tmp, m, false, 0.0, w.Coef, m, false, stream,
+                  2);
     if (rc) return rc;
   }
   if (refine) {
@@ -188,12 +188,13 @@ int run_var(const VarPlan& v, const VarWs& w, const float* X, int64_t ldx, int p
       }
       rc = gram_tn_f64b(X, ldx, mapZ, muZ, dz, w.E64, m, m, n_eff, w.Rres, m, w.scratch, stream);
       if (rc) return rc;
-      rc = trsm_lower(w.L, dz, dz, w.chol, false, w.Rres, m, m, w.Tmp, m, stream);
+      // Coef += L^{-T} L^{-1} Rres (two triangular products with the explicit inverse)
+      rc = gemm_f64(dz, m, dz, 1.0, w.L, dz, false, w.Rres, m, false, 0.0, w.Tmp, m, false,
+                    stream, 1);
       if (rc) return rc;
-      rc = trsm_lower(w.L, dz, dz, w.chol, true, w.Tmp, m, m, w.Rres, m, stream);
+      rc = gemm_f64(dz, m, dz, 1.0, w.L, dz, true, w.Tmp, m, false, 1.0, w.Coef, m, false,
+                    stream, 2);
       if (rc) return rc;
-      add_f64_kernel<<<(unsigned)ceil_div(dz * m, 256), 256, 0, stream>>>(w.Coef, w.Rres, dz * m);
-      VL_LAUNCH_CHECK();
     }
   }
   {

@@ -17,7 +17,7 @@ struct VarWs {
   double* Coef = nullptr;     // dz x m solution
   double* Rres = nullptr;     // dz x m refinement right-hand side
   float* CoefF = nullptr;     // dz x m float copy for the residual GEMM
-  double* L = nullptr;        // dz x dz Cholesky factor of G
+  double* L = nullptr;        // dz x dz inverse of the Cholesky factor of G
   double* Tmp = nullptr;      // dz x m intermediate of the two triangular solves
   double* chol = nullptr;     // factorisation scratch kept for the solves
   double* E64 = nullptr;      // n_eff x m FP64 residual of the refinement step
