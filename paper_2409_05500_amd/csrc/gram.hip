@@ -73,41 +73,60 @@ int colmeans(const float* A, int64_t lda, const int64_t* colmap, int64_t ncol, i
 
 // ------------------------------------------------------------------------------------------
 // Centred TN Gram, split-K: blockIdx.z covers rows [z*kchunk, (z+1)*kchunk); each split writes
-// its FP64 partial tile to P[z] (M x N, ld N).
+// its FP64 partial tile to P[z] (M x N, ld N).  With sym (A and B the same operand), blockIdx.x
+// enumerates the tiles on and below the diagonal only.
 // ------------------------------------------------------------------------------------------
+__device__ inline void gram_tile_origin(int sym, int64_t& i0, int64_t& j0) {
+  if (!sym) {
+    i0 = (int64_t)blockIdx.y * kGT;
+    j0 = (int64_t)blockIdx.x * kGT;
+    return;
+  }
+  const int64_t e = blockIdx.x;
+  int64_t ti = (int64_t)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
+  while (ti * (ti + 1) / 2 > e) --ti;
+  while ((ti + 1) * (ti + 2) / 2 <= e) ++ti;
+  i0 = ti * kGT;
+  j0 = (e - ti * (ti + 1) / 2) * kGT;
+}
 template <int kFlush>
 __global__ __launch_bounds__(256) void gram_tn_kernel(
     const float* __restrict__ A, int64_t lda, const int64_t* __restrict__ mapA,
     const double* __restrict__ muA, int64_t M, const float* __restrict__ B, int64_t ldb,
     const int64_t* __restrict__ mapB, const double* __restrict__ muB, int64_t N, int64_t K,
-    int64_t kchunk, double* __restrict__ P) {
+    int64_t kchunk, double* __restrict__ P, int sym) {
   const int64_t kb = (int64_t)blockIdx.z * kchunk;
   const int64_t ke = kb + kchunk < K ? kb + kchunk : K;
-  gram_tile_f32<kFlush>(A, lda, mapA, muA, M, B, ldb, mapB, muB, N, (int64_t)blockIdx.y * kGT,
-                        (int64_t)blockIdx.x * kGT, kb, ke, P + (int64_t)blockIdx.z * M * N, N,
-                        1.0);
+  int64_t i0, j0;
+  gram_tile_origin(sym, i0, j0);
+  gram_tile_f32<kFlush>(A, lda, mapA, muA, M, B, ldb, mapB, muB, N, i0, j0, kb, ke,
+                        P + (int64_t)blockIdx.z * M * N, N, 1.0);
 }
 
 __global__ __launch_bounds__(256) void gram_tn_bf16_kernel(
     const float* __restrict__ A, int64_t lda, const int64_t* __restrict__ mapA,
     const double* __restrict__ muA, int64_t M, const float* __restrict__ B, int64_t ldb,
     const int64_t* __restrict__ mapB, const double* __restrict__ muB, int64_t N, int64_t K,
-    int64_t kchunk, double* __restrict__ P) {
+    int64_t kchunk, double* __restrict__ P, int sym) {
   const int64_t kb = (int64_t)blockIdx.z * kchunk;
   const int64_t ke = kb + kchunk < K ? kb + kchunk : K;
-  gram_tile_bf16(A, lda, mapA, muA, M, B, ldb, mapB, muB, N, (int64_t)blockIdx.y * kGT,
-                 (int64_t)blockIdx.x * kGT, kb, ke, P + (int64_t)blockIdx.z * M * N, N, 1.0);
+  int64_t i0, j0;
+  gram_tile_origin(sym, i0, j0);
+  gram_tile_bf16(A, lda, mapA, muA, M, B, ldb, mapB, muB, N, i0, j0, kb, ke,
+                 P + (int64_t)blockIdx.z * M * N, N, 1.0);
 }
 
 __global__ __launch_bounds__(256) void gram_tn_f64_kernel(
     const float* __restrict__ A, int64_t lda, const int64_t* __restrict__ mapA,
     const double* __restrict__ muA, int64_t M, const float* __restrict__ B, int64_t ldb,
     const int64_t* __restrict__ mapB, const double* __restrict__ muB, int64_t N, int64_t K,
-    int64_t kchunk, double* __restrict__ P) {
+    int64_t kchunk, double* __restrict__ P, int sym) {
   const int64_t kb = (int64_t)blockIdx.z * kchunk;
   const int64_t ke = kb + kchunk < K ? kb + kchunk : K;
-  gram_tile_f64(A, lda, mapA, muA, M, B, ldb, mapB, muB, N, (int64_t)blockIdx.y * kGT,
-                (int64_t)blockIdx.x * kGT, kb, ke, P + (int64_t)blockIdx.z * M * N, N, 1.0);
+  int64_t i0, j0;
+  gram_tile_origin(sym, i0, j0);
+  gram_tile_f64(A, lda, mapA, muA, M, B, ldb, mapB, muB, N, i0, j0, kb, ke,
+                P + (int64_t)blockIdx.z * M * N, N, 1.0);
 }
 
 // C[i][j] = sum_t (A(t,i) - muA[i]) B64[t][j] with an FP64 right operand (not centred): the
@@ -200,29 +219,50 @@ __global__ void sum_splits_kernel(const double* __restrict__ P, int splits, int6
   C[(e / N) * ldc + (e % N)] = s * scale;
 }
 
+// Symmetric form: entries (i, j) with i >= j of the lower tiles are summed and written to both
+// (i, j) and (j, i), so C is exactly symmetric.
+__global__ void sum_splits_sym_kernel(const double* __restrict__ P, int splits, int64_t M,
+                                      double scale, double* __restrict__ C, int64_t ldc) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * M) return;
+  const int64_t i = e / M, j = e % M;
+  if (j > i) return;
+  double s = 0.0;
+  for (int z = 0; z < splits; ++z) s += P[(int64_t)z * M * M + e];
+  C[i * ldc + j] = s * scale;
+  C[j * ldc + i] = s * scale;
+}
+
 int gram_tn(const float* A, int64_t lda, const int64_t* mapA, const double* muA, int64_t M,
             const float* B, int64_t ldb, const int64_t* mapB, const double* muB, int64_t N,
             int64_t K, GramMode mode, double scale, double* C, int64_t ldc, double* scratch,
-            hipStream_t stream) {
+            hipStream_t stream, bool sym) {
   const int splits = gram_splits(M, N, K);
   const int64_t kchunk = round_up(ceil_div(K, splits), kGK);
-  dim3 grid((unsigned)ceil_div(N, kGT), (unsigned)ceil_div(M, kGT), (unsigned)splits);
+  const int64_t tm = ceil_div(M, kGT), tn = ceil_div(N, kGT);
+  dim3 grid(sym ? (unsigned)(tm * (tm + 1) / 2) : (unsigned)tn, sym ? 1u : (unsigned)tm,
+            (unsigned)splits);
+  const int sy = sym ? 1 : 0;
   if (mode == GramMode::kFp64)
     gram_tn_f64_kernel<<<grid, 256, 0, stream>>>(A, lda, mapA, muA, M, B, ldb, mapB, muB, N, K,
-                                                 kchunk, scratch);
+                                                 kchunk, scratch, sy);
   else if (mode == GramMode::kBf16)
     gram_tn_bf16_kernel<<<grid, 256, 0, stream>>>(A, lda, mapA, muA, M, B, ldb, mapB, muB, N, K,
-                                                  kchunk, scratch);
+                                                  kchunk, scratch, sy);
   else if (mode == GramMode::kFp32Flush64)
     gram_tn_kernel<4><<<grid, 256, 0, stream>>>(A, lda, mapA, muA, M, B, ldb, mapB, muB, N, K,
-                                                kchunk, scratch);
+                                                kchunk, scratch, sy);
   else
     gram_tn_kernel<0><<<grid, 256, 0, stream>>>(A, lda, mapA, muA, M, B, ldb, mapB, muB, N, K,
-                                                kchunk, scratch);
+                                                kchunk, scratch, sy);
   VL_LAUNCH_CHECK();
   const int64_t tot = M * N;
-  sum_splits_kernel<<<(unsigned)ceil_div(tot, 256), 256, 0, stream>>>(scratch, splits, M, N,
-                                                                     scale, C, ldc);
+  if (sym)
+    sum_splits_sym_kernel<<<(unsigned)ceil_div(tot, 256), 256, 0, stream>>>(scratch, splits, M,
+                                                                            scale, C, ldc);
+  else
+    sum_splits_kernel<<<(unsigned)ceil_div(tot, 256), 256, 0, stream>>>(scratch, splits, M, N,
+                                                                       scale, C, ldc);
   VL_LAUNCH_CHECK();
   return VL_OK;
 }

@@ -35,10 +35,12 @@ enum class GramMode { kFp32, kFp32Flush64, kFp64, kBf16 };
 
 // C[i*ldc + j] = scale * sum_{t<K} (A(t,i) - muA[i]) (B(t,j) - muB[j]),
 //   A(t,i) = A[mapA[i] + t*lda] (mapA == nullptr: mapA[i] = i); likewise B.
+// sym: B is the same operand as A (M == N): only the tiles on and below the diagonal are
+// computed, and C comes out exactly symmetric.
 int gram_tn(const float* A, int64_t lda, const int64_t* mapA, const double* muA, int64_t M,
             const float* B, int64_t ldb, const int64_t* mapB, const double* muB, int64_t N,
             int64_t K, GramMode mode, double scale, double* C, int64_t ldc, double* scratch,
-            hipStream_t stream);
+            hipStream_t stream, bool sym = false);
 
 // C[i*ldc + j] = sum_{t<K} (A(t,i) - muA[i]) B[t*ldb + j] with an FP64, uncentred B (FP64 MFMA).
 int gram_tn_f64b(const float* A, int64_t lda, const int64_t* mapA, const double* muA, int64_t M,

@@ -138,7 +138,7 @@ int run_pairwise(const PairwisePlan& p, const PairwiseWs& w, const float* E, int
     // covariance: exact products and FP64 sums (plain FP32 mode: FP32 MFMA throughout)
     rc = gram_tn(E, lde, nullptr, w.mu, m, E, lde, nullptr, w.mu, m, n_eff,
                  prec == VL_PREC_FP32 ? GramMode::kFp32 : GramMode::kFp64, 1.0 / (double)n_eff,
-                 cov, m, w.scratch, stream);
+                 cov, m, w.scratch, stream, true);
     if (rc) return rc;
   }
   {

@@ -141,4 +141,110 @@ __device__ inline void var_residual_tile_f64(
       }
 }
 
+// ------------------------------------------------------------------------------------------
+// Wide FP64 residual tile: 128 samples x 64 variables per workgroup; wave (wi, wj) of the 2 x 2
+// waves owns 64 x 32 = 4 x 2 blocks of v_mfma_f64_16x16x4f64.  Stages of 32 lags through LDS
+// (the centred lag values widened to FP64 once, at load); the next stage's global loads are in
+// flight during the products.  Same arithmetic and result as var_residual_tile_f64.
+// ------------------------------------------------------------------------------------------
+// v if keep, else +0.0, by masking the bits.  The mask is made opaque to the optimiser (an
+// empty asm statement on the mask, which no load feeds): otherwise it proves the masked value
+// dead and branches around the load that produces it, with a wait per load.
+__device__ __attribute__((always_inline)) inline double mask_f64(double v, bool keep) {
+  unsigned long long mk = 0ull - (unsigned long long)keep;
+  asm volatile("" : "+v"(mk));
+  return __longlong_as_double((long long)((unsigned long long)__double_as_longlong(v) & mk));
+}
+
+constexpr int kRT = 128;       // samples per tile
+constexpr int kRJ = 64;        // variables per tile
+constexpr int kRK = 32;        // lags per stage
+constexpr int kRZ = kRT + 1;   // LDS row strides (doubles)
+constexpr int kRC = kRJ + 1;
+
+template <class TOut>
+__device__ inline void var_residual_tile_f64w(
+    const float* __restrict__ X, int64_t ldx, const int64_t* __restrict__ colmap,
+    const double* __restrict__ mu, int64_t m, int p, int64_t n_eff,
+    const double* __restrict__ Coef, TOut* __restrict__ E, int64_t lde, int64_t t0, int64_t j0) {
+  __shared__ double Zs[kRK][kRZ];
+  __shared__ double Cs[kRK][kRC];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wi = wave >> 1, wj = wave & 1, li = lane & 15, lk = lane >> 4;
+  const int64_t dz = m * p;
+  const int64_t* mapZ = colmap + m;
+  const double* muZ = mu + m;
+  f64x4 acc[4][2];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const int zk = tid & 31, zt = tid >> 5;      // Z loader: 32 lags x 8 sample rows per pass
+  const int cj = tid & 63, ck = tid >> 6;      // Coef loader: 64 variables x 4 lags per pass
+  double rz[kRT / 8], rc[kRK / 4];
+  // Every load reads a clamped in-bounds address and the padding is selected afterwards, so
+  // the loads of a stage issue back to back (no branch, no wait per load).
+  const int64_t jc = j0 + cj < m ? j0 + cj : m - 1;
+  const bool vj = j0 + cj < m;
+  auto load = [&](int64_t k0) {
+    const int64_t k = k0 + zk;
+    const bool vk = k < dz;
+    const int64_t off = mapZ[vk ? k : dz - 1];
+    const double mz = vk ? muZ[k] : 0.0;
+    float xv[kRT / 8];
+#pragma unroll
+    for (int u = 0; u < kRT / 8; ++u) {
+      const int64_t t = t0 + zt + 8 * u;
+      xv[u] = X[off + (t < n_eff ? t : n_eff - 1) * ldx];
+    }
+#pragma unroll
+    for (int u = 0; u < kRK / 4; ++u) {
+      const int64_t kq = k0 + ck + 4 * u;
+      const double cv = Coef[(kq < dz ? kq : dz - 1) * m + jc];
+      rc[u] = mask_f64(cv, kq < dz && vj);
+    }
+#pragma unroll
+    for (int u = 0; u < kRT / 8; ++u) {
+      const int64_t t = t0 + zt + 8 * u;
+      rz[u] = mask_f64((double)xv[u] - mz, vk && t < n_eff);
+    }
+  };
+  load(0);
+  for (int64_t k0 = 0; k0 < dz; k0 += kRK) {
+#pragma unroll
+    for (int u = 0; u < kRT / 8; ++u) Zs[zk][zt + 8 * u] = rz[u];
+#pragma unroll
+    for (int u = 0; u < kRK / 4; ++u) Cs[ck + 4 * u][cj] = rc[u];
+    __syncthreads();
+    if (k0 + kRK < dz) load(k0 + kRK);
+#pragma unroll
+    for (int kk = 0; kk < kRK; kk += 4) {
+      double a[4], b[2];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) a[x] = Zs[kk + lk][wi * 64 + x * 16 + li];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) b[y] = Cs[kk + lk][wj * 32 + y * 16 + li];
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t t = t0 + wi * 64 + x * 16 + lk + 4 * r;     // f64 D layout
+        const int64_t j = j0 + wj * 32 + y * 16 + li;
+        if (t < n_eff && j < m) {
+          const double yv = (double)X[colmap[j] + t * ldx] - mu[j];
+          E[t * lde + j] = (TOut)(yv - acc[x][y][r]);
+        }
+      }
+}
+
 }  // namespace vl

@@ -65,6 +65,15 @@ __global__ __launch_bounds__(256) void var_residual_f64_kernel(
                               (int64_t)blockIdx.y * 64, (int64_t)blockIdx.x * 64);
 }
 
+template <class TOut>
+__global__ __launch_bounds__(256) void var_residual_f64w_kernel(
+    const float* __restrict__ X, int64_t ldx, const int64_t* __restrict__ colmap,
+    const double* __restrict__ mu, int64_t m, int p, int64_t n_eff,
+    const double* __restrict__ Coef, TOut* __restrict__ E, int64_t lde) {
+  var_residual_tile_f64w<TOut>(X, ldx, colmap, mu, m, p, n_eff, Coef, E, lde,
+                               (int64_t)blockIdx.y * kRT, (int64_t)blockIdx.x * kRJ);
+}
+
 // M[(tau-1) m m + i m + k] = Coef[(tau-1) m + k][i]
 __global__ void var_lag_matrices_kernel(const double* __restrict__ Coef, int64_t m, int p,
                                         double* __restrict__ M) {
@@ -126,9 +135,9 @@ size_t var_ws_bytes(const VarPlan& v, void* base, VarWs* out) {
 static int var_residual(const VarPlan& v, const VarWs& w, const float* X, int64_t ldx, float* E,
                         int64_t lde, bool fp64, hipStream_t stream) {
   if (fp64) {
-    dim3 grid((unsigned)ceil_div(v.m, 64), (unsigned)ceil_div(v.n_eff, 64));
-    var_residual_f64_kernel<float><<<grid, 256, 0, stream>>>(X, ldx, w.colmap, w.mu, v.m, v.p,
-                                                             v.n_eff, w.Coef, E, lde);
+    dim3 grid((unsigned)ceil_div(v.m, (int64_t)kRJ), (unsigned)ceil_div(v.n_eff, (int64_t)kRT));
+    var_residual_f64w_kernel<float><<<grid, 256, 0, stream>>>(X, ldx, w.colmap, w.mu, v.m, v.p,
+                                                              v.n_eff, w.Coef, E, lde);
     VL_LAUNCH_CHECK();
     return VL_OK;
   }
@@ -162,7 +171,7 @@ int run_var(const VarPlan& v, const VarWs& w, const float* X, int64_t ldx, int p
     if (rc) return rc;
     // G = Zc^T Zc, R = Zc^T Yc (R goes straight into Coef, solved in place)
     rc = gram_tn(X, ldx, mapZ, muZ, dz, X, ldx, mapZ, muZ, dz, n_eff, gmode, 1.0, w.G, dz,
-                 w.scratch, stream);
+                 w.scratch, stream, true);
     if (rc) return rc;
     rc = gram_tn(X, ldx, mapZ, muZ, dz, X, ldx, w.colmap, w.mu, m, n_eff, gmode, 1.0, w.Tmp, m,
                  w.scratch, stream);
@@ -181,9 +190,9 @@ int run_var(const VarPlan& v, const VarWs& w, const float* X, int64_t ldx, int p
     ProfileScope ps("var_refine", stream);
     for (int it = 0; it < kBf16RefineSteps; ++it) {
       {
-        dim3 grid((unsigned)ceil_div(m, 64), (unsigned)ceil_div(n_eff, 64));
-        var_residual_f64_kernel<double><<<grid, 256, 0, stream>>>(X, ldx, w.colmap, w.mu, m, v.p,
-                                                                  n_eff, w.Coef, w.E64, m);
+        dim3 grid((unsigned)ceil_div(m, (int64_t)kRJ), (unsigned)ceil_div(n_eff, (int64_t)kRT));
+        var_residual_f64w_kernel<double><<<grid, 256, 0, stream>>>(X, ldx, w.colmap, w.mu, m,
+                                                                   v.p, n_eff, w.Coef, w.E64, m);
         VL_LAUNCH_CHECK();
       }
       rc = gram_tn_f64b(X, ldx, mapZ, muZ, dz, w.E64, m, m, n_eff, w.Rres, m, w.scratch, stream);
