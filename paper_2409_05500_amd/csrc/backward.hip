@@ -220,16 +220,22 @@ __global__ __launch_bounds__(256) void bwd_rx_kernel(const float* __restrict__ R
   for (int64_t k0 = 0; k0 < m_pad; k0 += 32) {
     {
       const int kk = tid & 31, ii = tid >> 5;     // 32 j x 8 i per pass
-#pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        const int64_t i = i0 + ii + 8 * r, j = k0 + kk;
-        Rs[kk][ii + 8 * r] = (i < m_pad && j < m_pad) ? Rf[i * m_pad + j] : 0.f;
-      }
+      // clamped in-bounds addresses, padding masked after the loads (no branch per load)
+      float rv[8], xv[8];
       const int tt = tid & 63, kr = tid >> 6;
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
-        const int64_t j = k0 + kr + 4 * r, t = t0 + tt;
-        Xl[kr + 4 * r][tt] = (j < m_pad && t < n_pad) ? Xs[j * n_pad + t] : 0.f;
+        const int64_t i = i0 + ii + 8 * r, j = k0 + kk;
+        rv[r] = Rf[(i < m_pad ? i : m_pad - 1) * m_pad + (j < m_pad ? j : m_pad - 1)];
+        const int64_t j2 = k0 + kr + 4 * r, t = t0 + tt;
+        xv[r] = Xs[(j2 < m_pad ? j2 : m_pad - 1) * n_pad + (t < n_pad ? t : n_pad - 1)];
+      }
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int64_t i = i0 + ii + 8 * r, j = k0 + kk;
+        Rs[kk][ii + 8 * r] = mask_f32(rv[r], i < m_pad && j < m_pad);
+        const int64_t j2 = k0 + kr + 4 * r, t = t0 + tt;
+        Xl[kr + 4 * r][tt] = mask_f32(xv[r], j2 < m_pad && t < n_pad);
       }
     }
     __syncthreads();

@@ -132,4 +132,19 @@ __device__ inline float wave_reduce_scatter64(float (&v)[64]) {
   return v[0];
 }
 
+// v if keep, else +0.0, by masking the bits.  The mask is made opaque to the optimiser (an
+// empty asm statement on the mask, which no load feeds): otherwise it proves the masked value
+// dead and branches around the load that produces it, with a wait per load.
+__device__ __attribute__((always_inline)) inline double mask_f64(double v, bool keep) {
+  unsigned long long mk = 0ull - (unsigned long long)keep;
+  asm volatile("" : "+v"(mk));
+  return __longlong_as_double((long long)((unsigned long long)__double_as_longlong(v) & mk));
+}
+
+__device__ __attribute__((always_inline)) inline float mask_f32(float v, bool keep) {
+  unsigned mk = 0u - (unsigned)keep;
+  asm volatile("" : "+v"(mk));
+  return __uint_as_float(__float_as_uint(v) & mk);
+}
+
 }  // namespace vl

@@ -165,6 +165,7 @@ __global__ __launch_bounds__(256) void gram_tn_f64b_kernel(
     for (int r = 0; r < kGK64 / 4; ++r) {
       const int64_t t = k0 + rg + 4 * r;
       const bool in = t < ke;
+      // a plain conditional load (no arithmetic on the value here, so no wait per load)
       ra[r] = (va && in) ? pa[t * lda] : 0.f;
       rb[r] = (vb && in) ? pb[t * ldb] : 0.0;
     }

@@ -54,8 +54,9 @@ __device__ inline void gram_tile_f32(
     for (int r = 0; r < kGK / 4; ++r) {
       const int64_t t = k0 + rg + 4 * r;
       const bool in = t < ke;
-      ra[r] = (va && in) ? pa[t * lda] - ma : 0.f;
-      rb[r] = (vb && in) ? pb[t * ldb] - mb : 0.f;
+      const int64_t tc = in ? t : ke - 1;         // clamped, in bounds; padding masked below
+      ra[r] = mask_f32(pa[tc * lda] - ma, va && in);
+      rb[r] = mask_f32(pb[tc * ldb] - mb, vb && in);
     }
   };
   load(kb);
@@ -139,8 +140,9 @@ __device__ inline void gram_tile_bf16(
     for (int r = 0; r < kGK / 4; ++r) {
       const int64_t t = k0 + rg + 4 * r;
       const bool in = t < ke;
-      ra[r] = (va && in) ? pa[t * lda] - ma : 0.f;
-      rb[r] = (vb && in) ? pb[t * ldb] - mb : 0.f;
+      const int64_t tc = in ? t : ke - 1;         // clamped, in bounds; padding masked below
+      ra[r] = mask_f32(pa[tc * lda] - ma, va && in);
+      rb[r] = mask_f32(pb[tc * ldb] - mb, vb && in);
     }
   };
   load(kb);
@@ -226,6 +228,7 @@ __device__ inline void gram_tile_f64(
     for (int r = 0; r < kGK64 / 4; ++r) {
       const int64_t t = k0 + rg + 4 * r;
       const bool in = t < ke;
+      // a plain conditional load (no arithmetic on the value here, so no wait per load)
       ra[r] = (va && in) ? pa[t * lda] : 0.f;
       rb[r] = (vb && in) ? pb[t * ldb] : 0.f;
     }

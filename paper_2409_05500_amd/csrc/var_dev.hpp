@@ -29,18 +29,31 @@ __device__ inline void var_residual_tile_f32(
       const int kk = tid & 31, tt = tid >> 5;
       const int64_t k = k0 + kk;
       const bool vk = k < dz;
-      const int64_t off = vk ? mapZ[k] : 0;
+      // clamped in-bounds addresses, padding masked after the loads (no branch per load)
+      const int64_t off = mapZ[vk ? k : dz - 1];
       const float mz = vk ? (float)muZ[k] : 0.f;
+      float xv[8], cv[8];
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
         const int64_t t = t0 + tt + 8 * r;
-        Zs[kk][tt + 8 * r] = (vk && t < n_eff) ? X[off + t * ldx] - mz : 0.f;
+        xv[r] = X[off + (t < n_eff ? t : n_eff - 1) * ldx];
       }
       const int jj = tid & 63, kr = tid >> 6;
+      const int64_t jc = j0 + jj < m ? j0 + jj : m - 1;
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
-        const int64_t kq = k0 + kr + 4 * r, j = j0 + jj;
-        Cs[kr + 4 * r][jj] = (kq < dz && j < m) ? CoefF[kq * m + j] : 0.f;
+        const int64_t kq = k0 + kr + 4 * r;
+        cv[r] = CoefF[(kq < dz ? kq : dz - 1) * m + jc];
+      }
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int64_t t = t0 + tt + 8 * r;
+        Zs[kk][tt + 8 * r] = mask_f32(xv[r] - mz, vk && t < n_eff);
+      }
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int64_t kq = k0 + kr + 4 * r;
+        Cs[kr + 4 * r][jj] = mask_f32(cv[r], kq < dz && j0 + jj < m);
       }
     }
     __syncthreads();
@@ -91,14 +104,22 @@ __device__ inline void var_residual_tile_f64(
   auto load = [&](int64_t k0) {
     const int64_t k = k0 + lk;
     const bool vk = k < dz;
-    const int64_t off = vk ? mapZ[k] : 0;
+    const int64_t off = mapZ[vk ? k : dz - 1];
     const double mz = vk ? muZ[k] : 0.0;
+    const int64_t j = j0 + cj, jc = j < m ? j : m - 1;
+    float xv[4];
+    double cv[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int64_t t = t0 + lt + 16 * r;
-      rz[r] = (vk && t < n_eff) ? (double)X[off + t * ldx] - mz : 0.0;
-      const int64_t kq = k0 + ck + 4 * r, j = j0 + cj;
-      rcf[r] = (kq < dz && j < m) ? Coef[kq * m + j] : 0.0;
+      const int64_t t = t0 + lt + 16 * r, kq = k0 + ck + 4 * r;
+      xv[r] = X[off + (t < n_eff ? t : n_eff - 1) * ldx];
+      cv[r] = Coef[(kq < dz ? kq : dz - 1) * m + jc];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t t = t0 + lt + 16 * r, kq = k0 + ck + 4 * r;
+      rz[r] = mask_f64((double)xv[r] - mz, vk && t < n_eff);
+      rcf[r] = mask_f64(cv[r], kq < dz && j < m);
     }
   };
   load(0);
@@ -147,15 +168,6 @@ __device__ inline void var_residual_tile_f64(
 // (the centred lag values widened to FP64 once, at load); the next stage's global loads are in
 // flight during the products.  Same arithmetic and result as var_residual_tile_f64.
 // ------------------------------------------------------------------------------------------
-// v if keep, else +0.0, by masking the bits.  The mask is made opaque to the optimiser (an
-// empty asm statement on the mask, which no load feeds): otherwise it proves the masked value
-// dead and branches around the load that produces it, with a wait per load.
-__device__ __attribute__((always_inline)) inline double mask_f64(double v, bool keep) {
-  unsigned long long mk = 0ull - (unsigned long long)keep;
-  asm volatile("" : "+v"(mk));
-  return __longlong_as_double((long long)((unsigned long long)__double_as_longlong(v) & mk));
-}
-
 constexpr int kRT = 128;       // samples per tile
 constexpr int kRJ = 64;        // variables per tile
 constexpr int kRK = 32;        // lags per stage
