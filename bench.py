@@ -33,8 +33,8 @@ TRANS_PER_EVAL = 3
 # exactly: x1).  Keyed by the SHA-256 of the kernel sources the counters were taken with
 # (kernel_source_digest); any other source reports null.
 MEASURED_TRAFFIC = {
-    # FETCH_SIZE 35146.8 KiB x 2, WRITE_SIZE 8492.7 KiB x 1 per dispatch (9 dispatches)
-    "4194558e3915907216da564fa6da429987fdebf0bf28efe67eb5695970b463be": 80677120,
+    # FETCH_SIZE 34933.4 KiB x 2, WRITE_SIZE 8510.7 KiB x 1 per dispatch (15 dispatches)
+    "159500c59dc7e228286794dec56690d9643c3532ac34256ae6ddd31b7d10ba7b": 80258560,
 }
 STAGES = ("var_gram", "var_solve", "var_residual", "var_refine", "pairwise_cov",
           "pairwise_prep", "pairwise_moments", "pairwise_combine", "order", "estimate_b")

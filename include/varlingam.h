@@ -54,8 +54,10 @@ typedef enum {
  *   VL_PREC_BF16:  VAR Gram matrices by BF16 MFMA (FP32 partial sums added in FP64), FP64
  *                  Cholesky of that Gram, then three FP64 refinement steps (the residual and
  *                  its correlation with the lags formed in FP64); residual GEMM and covariance
- *                  as MIXED.  Meant for well-conditioned lag designs (cond(G) well below 256).
- *                  The batched fit takes FP32 and MIXED only. */
+ *                  as MIXED.  Meant for well-conditioned lag designs: when the last
+ *                  refinement step still changes the coefficients by more than 1e-6 of their
+ *                  largest magnitude, the fit raises VL_ERR_SINGULAR.  The batched fit takes
+ *                  FP32 and MIXED only. */
 typedef enum { VL_PREC_FP32 = 0, VL_PREC_MIXED = 1, VL_PREC_BF16 = 2 } vl_precision;
 
 /* Human-readable name of a status code (static string, never NULL). */

@@ -12,7 +12,9 @@
 //   BF16:  Gram matrices by BF16 MFMA (FP32 sums flushed to FP64), FP64 Cholesky of that Gram,
 //          then kBf16RefineSteps refinement steps Coef += G^{-1} Zc^T E64 with the residual
 //          E64 = Yc - Zc Coef and its correlation with Zc formed in FP64 (exact products of the
-//          FP32 data); each step shrinks the error by about cond(G) 2^-8.
+//          FP32 data); each step shrinks the error by about cond(G) times the BF16 Gram's
+//          relative error.  A last correction above 1e-6 of max|Coef| (no convergence: the
+//          design is too ill-conditioned for a BF16 Gram) raises VL_ERR_SINGULAR.
 #include "gram.hpp"
 #include "linalg.hpp"
 #include "var_fit.hpp"
@@ -48,21 +50,43 @@ __global__ void add_f64_kernel(double* __restrict__ a, const double* __restrict_
   if (e < n) a[e] += d[e];
 }
 
+// Convergence of the BF16-mode refinement: the last correction d must be below
+// kRefineTol * max|c| (and finite), else the design is too ill-conditioned for a BF16 Gram and
+// VL_ERR_SINGULAR is raised.  One workgroup.
+constexpr double kRefineTol = 1e-6;
+
+__global__ __launch_bounds__(256) void refine_check_kernel(const double* __restrict__ d,
+                                                           const double* __restrict__ c,
+                                                           int64_t n, int32_t* st) {
+  __shared__ double sd[256], sc[256];
+  double md = 0.0, mc = 0.0;
+  bool bad = false;
+  for (int64_t e = threadIdx.x; e < n; e += 256) {
+    const double dv = d[e], cv = c[e];
+    bad |= !isfinite(dv) || !isfinite(cv);
+    md = fmax(md, fabs(dv));
+    mc = fmax(mc, fabs(cv));
+  }
+  sd[threadIdx.x] = md;
+  sc[threadIdx.x] = mc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      sd[threadIdx.x] = fmax(sd[threadIdx.x], sd[threadIdx.x + h]);
+      sc[threadIdx.x] = fmax(sc[threadIdx.x], sc[threadIdx.x + h]);
+    }
+    __syncthreads();
+  }
+  if (bad) raise_status(st, VL_ERR_SINGULAR);
+  if (threadIdx.x == 0 && !(sd[0] <= kRefineTol * sc[0])) raise_status(st, VL_ERR_SINGULAR);
+}
+
 __global__ __launch_bounds__(256) void var_residual_kernel(
     const float* __restrict__ X, int64_t ldx, const int64_t* __restrict__ colmap,
     const double* __restrict__ mu, int64_t m, int p, int64_t n_eff,
     const float* __restrict__ CoefF, float* __restrict__ E, int64_t lde) {
   var_residual_tile_f32(X, ldx, colmap, mu, m, p, n_eff, CoefF, E, lde,
                         (int64_t)blockIdx.y * 64, (int64_t)blockIdx.x * 64);
-}
-
-template <class TOut>
-__global__ __launch_bounds__(256) void var_residual_f64_kernel(
-    const float* __restrict__ X, int64_t ldx, const int64_t* __restrict__ colmap,
-    const double* __restrict__ mu, int64_t m, int p, int64_t n_eff,
-    const double* __restrict__ Coef, TOut* __restrict__ E, int64_t lde) {
-  var_residual_tile_f64<TOut>(X, ldx, colmap, mu, m, p, n_eff, Coef, E, lde,
-                              (int64_t)blockIdx.y * 64, (int64_t)blockIdx.x * 64);
 }
 
 template <class TOut>
@@ -197,14 +221,18 @@ int run_var(const VarPlan& v, const VarWs& w, const float* X, int64_t ldx, int p
       }
       rc = gram_tn_f64b(X, ldx, mapZ, muZ, dz, w.E64, m, m, n_eff, w.Rres, m, w.scratch, stream);
       if (rc) return rc;
-      // Coef += L^{-T} L^{-1} Rres (two triangular products with the explicit inverse)
+      // correction L^{-T} L^{-1} Rres (two triangular products with the explicit inverse)
       rc = gemm_f64(dz, m, dz, 1.0, w.L, dz, false, w.Rres, m, false, 0.0, w.Tmp, m, false,
                     stream, 1);
       if (rc) return rc;
-      rc = gemm_f64(dz, m, dz, 1.0, w.L, dz, true, w.Tmp, m, false, 1.0, w.Coef, m, false,
+      rc = gemm_f64(dz, m, dz, 1.0, w.L, dz, true, w.Tmp, m, false, 0.0, w.Rres, m, false,
                     stream, 2);
       if (rc) return rc;
+      add_f64_kernel<<<(unsigned)ceil_div(dz * m, 256), 256, 0, stream>>>(w.Coef, w.Rres, dz * m);
+      VL_LAUNCH_CHECK();
     }
+    refine_check_kernel<<<1, 256, 0, stream>>>(w.Rres, w.Coef, dz * m, st);
+    VL_LAUNCH_CHECK();
   }
   {
     ProfileScope ps("var_residual", stream);

@@ -229,6 +229,23 @@ def test_var_fit_bf16_refined(api, dev, wl, seed):
     assert eE <= 1e-6
 
 
+def test_var_fit_bf16_ill_conditioned_raises_or_converges(api, dev):
+    """A strongly correlated design (m=70, n=700, edge probability 0.3): the BF16 Gram either
+    converges under refinement to the FP64 coefficients or the fit reports VL_ERR_SINGULAR;
+    it never returns unconverged coefficients silently."""
+    from paper_2409_05500_amd._lib import VarLiNGAMError
+    inst = synth.make_custom(70, 700, 1, "laplace", 70 + 700)
+    oM, _, _ = O.fit_var(inst.X_parity, 1)
+    try:
+        M, _, _ = [t.cpu().numpy() for t in api.fit_var(_dev(inst.X32, dev), 1, "bf16")]
+    except VarLiNGAMError as err:
+        print(f"bf16 on the ill-conditioned design: {err}", flush=True)
+        return
+    eM = np.max(np.abs(M - oM)) / max(1.0, np.abs(oM).max())
+    print(f"bf16 on the ill-conditioned design converged: M rel err {eM:.1e}", flush=True)
+    assert eM <= 1e-6
+
+
 def test_var_fit_ragged(api, dev):
     for m, n, p in [(1, 50, 1), (3, 40, 3), (7, 500, 2), (70, 700, 1)]:
         inst = synth.make_custom(m, n, p, "laplace", m + n)
