@@ -8,6 +8,16 @@
 
 namespace vl {
 
+// ------------------------------------------------------------------------------------------
+// FP64 GEMM on MFMA: C = beta C + alpha op(A) op(B).  A workgroup owns a 32 x 32 block of C (2 x 2
+// v_mfma_f64_16x16x4f64 blocks); its four waves split the K range in four and add their partial
+// products through LDS in a fixed order.  Operands are read straight from global memory (the
+// callers' matrices are a few MB and stay in cache), four K steps in flight, through clamped
+// in-bounds addresses with the padding masked.  tri = 1 / 2: op(A) lower / upper triangular (the
+// zero part of the K range is skipped).  lower_only: entries above the diagonal are not written.
+// ------------------------------------------------------------------------------------------
+typedef double f64x4g __attribute__((ext_vector_type(4)));
+
 __global__ __launch_bounds__(256) void gemm_f64_kernel(int64_t M, int64_t N, int64_t K,
                                                        double alpha, const double* __restrict__ A,
                                                        int64_t lda, int transA,
@@ -15,15 +25,101 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(int64_t M, int64_t N, int
                                                        int64_t ldb, int transB, double beta,
                                                        double* __restrict__ C, int64_t ldc,
                                                        int lower_only, int tri) {
-  gemm_f64_tile(M, N, K, alpha, A, lda, transA, Bm, ldb, transB, beta, C, ldc, lower_only,
-                (int64_t)blockIdx.y * 64, (int64_t)blockIdx.x * 64, tri);
+  __shared__ double part[3][32 * 32];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+  const int64_t i0 = (int64_t)blockIdx.y * 32, j0 = (int64_t)blockIdx.x * 32;
+  if (lower_only && j0 > i0 + 31) return;
+  int64_t kb = 0, ke = K;
+  if (tri == 2) kb = i0 < K ? i0 : K;
+  if (tri == 1) ke = i0 + 32 < K ? i0 + 32 : K;
+  // this wave's quarter of [kb, ke), in steps of 4
+  const int64_t span = round_up(ceil_div(ke - kb, (int64_t)4), (int64_t)4);
+  const int64_t wb = kb + w * span, we = wb + span < ke ? wb + span : ke;
+  int64_t ra[2], cb[2];
+  bool vr[2], vc[2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x) {
+    const int64_t r = i0 + x * 16 + li, c = j0 + x * 16 + li;
+    vr[x] = r < M;
+    vc[x] = c < N;
+    ra[x] = vr[x] ? r : M - 1;
+    cb[x] = vc[x] ? c : N - 1;
+  }
+  f64x4g acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = f64x4g{0.0, 0.0, 0.0, 0.0};
+  // operands of the next 16-wide K slice are loaded while the current one is multiplied
+  double a[4][2], b[4][2], an[4][2], bn[4][2];
+  auto load = [&](int64_t k0, double (&pa)[4][2], double (&pb)[4][2]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int64_t k = k0 + 4 * s + lk;
+      const bool vk = k < we;
+      const int64_t kc = vk ? k : (K > 0 ? K - 1 : 0);
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        const double av = transA ? A[kc * lda + ra[x]] : A[ra[x] * lda + kc];
+        const double bv = transB ? Bm[cb[x] * ldb + kc] : Bm[kc * ldb + cb[x]];
+        pa[s][x] = mask_f64(av, vk && vr[x]);
+        pb[s][x] = mask_f64(bv, vk && vc[x]);
+      }
+    }
+  };
+  if (wb < we) load(wb, a, b);
+  for (int64_t k0 = wb; k0 < we; k0 += 16) {
+    if (k0 + 16 < we) load(k0 + 16, an, bn);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s][x], b[s][y], acc[x][y], 0, 0, 0);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        a[s][x] = an[s][x];
+        b[s][x] = bn[s][x];
+      }
+  }
+  // result element (x, y, r) of this lane: row x*16 + lk + 4r, column y*16 + li of the block
+  if (w > 0) {
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          part[w - 1][(x * 16 + lk + 4 * r) * 32 + y * 16 + li] = acc[x][y][r];
+  }
+  __syncthreads();
+  if (w == 0) {
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int rr = x * 16 + lk + 4 * r, cc = y * 16 + li;
+          const double v = ((acc[x][y][r] + part[0][rr * 32 + cc]) + part[1][rr * 32 + cc]) +
+                           part[2][rr * 32 + cc];
+          const int64_t gi = i0 + rr, gj = j0 + cc;
+          if (gi < M && gj < N && (!lower_only || gj <= gi)) {
+            double* c = C + gi * ldc + gj;
+            *c = (beta == 0.0 ? 0.0 : beta * *c) + alpha * v;
+          }
+        }
+  }
 }
 
 int gemm_f64(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
              bool transA, const double* B, int64_t ldb, bool transB, double beta, double* C,
              int64_t ldc, bool lower_only, hipStream_t stream, int tri) {
   if (M <= 0 || N <= 0) return VL_OK;
-  dim3 grid((unsigned)ceil_div(N, 64), (unsigned)ceil_div(M, 64));
+  dim3 grid((unsigned)ceil_div(N, (int64_t)32), (unsigned)ceil_div(M, (int64_t)32));
   gemm_f64_kernel<<<grid, 256, 0, stream>>>(M, N, K, alpha, A, lda, transA ? 1 : 0, B, ldb,
                                             transB ? 1 : 0, beta, C, ldc, lower_only ? 1 : 0,
                                             tri);
