@@ -155,6 +155,26 @@ __device__ inline void tile_load(double (*D)[kTL], const double* __restrict__ sr
   }
 }
 
+// The tile_load mapping into registers (16 values per thread) and back into LDS: the loads can
+// be issued early and stored after a product that still reads the LDS tile.
+__device__ inline void tile_fetch(double (&v)[16], const double* __restrict__ src, int64_t ld,
+                                  int rows, int cols) {
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int e = threadIdx.x + 256 * u, r = e >> 6, c = e & 63;
+    const bool ok = r < rows && c < cols;
+    v[u] = mask_f64(src[(int64_t)(ok ? r : 0) * ld + (ok ? c : 0)], ok);
+  }
+}
+
+__device__ inline void tile_put(double (*D)[kTL], const double (&v)[16]) {
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    D[e >> 6][e & 63] = v[u];
+  }
+}
+
 // acc += op(P) op(Q) over 64 terms, P and Q 64 x 64 tiles in LDS (op = transpose when kTP /
 // kTQ).  Wave w owns rows 32 (w >> 1) .. +31 and columns 32 (w & 1) .. +31 as 2 x 2 blocks of
 // v_mfma_f64_16x16x4f64: A operand lane l -> (row l % 16, k l / 16), B operand -> (k l / 16,
@@ -325,47 +345,79 @@ __global__ __launch_bounds__(256) void chol_step_kernel(CholArgs a, int64_t k) {
     }
     (void)t;
     const int64_t ri = blk_rows(a.n, i);
+    // the tile this item updates, and the second operand: A_jk (trailing tile; the diagonal
+    // tiles reuse A_ik) or the right-hand tile of block row k
+    double* out;
+    const double* src2 = nullptr;
+    int64_t ldo, ld2 = 0, rows2 = kNb, cols;
+    if (j >= 0) {
+      out = a.A + i * kNb * a.lda + j * kNb;
+      ldo = a.lda;
+      cols = blk_rows(a.n, j);
+      if (j != i) {
+        src2 = Ak + j * kNb * a.lda;
+        ld2 = a.lda;
+        rows2 = cols;
+      }
+    } else if (!inv_side) {
+      cols = a.nrhs - c * kNb < kNb ? a.nrhs - c * kNb : kNb;
+      out = a.R + i * kNb * a.ldr + c * kNb;
+      ldo = a.ldr;
+      src2 = a.R + k * kNb * a.ldr + c * kNb;
+      ld2 = a.ldr;
+    } else {
+      cols = blk_rows(a.n, c);
+      out = a.Li + i * kNb * a.ldli + c * kNb;
+      ldo = a.ldli;
+      src2 = a.Li + k * kNb * a.ldli + c * kNb;
+      ld2 = a.ldli;
+    }
+    const int64_t cols2 = j >= 0 ? kNb : cols;
+    // all global loads of the item are issued before the first product
+    double cur[16], nxt[16];
+    {
+      int u = 0;
+      acc_each(acc, [&](int r, int q, double) {
+        const bool ok = r < ri && q < cols;
+        cur[u++] = out[(int64_t)(ok ? r : 0) * ldo + (ok ? q : 0)];
+      });
+    }
+    if (src2) tile_fetch(nxt, src2, ld2, (int)rows2, (int)cols2);
     tile_load(X, Ak + i * kNb * a.lda, a.lda, (int)ri, kNb);
     tile_load(Z, Wk, kNb, kNb, kNb);
     __syncthreads();
     acc_zero(acc);
     mm64<false, false>(X, Z, acc);
     __syncthreads();
-    acc_each(acc, [&](int r, int q, double v) { X[r][q] = v; });
-    // second operand into Z: A_jk (trailing) or the right-hand tile of block row k
-    double* out;
-    int64_t ldo, cols;
-    if (j >= 0) {
-      tile_load(Z, Ak + j * kNb * a.lda, a.lda, (int)blk_rows(a.n, j), kNb);
-      out = a.A + i * kNb * a.lda + j * kNb;
-      ldo = a.lda;
-      cols = blk_rows(a.n, j);
-    } else if (!inv_side) {
-      cols = a.nrhs - c * kNb < kNb ? a.nrhs - c * kNb : kNb;
-      tile_load(Z, a.R + k * kNb * a.ldr + c * kNb, a.ldr, kNb, (int)cols);
-      out = a.R + i * kNb * a.ldr + c * kNb;
-      ldo = a.ldr;
+    if (j == i) {
+      // diagonal tile: P into Z, A_ik stays in X as the second operand (transposed)
+      acc_each(acc, [&](int r, int q, double v) { Z[r][q] = v; });
+      __syncthreads();
+      acc_zero(acc);
+      mm64<false, true>(Z, X, acc);
     } else {
-      cols = blk_rows(a.n, c);
-      tile_load(Z, a.Li + k * kNb * a.ldli + c * kNb, a.ldli, kNb, (int)cols);
-      out = a.Li + i * kNb * a.ldli + c * kNb;
-      ldo = a.ldli;
+      acc_each(acc, [&](int r, int q, double v) { X[r][q] = v; });
+      tile_put(Z, nxt);
+      __syncthreads();
+      acc_zero(acc);
+      if (j >= 0) mm64<false, true>(X, Z, acc);
+      else mm64<false, false>(X, Z, acc);
     }
-    __syncthreads();
-    acc_zero(acc);
-    if (j >= 0) mm64<false, true>(X, Z, acc);
-    else mm64<false, false>(X, Z, acc);
     if (j == k + 1 && i == k + 1) {
       // the critical tile: updated block into X (identity-padded), then factor and invert
       __syncthreads();
+      int u = 0;
       acc_each(acc, [&](int r, int q, double v) {
-        X[r][q] = (r < ri && q < ri) ? out[(int64_t)r * ldo + q] - v : (r == q ? 1.0 : 0.0);
+        const double o = cur[u++];
+        X[r][q] = (r < ri && q < ri) ? o - v : (r == q ? 1.0 : 0.0);
       });
       factor_diag_store(X, Z, buf, D0, a, k + 1);
       return;
     }
+    int u = 0;
     acc_each(acc, [&](int r, int q, double v) {
-      if (r < ri && q < cols) out[(int64_t)r * ldo + q] -= v;
+      const double o = cur[u++];
+      if (r < ri && q < cols) out[(int64_t)r * ldo + q] = o - v;
     });
     return;
   }

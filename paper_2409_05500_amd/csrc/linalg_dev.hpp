@@ -105,8 +105,10 @@ __device__ __attribute__((always_inline)) inline void leaf_inverse(
 
 // The leaf at (b, b): its L into S (lower part; the part right of the diagonal is scratch) and
 // its inverse into the same block of Y.  Called by one whole wave.
-__device__ inline void leaf_factor_inv(double (*S)[kLd], double (*Y)[kLd], const double* D0,
-                                       int b, bool& bad_any) {
+__device__ __attribute__((always_inline)) inline void leaf_factor_inv(double (*S)[kLd],
+                                                                       double (*Y)[kLd],
+                                                                       const double* D0, int b,
+                                                                       bool& bad_any) {
   const int lane = threadIdx.x & 63, r = lane & 15;
   double a[kLeaf];
 #pragma unroll
@@ -161,8 +163,11 @@ __device__ inline void blk16_each(const f64x4_t& acc, F f) {
 // block:  Y_tu = -Y_tt sum_{u <= v < t} L_tv Y_vu.
 constexpr int kFactorBuf = 3 * kLeaf * kLeaf;
 
-__device__ inline void block_factor_inv(double (*S)[kLd], double (*Y)[kLd], double* buf,
-                                        const double* D0, int32_t* st) {
+__device__ __attribute__((always_inline)) inline void block_factor_inv(double (*S)[kLd],
+                                                                        double (*Y)[kLd],
+                                                                        double* buf,
+                                                                        const double* D0,
+                                                                        int32_t* st) {
   const int tid = threadIdx.x, w = tid >> 6;
   constexpr int kB = kNb / kLeaf;  // 4 block rows
   for (int e = tid; e < kNb * kNb; e += 256) Y[e >> 6][e & 63] = 0.0;
