@@ -128,10 +128,11 @@ __global__ __launch_bounds__(kThreads) void order_wave_kernel(const double* __re
 int run_order(const double* S, int64_t m, int32_t* order, double* margin, double* M0,
               int32_t* st, hipStream_t stream) {
   ProfileScope ps("order", stream);
-  // 16 waves form M0 quickly; with 64 or more variables per lane the block is cut to 4 waves
+  // 16 waves form M0 quickly; with more variables per lane the block is cut to 8 or 4 waves
   // so that the one sequential wave may hold them all in registers
 #define VL_ORDER_WAVE(R) \
-  order_wave_kernel<R, (R <= 16 ? 1024 : 256)><<<1, (R <= 16 ? 1024 : 256), 0, stream>>>( \
+  order_wave_kernel<R, (R <= 8 ? 1024 : (R <= 16 ? 512 : 256))> \
+      <<<1, (R <= 8 ? 1024 : (R <= 16 ? 512 : 256)), 0, stream>>>( \
       S, m, order, margin, st)
   if (m <= 64) VL_ORDER_WAVE(1);
   else if (m <= 128) VL_ORDER_WAVE(2);

@@ -72,15 +72,34 @@ __device__ inline void order_wave_block(const double* __restrict__ S, int64_t m,
   __shared__ double M0s[64 * R];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   bool bad = false;
-  for (int64_t row = wave; row < m; row += kThreads / 64) {
-    double s = 0.0;
-    for (int64_t j = lane; j < m; j += 64) {
-      const double v = S[row * m + j];
-      bad |= !isfinite(v);
-      if (j != row && v < 0.0) s += v * v;
+  // several rows per wave at once, every load of them issued before the sums (clamped
+  // in-bounds addresses; the padding is skipped in the sums)
+  constexpr int kRows = R <= 4 ? 4 : (R <= 8 ? 2 : 1);
+  for (int64_t row0 = (int64_t)wave * kRows; row0 < m; row0 += (int64_t)(kThreads / 64) * kRows) {
+    double v[kRows][R];
+#pragma unroll
+    for (int q = 0; q < kRows; ++q) {
+      const int64_t row = row0 + q < m ? row0 + q : m - 1;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int64_t j = lane + 64 * r;
+        v[q][r] = S[row * m + (j < m ? j : m - 1)];
+      }
     }
-    s = wave_sum_d(s);
-    if (lane == 0) M0s[row] = isfinite(s) ? s : INFINITY;
+#pragma unroll
+    for (int q = 0; q < kRows; ++q) {
+      const int64_t row = row0 + q;
+      double s = 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int64_t j = lane + 64 * r;
+        const bool in = j < m && row < m;
+        bad |= in && !isfinite(v[q][r]);
+        if (in && j != row && v[q][r] < 0.0) s += v[q][r] * v[q][r];
+      }
+      s = wave_sum_d(s);
+      if (lane == 0 && row < m) M0s[row] = isfinite(s) ? s : INFINITY;
+    }
   }
   if (bad) raise_status(st, VL_ERR_NONFINITE);
   __syncthreads();
