@@ -5,10 +5,11 @@
 // Throughput stages (column means, Gram matrices, residual GEMM, standardisation, Hx, pair
 // coefficients, pairwise moments, combine) launch the sum of the problems' blocks; a
 // block -> problem table and each problem's first block turn a block index into (problem,
-// local block), and the block runs the same body as the single-problem kernel.  Latency-bound
-// stages (Cholesky solve of the VAR normal equations; ordering followed by the B estimation)
-// run one 256-thread workgroup per problem, so a batch of a few hundred problems fills the
-// chip in one launch instead of a few hundred serial ones.
+// local block), and the block runs the same body as the single-problem kernel.  The two
+// Cholesky factorisations (VAR normal equations; permuted residual covariance for B0) run the
+// fused panel steps of the single-problem path, one launch per panel step for all problems
+// (at most four steps: d <= 256), followed by batched FP64 GEMM tiles (back substitution, lag
+// matrices B_tau).  The ordering runs one workgroup per problem.
 //
 // The Gram tiles here run over all samples in one block (no split-K; the batch supplies the
 // parallelism), so results differ from the single-problem path by summation order only.
@@ -18,8 +19,8 @@
 #include <string>
 #include <vector>
 
+#include "chol_dev.hpp"
 #include "gram_dev.hpp"
-#include "linalg_dev.hpp"
 #include "order_dev.hpp"
 #include "pairwise_dev.hpp"
 #include "profile.hpp"
@@ -29,6 +30,8 @@ namespace vl {
 
 constexpr int kBatchMaxM = 256;      // order body with 4 variables per lane
 constexpr int kBatchMaxDz = 256;
+constexpr int kMaxCholSteps = kBatchMaxDz / kNb;   // panel steps of either factorisation
+static_assert(kBatchMaxM <= kBatchMaxDz, "the B0 factorisation uses the same step maps");
 
 // Per-problem descriptor as the kernels see it (device copy in the workspace).
 struct BInst {
@@ -55,11 +58,12 @@ struct BInst {
   float* Xs;
   float2* coef;
   float *partU, *partB;
-  double *P, *Lc, *Id, *Linv, *bchol;
+  double *P, *Linv, *bchol;
 };
 
 enum BMap { kMapColVar, kMapColE, kMapGramVar, kMapGramCov, kMapResid, kMapStd, kMapPrep,
-            kMapMom, kMapComb, kNumMaps };
+            kMapMom, kMapComb, kMapVarChol0, kMapBChol0 = kMapVarChol0 + kMaxCholSteps,
+            kMapVarBack = kMapBChol0 + kMaxCholSteps, kMapBlag, kNumMaps };
 
 struct BTables {
   const BInst* inst;
@@ -134,7 +138,7 @@ __global__ __launch_bounds__(256) void bat_colmeans_kernel(BTables T, int which,
 
 // Centred Gram tiles over all samples.  which = 0: the lower-triangle tiles of G = Zc^T Zc
 // (dz x dz; the Cholesky reads nothing above the diagonal blocks) then R = Zc^T Yc (dz x m,
-// into Coef); which = 1: the lower-triangle tiles of Cov = Ec^T Ec / n_eff, each off-diagonal
+// into Tmp, where the forward substitution works on it); which = 1: the lower-triangle tiles of Cov = Ec^T Ec / n_eff, each off-diagonal
 // tile also written transposed (Cov exactly symmetric).  kFp64: FP64 MFMA on the widened data;
 // otherwise FP32 MFMA.
 // k-th tile (row-major) of the lower triangle of a t x t tile grid: (ti, tj), tj <= ti
@@ -178,7 +182,7 @@ __global__ __launch_bounds__(256) void bat_gram_kernel(BTables T, int which) {
     } else {
       const int64_t l2 = lb - tri;
       bat_gram_tile<kFp64>(d.X, d.ldx, mapZ, muZ, d.dz, d.X, d.ldx, d.colmap, d.mu, d.m,
-                           (l2 / tm) * kGT, (l2 % tm) * kGT, d.n_eff, d.Coef, d.m, 1.0, false);
+                           (l2 / tm) * kGT, (l2 % tm) * kGT, d.n_eff, d.Tmp, d.m, 1.0, false);
     }
   } else {
     int64_t ti, tj;
@@ -189,16 +193,60 @@ __global__ __launch_bounds__(256) void bat_gram_kernel(BTables T, int which) {
   }
 }
 
-// One workgroup per problem: Cholesky of G, Coef = G^{-1} R, lag matrices, intercept, and the
-// FP32 copy of Coef for the FP32 residual GEMM.
-__global__ __launch_bounds__(256) void bat_var_solve_kernel(const BInst* __restrict__ I,
+// The factorisation arguments of a problem: which = 0, the VAR normal equations (G, with the
+// right-hand sides R in Tmp and L^{-1} into L); which = 1, the order-permuted covariance P for
+// B0 (L^{-1} into Linv only).
+__device__ inline CholArgs bat_chol_args(const BInst& d, int which, int32_t* st) {
+  CholArgs a;
+  const int64_t n = which ? d.m : d.dz;
+  const int64_t nb = ceil_div(n, (int64_t)kNb);
+  double* ws = which ? d.bchol : d.chol;
+  a.A = which ? d.P : d.G;
+  a.n = n;
+  a.lda = n;
+  a.R = which ? nullptr : d.Tmp;
+  a.nrhs = which ? 0 : d.m;
+  a.ldr = d.m;
+  a.Li = which ? d.Linv : d.L;
+  a.ldli = n;
+  a.diag0 = ws;
+  a.Yb = ws + n;
+  a.Wb = ws + n + nb * kNb * kNb;
+  a.st = st;
+  return a;
+}
+
+// One workgroup per problem: L^{-1} set to the identity and the first diagonal block factored.
+__global__ __launch_bounds__(256) void bat_chol_prologue_kernel(const BInst* __restrict__ I,
+                                                                int which, int32_t* st0) {
+  const CholArgs a = bat_chol_args(I[blockIdx.x], which, st0 + blockIdx.x);
+  for (int64_t e = threadIdx.x; e < a.n * a.n; e += 256) chol_linv_init(a, e);
+  chol_prologue_block(a);
+}
+
+// Panel step k of every problem that has one (its items through the step-k map).
+__global__ __launch_bounds__(256) void bat_chol_step_kernel(BTables T, int which, int k,
                                                             int32_t* st0) {
+  int64_t lb;
+  const int b = bat_locate(T, (which ? kMapBChol0 : kMapVarChol0) + k, blockIdx.x, lb);
+  const CholArgs a = bat_chol_args(T.inst[b], which, st0 + b);
+  chol_step_item(a, k, lb);
+}
+
+// Back substitution Coef = L^{-T} (L^{-1} R), 32 x 32 tiles of Coef (dz x m).
+__global__ __launch_bounds__(256) void bat_back_kernel(BTables T) {
+  int64_t lb;
+  const int b = bat_locate(T, kMapVarBack, blockIdx.x, lb);
+  const BInst& d = T.inst[b];
+  const int64_t tn = ceil_div(d.m, (int64_t)32);
+  gemm_f64_block(d.dz, d.m, d.dz, 1.0, d.L, d.dz, 1, d.Tmp, d.m, 0, 0.0, d.Coef, d.m, 0, 2,
+                 (lb / tn) * 32, (lb % tn) * 32);
+}
+
+// One workgroup per problem: lag matrices, intercept and (FP32 mode) the FP32 coefficients.
+__global__ __launch_bounds__(256) void bat_var_post_kernel(const BInst* __restrict__ I) {
   const BInst& d = I[blockIdx.x];
-  int32_t* st = st0 + blockIdx.x;
   const int64_t m = d.m, dz = d.dz;
-  wg_potrf_lower(d.G, dz, dz, d.L, dz, d.chol, st);
-  wg_trsm_lower(d.L, dz, dz, d.chol, false, d.Coef, m, m, d.Tmp, m);
-  wg_trsm_lower(d.L, dz, dz, d.chol, true, d.Tmp, m, m, d.Coef, m);
   const int tid = threadIdx.x;
   for (int64_t e = tid; e < (int64_t)d.p * m * m; e += 256) {
     const int64_t tau1 = e / (m * m), rem = e % (m * m), i = rem / m, k = rem % m;
@@ -287,8 +335,10 @@ __global__ __launch_bounds__(256) void bat_combine_kernel(BTables T) {
 
 // One workgroup per problem: the ordering, then B0 from the LDL^T of the order-permuted
 // covariance (B0_KK = I - L^{-1}) and B_tau = (I - B0) M_tau.
-__global__ __launch_bounds__(256) void bat_order_b_kernel(const BInst* __restrict__ I,
-                                                          int32_t* st0) {
+// One workgroup per problem: the ordering, then the covariance permuted into that order
+// (with the permutation check).
+__global__ __launch_bounds__(256) void bat_order_kernel(const BInst* __restrict__ I,
+                                                        int32_t* st0) {
   const BInst& d = I[blockIdx.x];
   int32_t* st = st0 + blockIdx.x;
   const int64_t m = d.m;
@@ -312,24 +362,31 @@ __global__ __launch_bounds__(256) void bat_order_b_kernel(const BInst* __restric
   __syncthreads();
   for (int64_t a = tid; a < m; a += 256)
     if (seen[a] != 1) raise_status(st, VL_ERR_INVALID_ARG);
-  wg_potrf_lower(d.P, m, m, d.Lc, m, d.bchol, st);
-  for (int64_t e = tid; e < m * m; e += 256) d.Id[e] = (e / m == e % m) ? 1.0 : 0.0;
-  __syncthreads();
-  wg_trsm_lower(d.Lc, m, m, d.bchol, false, d.Id, m, m, d.Linv, m);
-  for (int64_t e = tid; e < m * m; e += 256) {
+}
+
+// One workgroup per problem: B0[K_a][K_b] = -Linv[a][b] / Linv[a][a] for b < a, else 0.
+__global__ __launch_bounds__(256) void bat_b0_kernel(const BInst* __restrict__ I) {
+  const BInst& d = I[blockIdx.x];
+  const int64_t m = d.m;
+  const int32_t* K = d.order;
+  for (int64_t e = threadIdx.x; e < m * m; e += 256) {
     const int64_t a = e / m, c = e % m;
     const int32_t ka = K[a], kc = K[c];
     if (ka < 0 || ka >= m || kc < 0 || kc >= m) continue;
-    d.B0[(int64_t)ka * m + kc] = c < a ? -d.Lc[a * m + a] * d.Linv[a * m + c] : 0.0;
+    d.B0[(int64_t)ka * m + kc] = c < a ? -d.Linv[a * m + c] / d.Linv[a * m + a] : 0.0;
   }
-  __syncthreads();
-  for (int tau = 0; tau < d.p; ++tau) {
-    const double* Mt = d.M + (int64_t)tau * m * m;
-    double* Bt = d.Blag + (int64_t)tau * m * m;
-    for (int64_t e = tid; e < m * m; e += 256) Bt[e] = Mt[e];
-    __syncthreads();
-    wg_gemm_f64(m, m, m, -1.0, d.B0, m, false, Mt, m, false, 1.0, Bt, m, false);
-  }
+}
+
+// B_tau = M_tau - B0 M_tau, 32 x 32 tiles of each B_tau.
+__global__ __launch_bounds__(256) void bat_blag_kernel(BTables T) {
+  int64_t lb;
+  const int b = bat_locate(T, kMapBlag, blockIdx.x, lb);
+  const BInst& d = T.inst[b];
+  const int64_t m = d.m, tm = ceil_div(m, (int64_t)32);
+  const int64_t tau = lb / (tm * tm), rem = lb % (tm * tm);
+  const double* Mt = d.M + tau * m * m;
+  gemm_f64_block(m, m, m, -1.0, d.B0, m, 0, Mt, m, 0, 1.0, d.Blag + tau * m * m, m, 0, 0,
+                 (rem / tm) * 32, (rem % tm) * 32, Mt);
 }
 
 }  // namespace vl
@@ -361,7 +418,7 @@ size_t carve_inst(const vl_instance& in, const InstLayout& L, char* base, BInst*
   t.Coef = c.take<double>(dz * m);
   t.L = c.take<double>(dz * dz);
   t.Tmp = c.take<double>(dz * m);
-  t.chol = c.take<double>(dz + ceil_div(dz, 64) * 64 * 64);
+  t.chol = c.take<double>(chol_ws_doubles_dev(dz));
   t.CoefF = c.take<float>(dz * m);
   t.emu = c.take<double>(m);
   t.cov = c.take<double>(m * m);
@@ -375,10 +432,8 @@ size_t carve_inst(const vl_instance& in, const InstLayout& L, char* base, BInst*
   t.partU = c.take<float>((size_t)L.nchunk * m * m);
   t.partB = c.take<float>((size_t)L.nchunk * m * m);
   t.P = c.take<double>(m * m);
-  t.Lc = c.take<double>(m * m);
-  t.Id = c.take<double>(m * m);
   t.Linv = c.take<double>(m * m);
-  t.bchol = c.take<double>(m + ceil_div(m, 64) * 64 * 64);
+  t.bchol = c.take<double>(chol_ws_doubles_dev(m));
   (void)n_eff;
   if (d) *d = t;
   return c.used;
@@ -411,6 +466,16 @@ int64_t blocks_for(int map, const vl_instance& in, const InstLayout& L) {
     case kMapPrep: return m + ceil_div(L.m_pad * L.m_pad, 256);
     case kMapMom: return ceil_div(L.items, 4);
     case kMapComb: return ceil_div(m * m, 256);
+    case kMapVarBack: return ceil_div(dz, 32) * ceil_div(m, 32);
+    case kMapBlag: return (int64_t)in.p * ceil_div(m, 32) * ceil_div(m, 32);
+  }
+  if (map >= kMapVarChol0 && map < kMapBChol0) {
+    const int64_t k = map - kMapVarChol0, nb = ceil_div(dz, (int64_t)kNb);
+    return k < nb ? step_items(nb, k, ceil_div(m, (int64_t)kNb), true).total() : 0;
+  }
+  if (map >= kMapBChol0 && map < kMapVarBack) {
+    const int64_t k = map - kMapBChol0, nb = ceil_div(m, (int64_t)kNb);
+    return k < nb ? step_items(nb, k, 0, true).total() : 0;
   }
   return 0;
 }
@@ -556,7 +621,16 @@ int launch_fit(const vl_batch* B, void* ws, int32_t* st, hipStream_t s) {
     if (f64) bat_gram_kernel<true><<<(unsigned)B->total[kMapGramVar], 256, 0, s>>>(T, 0);
     else bat_gram_kernel<false><<<(unsigned)B->total[kMapGramVar], 256, 0, s>>>(T, 0);
     VL_LAUNCH_CHECK();
-    bat_var_solve_kernel<<<(unsigned)n, 256, 0, s>>>(I, st);
+    bat_chol_prologue_kernel<<<(unsigned)n, 256, 0, s>>>(I, 0, st);
+    VL_LAUNCH_CHECK();
+    for (int k = 0; k < kMaxCholSteps; ++k) {
+      if (B->total[kMapVarChol0 + k] == 0) continue;
+      bat_chol_step_kernel<<<(unsigned)B->total[kMapVarChol0 + k], 256, 0, s>>>(T, 0, k, st);
+      VL_LAUNCH_CHECK();
+    }
+    bat_back_kernel<<<(unsigned)B->total[kMapVarBack], 256, 0, s>>>(T);
+    VL_LAUNCH_CHECK();
+    bat_var_post_kernel<<<(unsigned)n, 256, 0, s>>>(I);
     VL_LAUNCH_CHECK();
     if (f64) bat_var_residual_kernel<true><<<(unsigned)B->total[kMapResid], 256, 0, s>>>(T);
     else bat_var_residual_kernel<false><<<(unsigned)B->total[kMapResid], 256, 0, s>>>(T);
@@ -584,7 +658,18 @@ int launch_fit(const vl_batch* B, void* ws, int32_t* st, hipStream_t s) {
     ProfileScope ps("batch_order_b", s);
     bat_combine_kernel<<<(unsigned)B->total[kMapComb], 256, 0, s>>>(T);
     VL_LAUNCH_CHECK();
-    bat_order_b_kernel<<<(unsigned)n, 256, 0, s>>>(I, st);
+    bat_order_kernel<<<(unsigned)n, 256, 0, s>>>(I, st);
+    VL_LAUNCH_CHECK();
+    bat_chol_prologue_kernel<<<(unsigned)n, 256, 0, s>>>(I, 1, st);
+    VL_LAUNCH_CHECK();
+    for (int k = 0; k < kMaxCholSteps; ++k) {
+      if (B->total[kMapBChol0 + k] == 0) continue;
+      bat_chol_step_kernel<<<(unsigned)B->total[kMapBChol0 + k], 256, 0, s>>>(T, 1, k, st);
+      VL_LAUNCH_CHECK();
+    }
+    bat_b0_kernel<<<(unsigned)n, 256, 0, s>>>(I);
+    VL_LAUNCH_CHECK();
+    bat_blag_kernel<<<(unsigned)B->total[kMapBlag], 256, 0, s>>>(T);
     VL_LAUNCH_CHECK();
   }
   return VL_OK;

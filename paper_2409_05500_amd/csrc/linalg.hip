@@ -2,21 +2,11 @@
 // right-looking Cholesky fused with the forward substitution (one launch per 64-wide panel),
 // and a tiled FP64 GEMM.  Matrices are row-major with explicit leading dimensions.
 #include "linalg.hpp"
-#include "linalg_dev.hpp"
+#include "chol_dev.hpp"
 
 #include <math.h>
 
 namespace vl {
-
-// ------------------------------------------------------------------------------------------
-// FP64 GEMM on MFMA: C = beta C + alpha op(A) op(B).  A workgroup owns a 32 x 32 block of C (2 x 2
-// v_mfma_f64_16x16x4f64 blocks); its four waves split the K range in four and add their partial
-// products through LDS in a fixed order.  Operands are read straight from global memory (the
-// callers' matrices are a few MB and stay in cache), four K steps in flight, through clamped
-// in-bounds addresses with the padding masked.  tri = 1 / 2: op(A) lower / upper triangular (the
-// zero part of the K range is skipped).  lower_only: entries above the diagonal are not written.
-// ------------------------------------------------------------------------------------------
-typedef double f64x4g __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(256) void gemm_f64_kernel(int64_t M, int64_t N, int64_t K,
                                                        double alpha, const double* __restrict__ A,
@@ -25,94 +15,8 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(int64_t M, int64_t N, int
                                                        int64_t ldb, int transB, double beta,
                                                        double* __restrict__ C, int64_t ldc,
                                                        int lower_only, int tri) {
-  __shared__ double part[3][32 * 32];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
-  const int64_t i0 = (int64_t)blockIdx.y * 32, j0 = (int64_t)blockIdx.x * 32;
-  if (lower_only && j0 > i0 + 31) return;
-  int64_t kb = 0, ke = K;
-  if (tri == 2) kb = i0 < K ? i0 : K;
-  if (tri == 1) ke = i0 + 32 < K ? i0 + 32 : K;
-  // this wave's quarter of [kb, ke), in steps of 4
-  const int64_t span = round_up(ceil_div(ke - kb, (int64_t)4), (int64_t)4);
-  const int64_t wb = kb + w * span, we = wb + span < ke ? wb + span : ke;
-  int64_t ra[2], cb[2];
-  bool vr[2], vc[2];
-#pragma unroll
-  for (int x = 0; x < 2; ++x) {
-    const int64_t r = i0 + x * 16 + li, c = j0 + x * 16 + li;
-    vr[x] = r < M;
-    vc[x] = c < N;
-    ra[x] = vr[x] ? r : M - 1;
-    cb[x] = vc[x] ? c : N - 1;
-  }
-  f64x4g acc[2][2];
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int y = 0; y < 2; ++y) acc[x][y] = f64x4g{0.0, 0.0, 0.0, 0.0};
-  // operands of the next 16-wide K slice are loaded while the current one is multiplied
-  double a[4][2], b[4][2], an[4][2], bn[4][2];
-  auto load = [&](int64_t k0, double (&pa)[4][2], double (&pb)[4][2]) {
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int64_t k = k0 + 4 * s + lk;
-      const bool vk = k < we;
-      const int64_t kc = vk ? k : (K > 0 ? K - 1 : 0);
-#pragma unroll
-      for (int x = 0; x < 2; ++x) {
-        const double av = transA ? A[kc * lda + ra[x]] : A[ra[x] * lda + kc];
-        const double bv = transB ? Bm[cb[x] * ldb + kc] : Bm[kc * ldb + cb[x]];
-        pa[s][x] = mask_f64(av, vk && vr[x]);
-        pb[s][x] = mask_f64(bv, vk && vc[x]);
-      }
-    }
-  };
-  if (wb < we) load(wb, a, b);
-  for (int64_t k0 = wb; k0 < we; k0 += 16) {
-    if (k0 + 16 < we) load(k0 + 16, an, bn);
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y)
-          acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s][x], b[s][y], acc[x][y], 0, 0, 0);
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int x = 0; x < 2; ++x) {
-        a[s][x] = an[s][x];
-        b[s][x] = bn[s][x];
-      }
-  }
-  // result element (x, y, r) of this lane: row x*16 + lk + 4r, column y*16 + li of the block
-  if (w > 0) {
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int y = 0; y < 2; ++y)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          part[w - 1][(x * 16 + lk + 4 * r) * 32 + y * 16 + li] = acc[x][y][r];
-  }
-  __syncthreads();
-  if (w == 0) {
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int y = 0; y < 2; ++y)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int rr = x * 16 + lk + 4 * r, cc = y * 16 + li;
-          const double v = ((acc[x][y][r] + part[0][rr * 32 + cc]) + part[1][rr * 32 + cc]) +
-                           part[2][rr * 32 + cc];
-          const int64_t gi = i0 + rr, gj = j0 + cc;
-          if (gi < M && gj < N && (!lower_only || gj <= gi)) {
-            double* c = C + gi * ldc + gj;
-            *c = (beta == 0.0 ? 0.0 : beta * *c) + alpha * v;
-          }
-        }
-  }
+  gemm_f64_block(M, N, K, alpha, A, lda, transA, Bm, ldb, transB, beta, C, ldc, lower_only, tri,
+                 (int64_t)blockIdx.y * 32, (int64_t)blockIdx.x * 32);
 }
 
 int gemm_f64(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
@@ -127,345 +31,19 @@ int gemm_f64(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int
   return VL_OK;
 }
 
-// ------------------------------------------------------------------------------------------
-// Fused blocked Cholesky + forward substitution.  Panel width 64; nb = ceil(n / 64) block rows.
-// Per block k the workspace keeps Y_k = L_kk^{-1} and W_k = Y_k^T Y_k = (A_kk^{(k)})^{-1}, the
-// inverse of the diagonal block after the updates of panels < k.  Right-looking step k applies
-// panel k everywhere at once, each workgroup recomputing the panel product it needs:
-//   trailing tile (i, j), k < j <= i:   A_ij -= (A_ik W_k) A_jk^T      (= L_ik L_jk^T)
-//   right-hand tile (i, c), i > k:      R_ic -= (A_ik W_k) R_kc         (= L_ik (L^{-1} R)_kc)
-// and the workgroup of tile (k+1, k+1) goes on to factor and invert it (Y_{k+1}, W_{k+1}), so
-// one launch per panel covers the factorisation and the substitution.  Block row k of the
-// right-hand sides is final after step k - 1; step k + 1 (or the last step) scales it in place:
-//   (L^{-1} R)_kc = Y_k R_kc.
-// L^{-1} itself is the substitution applied to R = I, whose column tile c stays zero above
-// block row c (those tiles are skipped).
-// ------------------------------------------------------------------------------------------
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-
-constexpr int kTL = kLd;  // LDS tile leading dimension (65: rows land on different banks)
-
-// D[r][c] = src[r * ld + c] for r < rows, c < cols; 0 elsewhere
-__device__ inline void tile_load(double (*D)[kTL], const double* __restrict__ src, int64_t ld,
-                                 int rows, int cols) {
-#pragma unroll 4
-  for (int e = threadIdx.x; e < kNb * kNb; e += 256) {
-    const int r = e >> 6, c = e & 63;
-    D[r][c] = (r < rows && c < cols) ? src[(int64_t)r * ld + c] : 0.0;
-  }
-}
-
-// The tile_load mapping into registers (16 values per thread) and back into LDS: the loads can
-// be issued early and stored after a product that still reads the LDS tile.
-__device__ inline void tile_fetch(double (&v)[16], const double* __restrict__ src, int64_t ld,
-                                  int rows, int cols) {
-#pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int e = threadIdx.x + 256 * u, r = e >> 6, c = e & 63;
-    const bool ok = r < rows && c < cols;
-    v[u] = mask_f64(src[(int64_t)(ok ? r : 0) * ld + (ok ? c : 0)], ok);
-  }
-}
-
-__device__ inline void tile_put(double (*D)[kTL], const double (&v)[16]) {
-#pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int e = threadIdx.x + 256 * u;
-    D[e >> 6][e & 63] = v[u];
-  }
-}
-
-// acc += op(P) op(Q) over 64 terms, P and Q 64 x 64 tiles in LDS (op = transpose when kTP /
-// kTQ).  Wave w owns rows 32 (w >> 1) .. +31 and columns 32 (w & 1) .. +31 as 2 x 2 blocks of
-// v_mfma_f64_16x16x4f64: A operand lane l -> (row l % 16, k l / 16), B operand -> (k l / 16,
-// column l % 16), result register r -> (row l / 16 + 4 r, column l % 16).
-template <bool kTP, bool kTQ>
-__device__ inline void mm64(const double (*P)[kTL], const double (*Q)[kTL], f64x4 (&acc)[2][2]) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wi = w >> 1, wj = w & 1, lr = lane & 15, lk = lane >> 4;
-#pragma unroll 4
-  for (int kk = 0; kk < kNb; kk += 4) {
-    double a[2], b[2];
-#pragma unroll
-    for (int x = 0; x < 2; ++x) {
-      const int row = wi * 32 + x * 16 + lr, col = wj * 32 + x * 16 + lr;
-      a[x] = kTP ? P[kk + lk][row] : P[row][kk + lk];
-      b[x] = kTQ ? Q[col][kk + lk] : Q[kk + lk][col];
-    }
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int y = 0; y < 2; ++y)
-        acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
-  }
-}
-
-__device__ inline void acc_zero(f64x4 (&acc)[2][2]) {
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int y = 0; y < 2; ++y) acc[x][y] = f64x4{0.0, 0.0, 0.0, 0.0};
-}
-
-// f(row, col, value) for every result element this thread holds
-template <class F>
-__device__ inline void acc_each(const f64x4 (&acc)[2][2], F f) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wi = w >> 1, wj = w & 1;
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int y = 0; y < 2; ++y)
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        f(wi * 32 + x * 16 + (lane >> 4) + 4 * r, wj * 32 + y * 16 + (lane & 15), acc[x][y][r]);
-}
-
-struct CholArgs {
-  double* A;
-  int64_t n, lda;
-  double* R;          // right-hand sides (n x nrhs) or null
-  int64_t nrhs, ldr;
-  double* Li;         // L^{-1} (n x n) or null
-  int64_t ldli;
-  double* diag0;      // n: diagonal before elimination (pivot test)
-  double* Yb;         // nb x 64 x 64: Y_k
-  double* Wb;         // nb x 64 x 64: W_k
-  int32_t* st;
-};
-
-__host__ __device__ inline int64_t blk_rows(int64_t n, int64_t b) {
-  return n - b * kNb < kNb ? n - b * kNb : kNb;
-}
-
-// Work items of step k, in launch order: trailing tiles (the critical tile (k+1, k+1) first),
-// right-hand updates, L^{-1} updates, then the in-place scalings of block rows k - 1 and (last
-// step) k for the right-hand sides and for L^{-1}.
-struct StepItems {
-  int64_t trail, upd_r, upd_i, fin_r, fin_i;
-  __host__ __device__ int64_t total() const { return trail + upd_r + upd_i + fin_r + fin_i; }
-};
-
-__host__ __device__ inline StepItems step_items(int64_t nb, int64_t k, int64_t cr, bool li) {
-  StepItems s;
-  const int64_t t = nb - 1 - k;
-  s.trail = t * (t + 1) / 2;
-  s.upd_r = t * cr;
-  s.upd_i = li ? t * (k + 1) : 0;
-  const int64_t nfin = (k >= 1 ? 1 : 0) + (k == nb - 1 ? 1 : 0);
-  s.fin_r = nfin * cr;
-  s.fin_i = li ? (k >= 1 ? k : 0) + (k == nb - 1 ? k + 1 : 0) : 0;
-  return s;
-}
-
-// The critical tile's epilogue: S = the updated diagonal block (identity-padded) is factored;
-// Y_b and W_b = Y_b^T Y_b go to the workspace.
-__device__ inline void factor_diag_store(double (*S)[kTL], double (*Y)[kTL], double* buf,
-                                         double* D0, const CholArgs& a, int64_t b) {
-  const int64_t kb = blk_rows(a.n, b);
-  if (threadIdx.x < kNb) D0[threadIdx.x] = threadIdx.x < kb ? a.diag0[b * kNb + threadIdx.x] : 1.0;
-  block_factor_inv(S, Y, buf, D0, a.st);
-  double* Yo = a.Yb + b * kNb * kNb;
-  for (int e = threadIdx.x; e < kNb * kNb; e += 256) {
-    const int r = e >> 6, q = e & 63;
-    Yo[e] = q <= r ? Y[r][q] : 0.0;
-  }
-  f64x4 acc[2][2];
-  acc_zero(acc);
-  mm64<true, false>(Y, Y, acc);      // Y has exact zeros above the diagonal
-  double* Wo = a.Wb + b * kNb * kNb;
-  acc_each(acc, [&](int r, int c, double v) { Wo[r * kNb + c] = v; });
-}
-
 __global__ __launch_bounds__(256) void chol_prologue_kernel(CholArgs a) {
-  __shared__ double S[kNb][kTL];
-  __shared__ double Y[kNb][kTL];
-  __shared__ double buf[kFactorBuf];
-  __shared__ double D0[kNb];
   if (blockIdx.x > 0) {
-    // L^{-1} starts as the identity (the substitution works on it in place)
-    const int64_t e = (int64_t)(blockIdx.x - 1) * 256 + threadIdx.x;
-    if (a.Li && e < a.n * a.n) {
-      const int64_t r = e / a.n, c = e % a.n;
-      a.Li[r * a.ldli + c] = r == c ? 1.0 : 0.0;
-    }
+    chol_linv_init(a, (int64_t)(blockIdx.x - 1) * 256 + threadIdx.x);
     return;
   }
-  for (int64_t i = threadIdx.x; i < a.n; i += 256) a.diag0[i] = a.A[i * a.lda + i];
-  const int kb = (int)blk_rows(a.n, 0);
-  for (int e = threadIdx.x; e < kNb * kNb; e += 256) {
-    const int r = e >> 6, q = e & 63;
-    S[r][q] = (r < kb && q < kb) ? a.A[(int64_t)r * a.lda + q] : (r == q ? 1.0 : 0.0);
-  }
-  if (threadIdx.x < kNb) D0[threadIdx.x] = threadIdx.x < kb ? a.A[threadIdx.x * (a.lda + 1)] : 1.0;
-  block_factor_inv(S, Y, buf, D0, a.st);
-  double* Yo = a.Yb;
-  for (int e = threadIdx.x; e < kNb * kNb; e += 256) {
-    const int r = e >> 6, q = e & 63;
-    Yo[e] = q <= r ? Y[r][q] : 0.0;
-  }
-  f64x4 acc[2][2];
-  acc_zero(acc);
-  mm64<true, false>(Y, Y, acc);
-  acc_each(acc, [&](int r, int c, double v) { a.Wb[r * kNb + c] = v; });
+  chol_prologue_block(a);
 }
 
 __global__ __launch_bounds__(256) void chol_step_kernel(CholArgs a, int64_t k) {
-  __shared__ double X[kNb][kTL];
-  __shared__ double Z[kNb][kTL];
-  __shared__ double buf[kFactorBuf];
-  __shared__ double D0[kNb];
-  const int64_t nb = ceil_div(a.n, (int64_t)kNb);
-  const int64_t cr = a.R ? ceil_div(a.nrhs, (int64_t)kNb) : 0;
-  const StepItems s = step_items(nb, k, cr, a.Li != nullptr);
-  int64_t e = blockIdx.x;
-  const int64_t t = nb - 1 - k;
-  const double* Ak = a.A + k * kNb;                 // column block k of A
-  const double* Wk = a.Wb + k * kNb * kNb;
-  f64x4 acc[2][2];
-  if (e < s.trail + s.upd_r + s.upd_i) {
-    // row block i of the panel product P = A_ik W_k, into X
-    int64_t i, j = -1, c = -1;
-    bool inv_side = false;
-    if (e < s.trail) {
-      int64_t ii = (int64_t)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
-      while (ii * (ii + 1) / 2 > e) --ii;
-      while ((ii + 1) * (ii + 2) / 2 <= e) ++ii;
-      i = k + 1 + ii;
-      j = k + 1 + (e - ii * (ii + 1) / 2);
-    } else if (e < s.trail + s.upd_r) {
-      e -= s.trail;
-      i = k + 1 + e / cr;
-      c = e % cr;
-    } else {
-      e -= s.trail + s.upd_r;
-      i = k + 1 + e / (k + 1);
-      c = e % (k + 1);
-      inv_side = true;
-    }
-    (void)t;
-    const int64_t ri = blk_rows(a.n, i);
-    // the tile this item updates, and the second operand: A_jk (trailing tile; the diagonal
-    // tiles reuse A_ik) or the right-hand tile of block row k
-    double* out;
-    const double* src2 = nullptr;
-    int64_t ldo, ld2 = 0, rows2 = kNb, cols;
-    if (j >= 0) {
-      out = a.A + i * kNb * a.lda + j * kNb;
-      ldo = a.lda;
-      cols = blk_rows(a.n, j);
-      if (j != i) {
-        src2 = Ak + j * kNb * a.lda;
-        ld2 = a.lda;
-        rows2 = cols;
-      }
-    } else if (!inv_side) {
-      cols = a.nrhs - c * kNb < kNb ? a.nrhs - c * kNb : kNb;
-      out = a.R + i * kNb * a.ldr + c * kNb;
-      ldo = a.ldr;
-      src2 = a.R + k * kNb * a.ldr + c * kNb;
-      ld2 = a.ldr;
-    } else {
-      cols = blk_rows(a.n, c);
-      out = a.Li + i * kNb * a.ldli + c * kNb;
-      ldo = a.ldli;
-      src2 = a.Li + k * kNb * a.ldli + c * kNb;
-      ld2 = a.ldli;
-    }
-    const int64_t cols2 = j >= 0 ? kNb : cols;
-    // all global loads of the item are issued before the first product
-    double cur[16], nxt[16];
-    {
-      int u = 0;
-      acc_each(acc, [&](int r, int q, double) {
-        const bool ok = r < ri && q < cols;
-        cur[u++] = out[(int64_t)(ok ? r : 0) * ldo + (ok ? q : 0)];
-      });
-    }
-    if (src2) tile_fetch(nxt, src2, ld2, (int)rows2, (int)cols2);
-    tile_load(X, Ak + i * kNb * a.lda, a.lda, (int)ri, kNb);
-    tile_load(Z, Wk, kNb, kNb, kNb);
-    __syncthreads();
-    acc_zero(acc);
-    mm64<false, false>(X, Z, acc);
-    __syncthreads();
-    if (j == i) {
-      // diagonal tile: P into Z, A_ik stays in X as the second operand (transposed)
-      acc_each(acc, [&](int r, int q, double v) { Z[r][q] = v; });
-      __syncthreads();
-      acc_zero(acc);
-      mm64<false, true>(Z, X, acc);
-    } else {
-      acc_each(acc, [&](int r, int q, double v) { X[r][q] = v; });
-      tile_put(Z, nxt);
-      __syncthreads();
-      acc_zero(acc);
-      if (j >= 0) mm64<false, true>(X, Z, acc);
-      else mm64<false, false>(X, Z, acc);
-    }
-    if (j == k + 1 && i == k + 1) {
-      // the critical tile: updated block into X (identity-padded), then factor and invert
-      __syncthreads();
-      int u = 0;
-      acc_each(acc, [&](int r, int q, double v) {
-        const double o = cur[u++];
-        X[r][q] = (r < ri && q < ri) ? o - v : (r == q ? 1.0 : 0.0);
-      });
-      factor_diag_store(X, Z, buf, D0, a, k + 1);
-      return;
-    }
-    int u = 0;
-    acc_each(acc, [&](int r, int q, double v) {
-      const double o = cur[u++];
-      if (r < ri && q < cols) out[(int64_t)r * ldo + q] = o - v;
-    });
-    return;
-  }
-  // in-place scaling of a finished block row f: tile <- Y_f tile
-  e -= s.trail + s.upd_r + s.upd_i;
-  int64_t f, c;
-  bool inv_side;
-  if (e < s.fin_r) {
-    const int64_t first = k >= 1 ? cr : 0;         // items of block row k - 1 come first
-    f = e < first ? k - 1 : k;
-    c = e < first ? e : e - first;
-    inv_side = false;
-  } else {
-    e -= s.fin_r;
-    if (k >= 1 && e < k) {
-      f = k - 1;
-      c = e;
-    } else {
-      f = k;
-      c = e - (k >= 1 ? k : 0);
-    }
-    inv_side = true;
-  }
-  double* tile;
-  int64_t ld, cols;
-  if (!inv_side) {
-    tile = a.R + f * kNb * a.ldr + c * kNb;
-    ld = a.ldr;
-    cols = a.nrhs - c * kNb < kNb ? a.nrhs - c * kNb : kNb;
-  } else {
-    tile = a.Li + f * kNb * a.ldli + c * kNb;
-    ld = a.ldli;
-    cols = blk_rows(a.n, c);
-  }
-  const int64_t rf = blk_rows(a.n, f);
-  tile_load(X, a.Yb + f * kNb * kNb, kNb, kNb, kNb);
-  tile_load(Z, tile, ld, (int)rf, (int)cols);
-  __syncthreads();
-  acc_zero(acc);
-  mm64<false, false>(X, Z, acc);
-  acc_each(acc, [&](int r, int q, double v) {
-    if (r < rf && q < cols) tile[(int64_t)r * ld + q] = v;
-  });
+  chol_step_item(a, k, blockIdx.x);
 }
 
-size_t chol_ws_doubles(int64_t n) {
-  return (size_t)n + 2 * (size_t)ceil_div(n, (int64_t)kNb) * kNb * kNb;
-}
+size_t chol_ws_doubles(int64_t n) { return (size_t)chol_ws_doubles_dev(n); }
 
 int chol_solve_lower(double* A, int64_t n, int64_t lda, double* R, int64_t nrhs, int64_t ldr,
                      double* Linv, int64_t ldli, double* ws, int32_t* st, hipStream_t stream) {

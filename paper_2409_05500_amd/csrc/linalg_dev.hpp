@@ -1,7 +1,5 @@
-// Block-wide FP64 dense linear algebra bodies shared by the single-problem kernels and the
-// batched (one workgroup per problem) kernels: the 64 x 64 diagonal-block factor + inverse of
-// the blocked Cholesky, a 64 x 64 FP64 GEMM tile, and workgroup-level drivers of the blocked
-// factorisation and triangular solves.  Matrices are row-major with explicit leading dimensions.
+// The 64 x 64 diagonal-block factor + inverse of the blocked Cholesky (LDS in, LDS out), shared
+// by the single-problem and the batched factorisation kernels.  Matrices are row-major.
 #pragma once
 #include <math.h>
 
@@ -216,171 +214,6 @@ __device__ __attribute__((always_inline)) inline void block_factor_inv(double (*
     __syncthreads();
   }
   if (bad_any) raise_status(st, VL_ERR_SINGULAR);
-}
-
-// The diagonal block at A (kb x kb, leading dimension lda) factored and inverted: L11 into L
-// (kb x kb, strict upper part written as zero), L11^{-1} into Linv (64 x 64, dense).
-__device__ inline void potf2_inv_block(const double* __restrict__ A, int64_t lda, int kb,
-                                const double* __restrict__ diag0, double* __restrict__ L,
-                                int64_t ldl, double* __restrict__ Linv, int32_t* st) {
-  __shared__ double S[kNb][kLd];
-  __shared__ double Y[kNb][kLd];
-  __shared__ double buf[kFactorBuf];
-  __shared__ double D0[kNb];
-  const int t = threadIdx.x;
-  for (int e = t; e < kNb * kNb; e += 256) {
-    const int r = e >> 6, q = e & 63;
-    S[r][q] = (r < kb && q < kb) ? A[(int64_t)r * lda + q] : (r == q ? 1.0 : 0.0);
-  }
-  if (t < kNb) D0[t] = t < kb ? diag0[t] : 1.0;
-  block_factor_inv(S, Y, buf, D0, st);
-  for (int e = t; e < kNb * kNb; e += 256) {
-    const int r = e >> 6, q = e & 63;
-    if (r < kb && q < kb) L[(int64_t)r * ldl + q] = q <= r ? S[r][q] : 0.0;
-    Linv[e] = q <= r ? Y[r][q] : 0.0;
-  }
-  __syncthreads();
-}
-
-// ------------------------------------------------------------------------------------------
-// C = beta C + alpha op(A) op(B); FP64; 64 x 64 tiles, 256 threads x (4 x 4), K step 16;
-// tri skips the K range a triangular op(A) holds zeros in (i0 and K steps are multiples of 16).
-// op(A) is M x K: transA ? A[k * lda + i] : A[i * lda + k]; op(B) is K x N likewise.
-// lower_only: tiles strictly above the diagonal are skipped (and in diagonal tiles only
-// entries with j <= i are written).
-// ------------------------------------------------------------------------------------------
-__device__ inline void gemm_f64_tile(int64_t M, int64_t N, int64_t K, double alpha,
-                              const double* __restrict__ A, int64_t lda, int transA,
-                              const double* __restrict__ Bm, int64_t ldb, int transB, double beta,
-                              double* __restrict__ C, int64_t ldc, int lower_only, int64_t i0,
-                              int64_t j0, int tri = 0) {
-  __shared__ double As[16][64 + 1];
-  __shared__ double Bs[16][64 + 1];
-  if (lower_only && j0 > i0 + 63) return;
-  const int tid = threadIdx.x, ti = tid >> 4, tj = tid & 15;
-  // this thread's four loads per operand and K step; consecutive threads walk the contiguous
-  // dimension of each operand
-  int ak[4], ai[4], bk[4], bj[4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int e = tid + 256 * u;
-    ak[u] = transA ? e / 64 : e % 16;
-    ai[u] = transA ? e % 64 : e / 16;
-    bk[u] = transB ? e % 16 : e / 64;
-    bj[u] = transB ? e / 16 : e % 64;
-  }
-  auto load = [&](int64_t k0, double (&ra)[4], double (&rb)[4]) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t gi = i0 + ai[u], gk = k0 + ak[u];
-      ra[u] = (gi < M && gk < K) ? (transA ? A[gk * lda + gi] : A[gi * lda + gk]) : 0.0;
-      const int64_t gj = j0 + bj[u], gk2 = k0 + bk[u];
-      rb[u] = (gj < N && gk2 < K) ? (transB ? Bm[gj * ldb + gk2] : Bm[gk2 * ldb + gj]) : 0.0;
-    }
-  };
-  // tri = 1: op(A) lower triangular (terms k > i vanish); tri = 2: upper (k < i vanish)
-  const int64_t kbeg = tri == 2 ? (i0 < K ? i0 : K) : 0;
-  const int64_t kend = tri == 1 ? (i0 + 64 < K ? i0 + 64 : K) : K;
-  double acc[4][4] = {};
-  double ra[4], rb[4];
-  load(kbeg, ra, rb);
-  for (int64_t k0 = kbeg; k0 < kend; k0 += 16) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      As[ak[u]][ai[u]] = ra[u];
-      Bs[bk[u]][bj[u]] = rb[u];
-    }
-    __syncthreads();
-    if (k0 + 16 < kend) load(k0 + 16, ra, rb);   // in flight during the products below
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      double a[4], b[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        a[r] = As[kk][ti + 16 * r];
-        b[r] = Bs[kk][tj + 16 * r];
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[r][q] = fma(a[r], b[q], acc[r][q]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t gi = i0 + ti + 16 * r, gj = j0 + tj + 16 * q;
-      if (gi < M && gj < N && (!lower_only || gj <= gi)) {
-        double* c = C + gi * ldc + gj;
-        *c = (beta == 0.0 ? 0.0 : beta * *c) + alpha * acc[r][q];
-      }
-    }
-}
-
-// ------------------------------------------------------------------------------------------
-// The same factorisation and solves run by ONE workgroup of 256 threads (small matrices, one
-// workgroup per problem of a batch).  Phases are separated by workgroup barriers; the
-// workgroup's own global-memory writes are visible to it after each barrier.
-// ------------------------------------------------------------------------------------------
-__device__ inline void wg_gemm_f64(int64_t M, int64_t N, int64_t K, double alpha, const double* A,
-                            int64_t lda, bool transA, const double* B, int64_t ldb, bool transB,
-                            double beta, double* C, int64_t ldc, bool lower_only) {
-  const int64_t tm = ceil_div(M, 64), tn = ceil_div(N, 64);
-  for (int64_t t = 0; t < tm * tn; ++t)
-    gemm_f64_tile(M, N, K, alpha, A, lda, transA ? 1 : 0, B, ldb, transB ? 1 : 0, beta, C, ldc,
-                  lower_only ? 1 : 0, (t / tn) * 64, (t % tn) * 64);
-  __syncthreads();
-}
-
-__device__ inline void wg_potrf_lower(double* A, int64_t n, int64_t lda, double* L, int64_t ldl,
-                               double* ws, int32_t* st) {
-  double* diag0 = ws;
-  double* inv = ws + n;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) diag0[i] = A[i * lda + i];
-  __syncthreads();
-  for (int64_t k0 = 0; k0 < n; k0 += kNb) {
-    const int kb = (int)(n - k0 < kNb ? n - k0 : kNb);
-    double* invk = inv + (k0 / kNb) * kNb * kNb;
-    potf2_inv_block(A + k0 * lda + k0, lda, kb, diag0 + k0, L + k0 * ldl + k0, ldl, invk, st);
-    const int64_t rest = n - k0 - kb;
-    if (rest <= 0) break;
-    wg_gemm_f64(rest, kb, kb, 1.0, A + (k0 + kb) * lda + k0, lda, false, invk, kNb, true, 0.0,
-                L + (k0 + kb) * ldl + k0, ldl, false);
-    wg_gemm_f64(rest, rest, kb, -1.0, L + (k0 + kb) * ldl + k0, ldl, false,
-                L + (k0 + kb) * ldl + k0, ldl, true, 1.0, A + (k0 + kb) * lda + (k0 + kb), lda,
-                true);
-  }
-}
-
-__device__ inline void wg_trsm_lower(const double* L, int64_t n, int64_t ldl, const double* ws,
-                              bool trans, double* B, int64_t nrhs, int64_t ldb, double* X,
-                              int64_t ldx) {
-  const double* inv = ws + n;
-  const int64_t nblk = ceil_div(n, kNb);
-  if (!trans) {
-    for (int64_t b = 0; b < nblk; ++b) {
-      const int64_t k0 = b * kNb;
-      const int kb = (int)(n - k0 < kNb ? n - k0 : kNb);
-      wg_gemm_f64(kb, nrhs, kb, 1.0, inv + b * kNb * kNb, kNb, false, B + k0 * ldb, ldb, false,
-                  0.0, X + k0 * ldx, ldx, false);
-      const int64_t rest = n - k0 - kb;
-      if (rest > 0)
-        wg_gemm_f64(rest, nrhs, kb, -1.0, L + (k0 + kb) * ldl + k0, ldl, false, X + k0 * ldx,
-                    ldx, false, 1.0, B + (k0 + kb) * ldb, ldb, false);
-    }
-  } else {
-    for (int64_t b = nblk - 1; b >= 0; --b) {
-      const int64_t k0 = b * kNb;
-      const int kb = (int)(n - k0 < kNb ? n - k0 : kNb);
-      wg_gemm_f64(kb, nrhs, kb, 1.0, inv + b * kNb * kNb, kNb, true, B + k0 * ldb, ldb, false,
-                  0.0, X + k0 * ldx, ldx, false);
-      if (k0 > 0)
-        wg_gemm_f64(k0, nrhs, kb, -1.0, L + k0 * ldl, ldl, true, X + k0 * ldx, ldx, false, 1.0, B,
-                    ldb, false);
-    }
-  }
 }
 
 }  // namespace vl
