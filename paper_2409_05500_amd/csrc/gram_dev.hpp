@@ -208,6 +208,9 @@ __device__ inline void gram_tile_f64(
   const float* pa = A + (va ? (mapA ? mapA[ia] : ia) : 0);
   const float* pb = B + (vb ? (mapB ? mapB[jb] : jb) : 0);
   const int wi = wave >> 1, wj = wave & 1;
+  // 16 x 16 blocks wholly in the padding (edge tiles) are skipped (wave-uniform tests)
+  const bool live_a[2] = {i0 + wi * 32 < M, i0 + wi * 32 + 16 < M};
+  const bool live_b[2] = {j0 + wj * 32 < N, j0 + wj * 32 + 16 < N};
   // the means are subtracted after widening (in FP64), per operand column of this lane
   double mua[2], mub[2];
 #pragma unroll
@@ -245,6 +248,7 @@ __device__ inline void gram_tile_f64(
     if (k0 + kGK64 < ke) load(k0 + kGK64);
 #pragma unroll
     for (int kk = 0; kk < kGK64; kk += 4) {
+      if (!(live_a[0] && live_b[0])) break;
       const bool in = k0 + kk + (lane >> 4) < ke;
       double av[2], bv[2];
 #pragma unroll
@@ -258,7 +262,8 @@ __device__ inline void gram_tile_f64(
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+          if (live_a[a] && live_b[b])
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
     __syncthreads();
   }

@@ -90,6 +90,8 @@ __device__ inline void var_residual_tile_f64(
   __shared__ double Cs[16][64 + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wi = wave >> 1, wj = wave & 1;
+  const bool live_a[2] = {t0 + wi * 32 < n_eff, t0 + wi * 32 + 16 < n_eff};
+  const bool live_b[2] = {j0 + wj * 32 < m, j0 + wj * 32 + 16 < m};
   const int64_t dz = m * p;
   const int64_t* mapZ = colmap + m;
   const double* muZ = mu + m;
@@ -143,7 +145,8 @@ __device__ inline void var_residual_tile_f64(
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+          if (live_a[a] && live_b[b])   // 16 x 16 blocks wholly in the padding are skipped
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
     __syncthreads();
   }
