@@ -167,13 +167,13 @@ __device__ inline void var_residual_tile_f64(
 
 // ------------------------------------------------------------------------------------------
 // Wide FP64 residual tile: 128 samples x 64 variables per workgroup; wave (wi, wj) of the 2 x 2
-// waves owns 64 x 32 = 4 x 2 blocks of v_mfma_f64_16x16x4f64.  Stages of 32 lags through LDS
+// waves owns 64 x 32 = 4 x 2 blocks of v_mfma_f64_16x16x4f64.  Stages of kRK lags through LDS
 // (the centred lag values widened to FP64 once, at load); the next stage's global loads are in
 // flight during the products.  Same arithmetic and result as var_residual_tile_f64.
 // ------------------------------------------------------------------------------------------
 constexpr int kRT = 128;       // samples per tile
 constexpr int kRJ = 64;        // variables per tile
-constexpr int kRK = 32;        // lags per stage
+constexpr int kRK = 16;        // lags per stage
 constexpr int kRZ = kRT + 1;   // LDS row strides (doubles)
 constexpr int kRC = kRJ + 1;
 
@@ -194,9 +194,11 @@ __device__ inline void var_residual_tile_f64w(
   for (int x = 0; x < 4; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = f64x4{0.0, 0.0, 0.0, 0.0};
-  const int zk = tid & 31, zt = tid >> 5;      // Z loader: 32 lags x 8 sample rows per pass
+  constexpr int kZRows = 256 / kRK;            // Z loader: kRK lags x kZRows sample rows a pass
+  constexpr int kZPass = kRT / kZRows;
+  const int zk = tid % kRK, zt = tid / kRK;
   const int cj = tid & 63, ck = tid >> 6;      // Coef loader: 64 variables x 4 lags per pass
-  double rz[kRT / 8], rc[kRK / 4];
+  double rz[kZPass], rc[kRK / 4];
   // Every load reads a clamped in-bounds address and the padding is selected afterwards, so
   // the loads of a stage issue back to back (no branch, no wait per load).
   const int64_t jc = j0 + cj < m ? j0 + cj : m - 1;
@@ -206,10 +208,10 @@ __device__ inline void var_residual_tile_f64w(
     const bool vk = k < dz;
     const int64_t off = mapZ[vk ? k : dz - 1];
     const double mz = vk ? muZ[k] : 0.0;
-    float xv[kRT / 8];
+    float xv[kZPass];
 #pragma unroll
-    for (int u = 0; u < kRT / 8; ++u) {
-      const int64_t t = t0 + zt + 8 * u;
+    for (int u = 0; u < kZPass; ++u) {
+      const int64_t t = t0 + zt + kZRows * u;
       xv[u] = X[off + (t < n_eff ? t : n_eff - 1) * ldx];
     }
 #pragma unroll
@@ -219,15 +221,15 @@ __device__ inline void var_residual_tile_f64w(
       rc[u] = mask_f64(cv, kq < dz && vj);
     }
 #pragma unroll
-    for (int u = 0; u < kRT / 8; ++u) {
-      const int64_t t = t0 + zt + 8 * u;
+    for (int u = 0; u < kZPass; ++u) {
+      const int64_t t = t0 + zt + kZRows * u;
       rz[u] = mask_f64((double)xv[u] - mz, vk && t < n_eff);
     }
   };
   load(0);
   for (int64_t k0 = 0; k0 < dz; k0 += kRK) {
 #pragma unroll
-    for (int u = 0; u < kRT / 8; ++u) Zs[zk][zt + 8 * u] = rz[u];
+    for (int u = 0; u < kZPass; ++u) Zs[zk][zt + kZRows * u] = rz[u];
 #pragma unroll
     for (int u = 0; u < kRK / 4; ++u) Cs[ck + 4 * u][cj] = rc[u];
     __syncthreads();
