@@ -6,9 +6,10 @@ stream).  Workload: m = 400 variables, n = 10000 samples, p = 2, Student-t(4) sh
 
 Prints ONE JSON line.  value = ordered-pair sample-evaluations per second of the whole step
 (m (m - 1) (n - p) per step / step time).  The line also carries the pairwise kernel's own
-rate, the stage breakdown, the plain-FP32 step time, the roofline of the dominant kernel
-(from HIP events recorded on its launch stream during the timed loop) and the oracle's CPU
-rate on a bounded sample.
+rate, the stage breakdown, the plain-FP32 and BF16 step times, the roofline of the dominant
+kernel (from HIP events recorded on its launch stream during the timed loop), the oracle's CPU
+rate on a bounded sample, and sections for the original iterative DirectLiNGAM search on the
+same residuals, the 256-problem batched workload and the score backward.
 """
 from __future__ import annotations
 
@@ -130,6 +131,29 @@ def bench_batched(api, torch, steps: int, seed: int):
     return out
 
 
+def bench_iterative(api, torch, E, stage_ms, steps):
+    """The original iterative DirectLiNGAM search (Sec. 3 steps 1-5) on the fit's residuals,
+    against the heuristic's precompute + ordering stages of the same fit."""
+    n_eff, m = E.shape
+    api.order_iterative(E)                          # warm-up (and status check)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(steps):
+        order, _ = api.order_iterative(E)
+    t1.record()
+    torch.cuda.synchronize()
+    it_ms = t0.elapsed_time(t1) / steps
+    heur = sum(stage_ms.get(k, 0.0) for k in ("pairwise_cov", "pairwise_prep", "pairwise_moments",
+                                              "pairwise_combine", "order"))
+    evals = sum(u * (u - 1) for u in range(2, m + 1)) * n_eff
+    return {"m": m, "n_eff": n_eff, "ms": it_ms, "sample_evals": evals,
+            "sample_evals_per_s": evals / (it_ms / 1e3),
+            "heuristic_precompute_plus_order_ms": heur,
+            "speedup_heuristic_vs_iterative": it_ms / heur if heur else None}
+
+
 def bench_backward(api, _lib, torch, steps: int, seed: int):
     """Gradient of the score matrix, dE = d<G, S(E)>/dE, at m = 1000, n = 50000 (Laplace
     shocks, p = 1): E is the GPU VAR fit's residual matrix, G a seeded N(0, 1) cotangent.
@@ -195,6 +219,8 @@ def main():
                     help="skip the batched-workload section (256 uneven problems)")
     ap.add_argument("--no-backward", action="store_true",
                     help="skip the score-gradient section (m = 1000, n = 50000)")
+    ap.add_argument("--no-iterative", action="store_true",
+                    help="skip the original iterative DirectLiNGAM search on the fit's residuals")
     ap.add_argument("--only", choices=("batch", "backward"), default=None,
                     help="profiling runs: run just one extra section and print its JSON")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -312,6 +338,8 @@ def main():
         "bf16_vs_mixed": bf16_dev,
         "stage_ms": stage_ms,
     }
+    if not args.no_iterative:
+        out["iterative"] = bench_iterative(api, torch, fit.E, stage_ms, 3)
     if not args.no_batch:
         out["batched"] = bench_batched(api, torch, max(3, args.steps // 2), args.seed)
     if not args.no_backward:

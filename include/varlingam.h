@@ -150,6 +150,29 @@ int approx_order(const double* S, int64_t m, int32_t* order, double* margin, voi
                  size_t ws_bytes, int32_t* dev_status, void* stream);
 
 /* ------------------------------------------------------------------------------------- */
+/* The original iterative DirectLiNGAM ordering (Sec. 3 steps 1-5), the search the       */
+/* heuristic replaces: at step k, with U the variables not yet ordered and x_i their       */
+/* current data, the pairwise scores S are recomputed on the current data exactly as       */
+/* pairwise_stats does, c_k = argmin_{i in U} sum_{j in U, j != i} min(0, S[i,j])^2 (exact */
+/* ties -> lowest index), and every other variable of U is replaced by its residual on     */
+/* x_{c_k}, taken between the standardised columns (population moments):                 */
+/*   x_j <- std(x_j) - rho_{j,c_k} std(x_{c_k}).                                           */
+/* O(m^3 n) work: one pairwise pass over the remaining variables per step.                 */
+/* E        in, n_eff x m float32 (leading dimension lde >= m), not modified.              */
+/* prec     VL_PREC_FP32, VL_PREC_MIXED or VL_PREC_BF16 as for pairwise_stats.             */
+/* order    out, m int32: order[k] = c_k (original variable index).                        */
+/* margin   out, m float64: second-smallest minus smallest aggregate at step k; +inf at    */
+/*          the last step.                                                                  */
+/* Host errors: m < 1, m > 4096 or n_eff < 2 -> VL_ERR_SHAPE.  Status: as pairwise_stats   */
+/* (a variable that becomes constant or collinear after the residual updates is           */
+/* VL_ERR_DEGENERATE).                                                                     */
+/* ------------------------------------------------------------------------------------- */
+size_t varlingam_order_iterative_workspace_bytes(int64_t n_eff, int64_t m, int prec);
+int varlingam_order_iterative(const float* E, int64_t n_eff, int64_t m, int64_t lde, int prec,
+                              int32_t* order, double* margin, void* ws, size_t ws_bytes,
+                              int32_t* dev_status, void* stream);
+
+/* ------------------------------------------------------------------------------------- */
 /* B0 and lag matrices from the order (Sec. 4: estimation of the instantaneous matrix B0; */
 /* Sec. 2.1: VarLiNGAM lag matrices).                                                     */
 /*   B0[K_k, K_<k] = least-squares coefficients of e_{K_k} on its predecessors, obtained   */

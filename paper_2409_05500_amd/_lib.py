@@ -48,6 +48,8 @@ SIGNATURES = {
                                        _p, _p]),
     "approx_order_workspace_bytes": (_sz, [_i64]),
     "approx_order": (_i32, [_p, _i64, _p, _p, _p, _sz, _p, _p]),
+    "varlingam_order_iterative_workspace_bytes": (_sz, [_i64, _i64, _i32]),
+    "varlingam_order_iterative": (_i32, [_p, _i64, _i64, _i64, _i32, _p, _p, _p, _sz, _p, _p]),
     "estimate_B_workspace_bytes": (_sz, [_i64, _i32]),
     "estimate_B": (_i32, [_p, _p, _p, _i64, _i32, _p, _p, _p, _sz, _p, _p]),
     "varlingam_batch_create": (_i32, [C.POINTER(VlInstance), _i32, _i32,

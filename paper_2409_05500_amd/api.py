@@ -181,6 +181,25 @@ def approx_order(S: torch.Tensor, status: "DeviceStatus | None" = None):
     return order, margin
 
 
+def order_iterative(E: torch.Tensor, prec="mixed", status: "DeviceStatus | None" = None):
+    """(order [m] int32, margin [m] f64) of the original iterative DirectLiNGAM search on the
+    n_eff x m residuals (the pairwise scores recomputed on the updated data at every step)."""
+    _require(E, torch.float32, "E")
+    n_eff, m = E.shape
+    dev = E.device
+    order = torch.empty(m, dtype=torch.int32, device=dev)
+    margin = torch.empty(m, dtype=torch.float64, device=dev)
+    ws = _workspace(lib.varlingam_order_iterative_workspace_bytes(n_eff, m, _prec(prec)), dev)
+    st = status if status is not None else DeviceStatus(dev)
+    check(lib.varlingam_order_iterative(E.data_ptr(), n_eff, m, E.stride(0), _prec(prec),
+                                        order.data_ptr(), margin.data_ptr(), ws.data_ptr(),
+                                        ws.numel(), st.ptr, _stream_ptr(dev)),
+          "varlingam_order_iterative")
+    if status is None:
+        st.read("varlingam_order_iterative")
+    return order, margin
+
+
 def estimate_B(Cov: torch.Tensor, M: torch.Tensor, order: torch.Tensor,
                status: "DeviceStatus | None" = None):
     """(B0 [m, m], B_lags [p, m, m]) f64 from the residual covariance, VAR matrices and order."""

@@ -1,6 +1,7 @@
 // extern "C" entry points: argument validation, workspace carving, status handling.
 #include "backward.hpp"
 #include "estimate_b.hpp"
+#include "iterative.hpp"
 #include "order.hpp"
 #include "pairwise.hpp"
 #include "var_fit.hpp"
@@ -86,6 +87,29 @@ int pairwise_stats(const float* E, int64_t n_eff, int64_t m, int64_t lde, int pr
   int rc = begin(dev_status, s);
   if (rc) return rc;
   return run_pairwise(p, w, E, lde, prec, Hx, Hr, S, Cov, nullptr, dev_status, s);
+}
+
+// ----------------------------------------------------------------------------------------
+size_t varlingam_order_iterative_workspace_bytes(int64_t n_eff, int64_t m, int prec) {
+  (void)prec;
+  if (m < 1 || m > 4096 || n_eff < 2) return 0;
+  return iter_ws_bytes(n_eff, m, nullptr, nullptr);
+}
+
+int varlingam_order_iterative(const float* E, int64_t n_eff, int64_t m, int64_t lde, int prec,
+                              int32_t* order, double* margin, void* ws, size_t ws_bytes,
+                              int32_t* dev_status, void* stream) {
+  if (!E || !order || !margin || !dev_status || !valid_prec(prec)) return VL_ERR_INVALID_ARG;
+  if (m < 1 || m > 4096 || n_eff < 2) return VL_ERR_SHAPE;
+  if (lde < m) return VL_ERR_INVALID_ARG;
+  const size_t need = iter_ws_bytes(n_eff, m, nullptr, nullptr);
+  if (!ws || ws_bytes < need || !aligned256(ws)) return VL_ERR_WORKSPACE;
+  IterWs w;
+  iter_ws_bytes(n_eff, m, ws, &w);
+  hipStream_t s = as_stream(stream);
+  int rc = begin(dev_status, s);
+  if (rc) return rc;
+  return run_order_iterative(E, n_eff, m, lde, prec, order, margin, w, dev_status, s);
 }
 
 // ----------------------------------------------------------------------------------------

@@ -49,3 +49,33 @@ def b_rel_error(B, B_ref):
     B_ref = np.asarray(B_ref, dtype=np.float64)
     floor = 1e-2 * max(np.max(np.abs(B_ref)), 1e-300)
     return float(np.max(np.abs(B - B_ref) / np.maximum(np.abs(B_ref), floor)))
+
+
+def iterative_order_violations(order, E, tie=ORDER_TIE):
+    """Walk a GPU order of the original iterative DirectLiNGAM search (Sec. 3 steps 1-5) with
+    the oracle's arithmetic: at each step the oracle's aggregates on its current data must put
+    the GPU's pick within `tie` of their minimum; the oracle's data is then refined with the
+    GPU's pick.  Returns the list of (step, gpu_pick, gap) that fail."""
+    X = np.array(E, dtype=np.float64, copy=True)
+    m = X.shape[1]
+    U = list(range(m))
+    bad = []
+    for k, c in enumerate(np.asarray(order).tolist()):
+        if c not in U:
+            bad.append((k, c, np.inf))
+            break
+        if len(U) == 1:
+            break
+        Xs = {i: O.standardize(X[:, i]) for i in U}
+        H = {i: O.entropy(Xs[i]) for i in U}
+        Hr = {(i, j): O.entropy(O.standardize(O.residual(Xs[i], Xs[j])))
+              for i in U for j in U if i != j}
+        M = {i: sum(min(0.0, (H[j] + Hr[i, j]) - (H[i] + Hr[j, i])) ** 2 for j in U if j != i)
+             for i in U}
+        gap = float(M[c] - min(M.values()))
+        if gap > tie:
+            bad.append((k, c, gap))
+        U.remove(c)
+        for j in U:
+            X[:, j] = O.residual(Xs[j], Xs[c])
+    return bad
