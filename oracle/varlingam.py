@@ -26,14 +26,19 @@ Readings where the paper is silent (each is also listed in the design notes):
 * "the data matrix X" of Alg. 1 is the VAR residual matrix;
 * the VAR model includes an intercept and uses the given lag order p;
 * B0 is the least-squares regression (with intercept) of each variable on its predecessors in
-  the order; B_tau = (I - B0) M_tau.
+  the order; B_tau = (I - B0) M_tau;
+* lag-order selection (before the fit; the paper fixes p): every candidate p on the common
+  sample t = p_max .. n-1, AIC / BIC of Lutkepohl (2005) with the maximum-likelihood residual
+  covariance (divisor T) and p m^2 counted parameters.
 
 Pinned by (tests marked "not gpu"): quadrature population values of H for five laws, the
 unit-Gaussian special case, residual orthogonality identities, antisymmetry / invariance /
 equivariance of S, a hand-built total-order S, m = 2 identity with the iterative algorithm and
 equal first picks for any m, tiny-m agreement with the iterative algorithm, recovery of the
 generating order, VAR orthogonality and the AR(1) closed form, the exact OLS identity
-(I - B0) Sigma (I - B0)^T diagonal, and the generator identity (I - B0) M_tau = B_tau.
+(I - B0) Sigma (I - B0)^T diagonal, the generator identity (I - B0) M_tau = B_tau, and for the
+lag selection the univariate closed form, nested monotonicity, scale invariance and recovery
+of the generating lag order by BIC on long series.
 Parity unpinned: the literal digits of k1 and gamma (pinned by citation of the published
 constants only).
 """
@@ -261,6 +266,39 @@ def fit_var(X: np.ndarray, p: int):
     c = coef[-1].copy()
     E = Y - Z @ coef
     return M, c, E
+
+
+def select_lag(X: np.ndarray, p_max: int) -> dict:
+    """VAR lag-order selection for the fit of Sec. 2.1 (the paper fixes p; this is the step
+    before it).  Every p = 1 .. p_max is fitted by least squares with intercept on the same
+    sample t = p_max .. n-1 (T = n - p_max rows), and scored with the maximum-likelihood
+    residual covariance Sigma_p = E_p^T E_p / T:
+        AIC(p) = ln det Sigma_p + 2 p m^2 / T,   BIC(p) = ln det Sigma_p + ln(T) p m^2 / T
+    (Lutkepohl 2005, Sec. 4.3; the m intercepts are common to every p and not counted).
+    Returns ln det Sigma_p, AIC, BIC (arrays over p) and the p minimising each (lowest p on
+    ties)."""
+    X = np.asarray(X, dtype=np.float64)
+    n, m = X.shape
+    if p_max < 1 or n - p_max <= m * p_max + 1:
+        raise ValueError("lag selection needs p_max >= 1 and n - p_max > m p_max + 1")
+    T = n - p_max
+    Y = X[p_max:]
+    logdet, aic, bic = [], [], []
+    for p in range(1, p_max + 1):
+        Z = np.hstack([X[p_max - tau: n - tau] for tau in range(1, p + 1)] + [np.ones((T, 1))])
+        coef, _, rank, _ = np.linalg.lstsq(Z, Y, rcond=None)
+        if rank < Z.shape[1]:
+            raise ValueError("singular VAR design")
+        E = Y - Z @ coef
+        sign, ld = np.linalg.slogdet(E.T @ E / T)
+        if sign <= 0:
+            raise ValueError("singular residual covariance")
+        logdet.append(ld)
+        aic.append(ld + 2.0 * p * m * m / T)
+        bic.append(ld + math.log(T) * p * m * m / T)
+    aic, bic = np.array(aic), np.array(bic)
+    return {"logdet": np.array(logdet), "aic": aic, "bic": bic,
+            "p_aic": int(np.argmin(aic)) + 1, "p_bic": int(np.argmin(bic)) + 1}
 
 
 # ---------------------------------------------------------------------------------------------
