@@ -83,3 +83,22 @@ def test_white_noise_picks_the_smallest_lag():
 def test_generator_series():
     inst = synth.make_custom(6, 8000, 2, "laplace", 8, edge_prob=0.2, w_lo=0.1, w_hi=0.4)
     assert O.select_lag(inst.X_parity, 4)["p_bic"] == 2
+
+
+def test_penalty_per_lag_matches_the_likelihood_ratio_degrees_of_freedom():
+    """Wilks: when the extra lag is superfluous, T (ln det Sigma_p - ln det Sigma_{p+1}) is
+    asymptotically chi-square with one degree of freedom per added coefficient.  Its Monte
+    Carlo mean over VAR(1) series fixes that count (m^2 = 9 here, against m = 3 or 2 m^2), and
+    the criteria's increments per lag must be 2 (AIC) and ln T (BIC) times it, over T."""
+    m, n, R = 3, 600, 300
+    drops, d_aic, d_bic = [], [], []
+    for r in range(R):
+        res = O.select_lag(_var_series(m, n, 1, 1000 + r), 2)
+        T = n - 2
+        drops.append(T * (res["logdet"][0] - res["logdet"][1]))
+        d_aic.append(T * ((res["aic"][1] - res["logdet"][1]) - (res["aic"][0] - res["logdet"][0])))
+        d_bic.append(T * ((res["bic"][1] - res["logdet"][1]) - (res["bic"][0] - res["logdet"][0])))
+    dof = float(np.mean(drops))          # chi2_9: mean 9, standard error sqrt(18 / R) = 0.25
+    assert abs(dof - m * m) < 1.2, dof
+    assert abs(np.mean(d_aic) - 2 * dof) < 2.4
+    assert abs(np.mean(d_bic) - math.log(n - 2) * dof) < 1.2 * math.log(n - 2)
