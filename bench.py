@@ -9,7 +9,8 @@ Prints ONE JSON line.  value = ordered-pair sample-evaluations per second of the
 rate, the stage breakdown, the plain-FP32 and BF16 step times, the roofline of the dominant
 kernel (from HIP events recorded on its launch stream during the timed loop), the oracle's CPU
 rate on a bounded sample, and sections for the original iterative DirectLiNGAM search on the
-same residuals, the 256-problem batched workload and the score backward.
+same residuals, VAR lag-order selection on the same series, the 256-problem batched workload
+and the score backward.
 """
 from __future__ import annotations
 
@@ -154,6 +155,50 @@ def bench_iterative(api, torch, E, stage_ms, steps):
             "speedup_heuristic_vs_iterative": it_ms / heur if heur else None}
 
 
+def bench_lag_select(api, torch, X, p_max, steps):
+    """VAR lag-order selection over p = 1 .. p_max (one Gram of the p_max design, one fused
+    factorisation, scores from the leading blocks), against p_max separate VAR fits."""
+    n, m = X.shape
+    api.select_lag(X, p_max)                        # warm-up (and status check)
+    for p in range(1, p_max + 1):
+        api.fit_var(X, p)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(steps):
+            fn()
+        t1.record()
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1) / steps
+
+    # the C entry point with preallocated outputs, so that no call synchronises; one status
+    # word, read after the loops
+    from paper_2409_05500_amd._lib import lib
+    dev = X.device
+    outs = [torch.empty(p_max, dtype=torch.float64, device=dev) for _ in range(3)]
+    best = torch.empty(2, dtype=torch.int32, device=dev)
+    nb = lib.varlingam_select_lag_workspace_bytes(n, m, p_max)
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    st = api.DeviceStatus(dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+
+    def select():
+        rc = lib.varlingam_select_lag(X.data_ptr(), n, m, X.stride(0), p_max,
+                                      *[o.data_ptr() for o in outs], best.data_ptr(),
+                                      ws.data_ptr(), nb, st.ptr, stream)
+        assert rc == 0, rc
+
+    sel_ms = timed(select)
+    loop_ms = timed(lambda: [api.fit_var(X, p, status=st) for p in range(1, p_max + 1)])
+    st.read("lag selection bench")
+    _, _, _, (pa, pb) = api.select_lag(X, p_max)
+    return {"m": m, "n": n, "p_max": p_max, "ms": sel_ms, "separate_fits_ms": loop_ms,
+            "p_aic": pa, "p_bic": pb}
+
+
 def bench_backward(api, _lib, torch, steps: int, seed: int):
     """Gradient of the score matrix, dE = d<G, S(E)>/dE, at m = 1000, n = 50000 (Laplace
     shocks, p = 1): E is the GPU VAR fit's residual matrix, G a seeded N(0, 1) cotangent.
@@ -221,6 +266,8 @@ def main():
                     help="skip the score-gradient section (m = 1000, n = 50000)")
     ap.add_argument("--no-iterative", action="store_true",
                     help="skip the original iterative DirectLiNGAM search on the fit's residuals")
+    ap.add_argument("--no-lag-select", action="store_true",
+                    help="skip the VAR lag-order selection section")
     ap.add_argument("--only", choices=("batch", "backward"), default=None,
                     help="profiling runs: run just one extra section and print its JSON")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -340,6 +387,8 @@ def main():
     }
     if not args.no_iterative:
         out["iterative"] = bench_iterative(api, torch, fit.E, stage_ms, 3)
+    if not args.no_lag_select:
+        out["lag_select"] = bench_lag_select(api, torch, X, 2 * p, 5)
     if not args.no_batch:
         out["batched"] = bench_batched(api, torch, max(3, args.steps // 2), args.seed)
     if not args.no_backward:

@@ -83,6 +83,26 @@ int varlingam_fit_var(const float* X, int64_t n, int64_t m, int64_t ldx, int p, 
                       size_t ws_bytes, int32_t* dev_status, void* stream);
 
 /* ------------------------------------------------------------------------------------- */
+/* VAR lag-order selection, the step before the fit (Sec. 2.1 fits a VAR model with a     */
+/* given p; the paper does not choose it).  Every p = 1 .. p_max is fitted by least        */
+/* squares with intercept on the same sample t = p_max .. n-1 (T = n - p_max rows) and     */
+/* scored with the maximum-likelihood residual covariance Sigma_p = E_p^T E_p / T:         */
+/*   AIC(p) = ln det Sigma_p + 2 p m^2 / T,   BIC(p) = ln det Sigma_p + ln(T) p m^2 / T     */
+/* (Lutkepohl 2005; the m intercepts, common to every p, are not counted).  FP64 Gram      */
+/* (exact products of the FP32 data) and FP64 factorisations throughout.                   */
+/* X       in, n x m float32 (leading dimension ldx >= m).                                  */
+/* logdet, aic, bic  out, p_max float64 each (entry p - 1 for lag order p).                 */
+/* best    out, 2 int32: the p minimising AIC and BIC (lowest p on ties).                   */
+/* Host errors: m < 1, p_max < 1, n - p_max <= m p_max + 1 or m p_max > 4096 ->            */
+/* VL_ERR_SHAPE.  Status: VL_ERR_NONFINITE, VL_ERR_SINGULAR (a singular design or residual */
+/* covariance).                                                                            */
+/* ------------------------------------------------------------------------------------- */
+size_t varlingam_select_lag_workspace_bytes(int64_t n, int64_t m, int p_max);
+int varlingam_select_lag(const float* X, int64_t n, int64_t m, int64_t ldx, int p_max,
+                         double* logdet, double* aic, double* bic, int32_t* best, void* ws,
+                         size_t ws_bytes, int32_t* dev_status, void* stream);
+
+/* ------------------------------------------------------------------------------------- */
 /* Precompute of every pairwise statistic, once (Sec. 4.2 steps 1-2; Alg. 1 first two     */
 /* lines), from the unaltered residual matrix.                                            */
 /*                                                                                        */

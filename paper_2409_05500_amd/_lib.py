@@ -38,6 +38,9 @@ SIGNATURES = {
     "varlingam_fit_var_workspace_bytes": (_sz, [_i64, _i64, _i32, _i32]),
     "varlingam_fit_var": (_i32, [_p, _i64, _i64, _i64, _i32, _i32, _p, _p, _p, _i64, _p, _sz,
                                  _p, _p]),
+    "varlingam_select_lag_workspace_bytes": (_sz, [_i64, _i64, _i32]),
+    "varlingam_select_lag": (_i32, [_p, _i64, _i64, _i64, _i32, _p, _p, _p, _p, _p, _sz, _p,
+                                    _p]),
     "pairwise_stats_workspace_bytes": (_sz, [_i64, _i64, _i32]),
     "pairwise_stats": (_i32, [_p, _i64, _i64, _i64, _i32, _p, _p, _p, _p, _p, _sz, _p, _p]),
     "pairwise_stats_backward_workspace_bytes": (_sz, [_i64, _i64, _i32]),

@@ -73,6 +73,28 @@ def fit_var(X: torch.Tensor, p: int, prec="mixed", status: "DeviceStatus | None"
     return M, c, E
 
 
+def select_lag(X: torch.Tensor, p_max: int, status: "DeviceStatus | None" = None):
+    """VAR lag-order selection over p = 1 .. p_max on the common sample t = p_max .. n-1:
+    (logdet [p_max], aic [p_max], bic [p_max]) f64 and (p_AIC, p_BIC)."""
+    _require(X, torch.float32, "X")
+    n, m = X.shape
+    dev = X.device
+    logdet = torch.empty(p_max, dtype=torch.float64, device=dev)
+    aic = torch.empty(p_max, dtype=torch.float64, device=dev)
+    bic = torch.empty(p_max, dtype=torch.float64, device=dev)
+    best = torch.empty(2, dtype=torch.int32, device=dev)
+    ws = _workspace(lib.varlingam_select_lag_workspace_bytes(n, m, p_max), dev)
+    st = status if status is not None else DeviceStatus(dev)
+    check(lib.varlingam_select_lag(X.data_ptr(), n, m, X.stride(0), p_max, logdet.data_ptr(),
+                                   aic.data_ptr(), bic.data_ptr(), best.data_ptr(),
+                                   ws.data_ptr(), ws.numel(), st.ptr, _stream_ptr(dev)),
+          "varlingam_select_lag")
+    if status is None:
+        st.read("varlingam_select_lag")
+    b = best.cpu().tolist()
+    return logdet, aic, bic, (int(b[0]), int(b[1]))
+
+
 def pairwise_stats(E: torch.Tensor, prec="mixed", status: "DeviceStatus | None" = None):
     """Hx [m], Hr [m, m], S [m, m], Cov [m, m] (all f64) from the n_eff x m residuals."""
     _require(E, torch.float32, "E")

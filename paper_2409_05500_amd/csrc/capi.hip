@@ -66,6 +66,29 @@ int varlingam_fit_var(const float* X, int64_t n, int64_t m, int64_t ldx, int p, 
 }
 
 // ----------------------------------------------------------------------------------------
+size_t varlingam_select_lag_workspace_bytes(int64_t n, int64_t m, int p_max) {
+  if (m < 1 || p_max < 1 || n - p_max <= m * p_max + 1 || m * p_max > 4096) return 0;
+  return lag_ws_bytes(plan_var(n, m, p_max), nullptr, nullptr);
+}
+
+int varlingam_select_lag(const float* X, int64_t n, int64_t m, int64_t ldx, int p_max,
+                         double* logdet, double* aic, double* bic, int32_t* best, void* ws,
+                         size_t ws_bytes, int32_t* dev_status, void* stream) {
+  if (!X || !logdet || !aic || !bic || !best || !dev_status) return VL_ERR_INVALID_ARG;
+  if (m < 1 || p_max < 1 || n - p_max <= m * p_max + 1 || m * p_max > 4096) return VL_ERR_SHAPE;
+  if (ldx < m) return VL_ERR_INVALID_ARG;
+  const VarPlan v = plan_var(n, m, p_max);
+  const size_t need = lag_ws_bytes(v, nullptr, nullptr);
+  if (!ws || ws_bytes < need || !aligned256(ws)) return VL_ERR_WORKSPACE;
+  LagWs w;
+  lag_ws_bytes(v, ws, &w);
+  hipStream_t s = as_stream(stream);
+  int rc = begin(dev_status, s);
+  if (rc) return rc;
+  return run_lag_select(v, w, X, ldx, logdet, aic, bic, best, dev_status, s);
+}
+
+// ----------------------------------------------------------------------------------------
 size_t pairwise_stats_workspace_bytes(int64_t n_eff, int64_t m, int prec) {
   (void)prec;
   if (m < 2 || n_eff < 2 || m > 65536) return 0;

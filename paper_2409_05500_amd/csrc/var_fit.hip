@@ -175,13 +175,12 @@ static int var_residual(const VarPlan& v, const VarWs& w, const float* X, int64_
   return VL_OK;
 }
 
-int run_var(const VarPlan& v, const VarWs& w, const float* X, int64_t ldx, int prec, double* M,
-            double* intercept, float* E, int64_t lde, int32_t* st, hipStream_t stream) {
+// Column map, means, G = Zc^T Zc and R = Zc^T Yc (R into Tmp, where the forward substitution
+// of the factorisation works on it).
+static int var_normal_equations(const VarPlan& v, const VarWs& w, const float* X, int64_t ldx,
+                                GramMode gmode, int32_t* st, hipStream_t stream) {
   const int64_t m = v.m, dz = v.dz, n_eff = v.n_eff;
   const int64_t nc = m * (v.p + 1);
-  const bool plain = prec == VL_PREC_FP32;
-  const bool refine = prec == VL_PREC_BF16;
-  const GramMode gmode = plain ? GramMode::kFp32 : refine ? GramMode::kBf16 : GramMode::kFp64;
   const int64_t* mapZ = w.colmap + m;
   const double* muZ = w.mu + m;
   int rc;
@@ -193,7 +192,7 @@ int run_var(const VarPlan& v, const VarWs& w, const float* X, int64_t ldx, int p
     VL_LAUNCH_CHECK();
     rc = colmeans(X, ldx, w.colmap, nc, n_eff, w.mu, w.scratch, st, stream);
     if (rc) return rc;
-    // G = Zc^T Zc, R = Zc^T Yc (R goes straight into Coef, solved in place)
+    // G = Zc^T Zc, R = Zc^T Yc (R into Tmp, where the substitution works on it)
     rc = gram_tn(X, ldx, mapZ, muZ, dz, X, ldx, mapZ, muZ, dz, n_eff, gmode, 1.0, w.G, dz,
                  w.scratch, stream, true);
     if (rc) return rc;
@@ -201,8 +200,21 @@ int run_var(const VarPlan& v, const VarWs& w, const float* X, int64_t ldx, int p
                  w.scratch, stream);
     if (rc) return rc;
   }
+  return VL_OK;
+}
+
+int run_var(const VarPlan& v, const VarWs& w, const float* X, int64_t ldx, int prec, double* M,
+            double* intercept, float* E, int64_t lde, int32_t* st, hipStream_t stream) {
+  const int64_t m = v.m, dz = v.dz, n_eff = v.n_eff;
+  const bool plain = prec == VL_PREC_FP32;
+  const bool refine = prec == VL_PREC_BF16;
+  const GramMode gmode = plain ? GramMode::kFp32 : refine ? GramMode::kBf16 : GramMode::kFp64;
+  const int64_t* mapZ = w.colmap + m;
+  const double* muZ = w.mu + m;
+  int rc = var_normal_equations(v, w, X, ldx, gmode, st, stream);
+  if (rc) return rc;
   {
-    // G = L L^T with Tmp <- L^{-1} R and Linv = L^{-1} in the same pass; Coef = L^{-T} Tmp
+    // G = L L^T with Tmp <- L^{-1} R and L <- L^{-1} in the same pass; Coef = L^{-T} Tmp
     ProfileScope ps("var_solve", stream);
     rc = chol_solve_lower(w.G, dz, dz, w.Tmp, m, m, w.L, dz, w.chol, st, stream);
     if (rc) return rc;
@@ -243,6 +255,103 @@ int run_var(const VarPlan& v, const VarWs& w, const float* X, int64_t ldx, int p
   VL_LAUNCH_CHECK();
   var_intercept_kernel<<<(unsigned)ceil_div(m, 4), 256, 0, stream>>>(w.Coef, w.mu, m, dz,
                                                                     intercept);
+  VL_LAUNCH_CHECK();
+  return VL_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// Lag-order selection, the step before the fit (the paper fixes p): every p = 1 .. p_max on the
+// common sample t = p_max .. n-1 (T rows), scored with the ML residual covariance Sigma_p:
+//   AIC(p) = ln det Sigma_p + 2 p m^2 / T,   BIC(p) = ln det Sigma_p + ln(T) p m^2 / T.
+// On a common sample the lag-p normal equations are the leading (p m) block of the lag-p_max
+// ones, and the Cholesky factor of a leading block is the leading block of the factor, so one
+// Gram and one factorisation serve every p: with W = L^{-1} R (rows in lag blocks W_1, W_2, ..)
+//   T Sigma_p = Yc^T Yc - R_p^T G_p^{-1} R_p = Yc^T Yc - sum_{tau <= p} W_tau^T W_tau,
+// and ln det Sigma_p = -2 sum_i ln (L_p^{-1})_ii - m ln T from the factor of T Sigma_p.
+// ------------------------------------------------------------------------------------------
+__global__ void lag_copy_kernel(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) b[e] = a[e];
+}
+
+__global__ __launch_bounds__(256) void lag_scores_kernel(const double* __restrict__ Li, int64_t m,
+                                                         int p, double T,
+                                                         double* __restrict__ logdet,
+                                                         double* __restrict__ aic,
+                                                         double* __restrict__ bic) {
+  __shared__ double part[4];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < m; i += 256) s += log(Li[i * m + i]);
+  s = wave_sum_d(s);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double ld = -2.0 * ((part[0] + part[1]) + (part[2] + part[3])) - (double)m * log(T);
+    const double k = (double)p * (double)m * (double)m;
+    logdet[p - 1] = ld;
+    aic[p - 1] = ld + 2.0 * k / T;
+    bic[p - 1] = ld + log(T) * k / T;
+  }
+}
+
+// best[0] = argmin AIC + 1, best[1] = argmin BIC + 1 (lowest p on ties)
+__global__ void lag_best_kernel(const double* __restrict__ aic, const double* __restrict__ bic,
+                                int p_max, int32_t* __restrict__ best) {
+  if (threadIdx.x != 0) return;
+  int ba = 0, bb = 0;
+  for (int q = 1; q < p_max; ++q) {
+    if (aic[q] < aic[ba]) ba = q;
+    if (bic[q] < bic[bb]) bb = q;
+  }
+  best[0] = ba + 1;
+  best[1] = bb + 1;
+}
+
+size_t lag_ws_bytes(const VarPlan& v, void* base, LagWs* out) {
+  Carver c(base);
+  LagWs w;
+  const size_t vb = var_ws_bytes(v, nullptr, nullptr);
+  char* vbase = c.take<char>(vb);
+  if (base) var_ws_bytes(v, vbase, &w.var);
+  const int64_t m = v.m;
+  w.Syy = c.take<double>(m * m);
+  w.A = c.take<double>(m * m);
+  w.Li = c.take<double>(m * m);
+  w.chol = c.take<double>(chol_ws_doubles(m));
+  w.gscr = c.take<double>((size_t)gram_splits(m, m, v.n_eff) * m * m);
+  if (out) *out = w;
+  return c.used;
+}
+
+int run_lag_select(const VarPlan& v, const LagWs& w, const float* X, int64_t ldx, double* logdet,
+                   double* aic, double* bic, int32_t* best, int32_t* st, hipStream_t stream) {
+  const int64_t m = v.m, dz = v.dz, n_eff = v.n_eff;
+  const VarWs& vw = w.var;
+  int rc = var_normal_equations(v, vw, X, ldx, GramMode::kFp64, st, stream);
+  if (rc) return rc;
+  {
+    ProfileScope ps("var_solve", stream);
+    rc = chol_solve_lower(vw.G, dz, dz, vw.Tmp, m, m, nullptr, dz, vw.chol, st, stream);
+    if (rc) return rc;
+  }
+  ProfileScope ps("lag_scores", stream);
+  // T Sigma_0 = Yc^T Yc (the lag-0 columns: the first m of the column map)
+  rc = gram_tn(X, ldx, vw.colmap, vw.mu, m, X, ldx, vw.colmap, vw.mu, m, n_eff, GramMode::kFp64,
+               1.0, w.Syy, m, w.gscr, stream, true);
+  if (rc) return rc;
+  const double T = (double)n_eff;
+  for (int p = 1; p <= v.p; ++p) {
+    const double* Wp = vw.Tmp + (int64_t)(p - 1) * m * m;
+    rc = gemm_f64(m, m, m, -1.0, Wp, m, true, Wp, m, false, 1.0, w.Syy, m, false, stream);
+    if (rc) return rc;
+    lag_copy_kernel<<<(unsigned)ceil_div(m * m, 256), 256, 0, stream>>>(w.Syy, w.A, m * m);
+    VL_LAUNCH_CHECK();
+    rc = chol_solve_lower(w.A, m, m, nullptr, 0, 0, w.Li, m, w.chol, st, stream);
+    if (rc) return rc;
+    lag_scores_kernel<<<1, 256, 0, stream>>>(w.Li, m, p, T, logdet, aic, bic);
+    VL_LAUNCH_CHECK();
+  }
+  lag_best_kernel<<<1, 64, 0, stream>>>(aic, bic, v.p, best);
   VL_LAUNCH_CHECK();
   return VL_OK;
 }

@@ -24,9 +24,24 @@ struct VarWs {
   double* scratch = nullptr;  // split-K partials
 };
 
+// Lag-order selection workspace: the VAR workspace of the p_max plan, then m x m buffers.
+struct LagWs {
+  VarWs var;
+  double* Syy = nullptr;    // T Sigma_p, updated in place from p = 0
+  double* A = nullptr;      // copy factored for the log-determinant
+  double* Li = nullptr;     // its L^{-1}
+  double* chol = nullptr;   // factorisation scratch (m)
+  double* gscr = nullptr;   // split-K partials of Yc^T Yc
+};
+
 VarPlan plan_var(int64_t n, int64_t m, int p);
 size_t var_ws_bytes(const VarPlan& v, void* base, VarWs* out);
 int run_var(const VarPlan& v, const VarWs& w, const float* X, int64_t ldx, int prec, double* M,
             double* intercept, float* E, int64_t lde, int32_t* st, hipStream_t stream);
+
+// v = plan_var(n, m, p_max).  logdet / aic / bic: p_max doubles each; best: {p_AIC, p_BIC}.
+size_t lag_ws_bytes(const VarPlan& v, void* base, LagWs* out);
+int run_lag_select(const VarPlan& v, const LagWs& w, const float* X, int64_t ldx, double* logdet,
+                   double* aic, double* bic, int32_t* best, int32_t* st, hipStream_t stream);
 
 }  // namespace vl

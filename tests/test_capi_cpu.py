@@ -109,6 +109,37 @@ def test_host_validation_without_gpu(L):
         L.VL_ERR_WORKSPACE
 
 
+def test_iterative_and_lag_selection_host_checks(L):
+    lib = L.lib
+    big = 1 << 30
+    # iterative ordering: workspace query, shapes, leading dimension, precision, workspace
+    assert lib.varlingam_order_iterative_workspace_bytes(1000, 40, 1) > 2 * 1000 * 40 * 4
+    assert lib.varlingam_order_iterative_workspace_bytes(1000, 5000, 1) == 0
+    it = lib.varlingam_order_iterative
+    assert it(None, 100, 4, 4, 1, FAKE, FAKE, FAKE, big, FAKE, None) == L.VL_ERR_INVALID_ARG
+    assert it(FAKE, 100, 5000, 5000, 1, FAKE, FAKE, FAKE, big, FAKE, None) == L.VL_ERR_SHAPE
+    assert it(FAKE, 1, 4, 4, 1, FAKE, FAKE, FAKE, big, FAKE, None) == L.VL_ERR_SHAPE
+    assert it(FAKE, 100, 4, 3, 1, FAKE, FAKE, FAKE, big, FAKE, None) == L.VL_ERR_INVALID_ARG
+    assert it(FAKE, 100, 4, 4, 7, FAKE, FAKE, FAKE, big, FAKE, None) == L.VL_ERR_INVALID_ARG
+    assert it(FAKE, 100, 4, 4, 1, FAKE, FAKE, FAKE, 16, FAKE, None) == L.VL_ERR_WORKSPACE
+    # lag selection: p_max >= 1, n - p_max > m p_max + 1, m p_max <= 4096
+    assert lib.varlingam_select_lag_workspace_bytes(1000, 10, 4) > 0
+    assert lib.varlingam_select_lag_workspace_bytes(30, 10, 4) == 0
+    sl = lib.varlingam_select_lag
+    assert sl(FAKE, 1000, 10, 10, 0, FAKE, FAKE, FAKE, FAKE, FAKE, big, FAKE, None) == \
+        L.VL_ERR_SHAPE
+    assert sl(FAKE, 30, 10, 10, 4, FAKE, FAKE, FAKE, FAKE, FAKE, big, FAKE, None) == \
+        L.VL_ERR_SHAPE
+    assert sl(FAKE, 100000, 1100, 1100, 4, FAKE, FAKE, FAKE, FAKE, FAKE, big, FAKE, None) == \
+        L.VL_ERR_SHAPE
+    assert sl(FAKE, 1000, 10, 9, 4, FAKE, FAKE, FAKE, FAKE, FAKE, big, FAKE, None) == \
+        L.VL_ERR_INVALID_ARG
+    assert sl(FAKE, 1000, 10, 10, 4, FAKE, FAKE, FAKE, None, FAKE, big, FAKE, None) == \
+        L.VL_ERR_INVALID_ARG
+    assert sl(FAKE, 1000, 10, 10, 4, FAKE, FAKE, FAKE, FAKE, FAKE, 16, FAKE, None) == \
+        L.VL_ERR_WORKSPACE
+
+
 def test_build_flags_disable_packed_fp32():
     from paper_2409_05500_amd import build
     f = build.FLAGS
