@@ -9,8 +9,8 @@ Prints ONE JSON line.  value = ordered-pair sample-evaluations per second of the
 rate, the stage breakdown, the plain-FP32 and BF16 step times, the roofline of the dominant
 kernel (from HIP events recorded on its launch stream during the timed loop), the oracle's CPU
 rate on a bounded sample, and sections for the original iterative DirectLiNGAM search on the
-same residuals, VAR lag-order selection on the same series, the 256-problem batched workload
-and the score backward.
+same residuals, VAR lag-order selection and adaptive-lasso pruning on the same series, the
+256-problem batched workload and the score backward.
 """
 from __future__ import annotations
 
@@ -199,6 +199,62 @@ def bench_lag_select(api, torch, X, p_max, steps):
             "p_aic": pa, "p_bic": pb}
 
 
+def bench_prune(api, torch, X, fit, steps):
+    """Adaptive-lasso pruning of the fit's B0 / B_tau (complete LARS-lasso paths, BIC knot),
+    through the C entry point with preallocated outputs (no synchronisation inside the loop).
+    Reports the algorithmic bytes of the path arithmetic: per step the inverse of the active
+    Gram is read and written once (the bordering pass, which also applies the previous
+    bordering's deferred rank-one term: 2 |A|^2 doubles), and |A| entries of the covariance are
+    read for every inactive column (|A| (d - |A|) doubles)."""
+    import numpy as np
+    from paper_2409_05500_amd._lib import lib
+    n, m = X.shape
+    p = fit.B_lags.shape[0]
+    dev = X.device
+    B0o = torch.empty((m, m), dtype=torch.float64, device=dev)
+    Blo = torch.empty((p, m, m), dtype=torch.float64, device=dev)
+    info = torch.empty((m, 3), dtype=torch.int32, device=dev)
+    nb = lib.varlingam_prune_workspace_bytes(n, m, p, 0)
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    st = api.DeviceStatus(dev)
+    K = fit.order.to(torch.int32).contiguous()
+    B0c, Blc = fit.B0.contiguous(), fit.B_lags.contiguous()
+    stream = torch.cuda.current_stream(dev).cuda_stream
+
+    def run():
+        rc = lib.varlingam_prune(X.data_ptr(), n, m, X.stride(0), p, K.data_ptr(),
+                                 B0c.data_ptr(), Blc.data_ptr(), 0, B0o.data_ptr(),
+                                 Blo.data_ptr(), info.data_ptr(), ws.data_ptr(), nb, st.ptr,
+                                 stream)
+        assert rc == 0, rc
+
+    run()
+    torch.cuda.synchronize()
+    st.read("prune bench")
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(steps):
+        run()
+    t1.record()
+    torch.cuda.synchronize()
+    st.read("prune bench")
+    ms = t0.elapsed_time(t1) / steps
+    inf = info.cpu().numpy()
+    order = K.cpu().numpy()
+    byts = 0
+    for pos in range(m):
+        # model: the active set grows by one column per step (exact when no column leaves)
+        d = pos + m * p
+        a = np.minimum(np.arange(1, int(inf[order[pos]][0]) + 1, dtype=np.float64), d)
+        byts += int(8 * (2 * a * a + a * (d - a)).sum())
+    nnz0 = int((B0o != 0).sum().item())
+    return {"m": m, "n": n, "p": p, "ms": ms, "workspace_bytes": nb,
+            "path_steps_total": int(inf[:, 0].sum()), "df_mean": float(inf[:, 2].mean()),
+            "B0_nonzeros_before": int((fit.B0 != 0).sum().item()), "B0_nonzeros_after": nnz0,
+            "path_bytes": byts, "path_GB_per_s": byts / (ms / 1e3) / 1e9}
+
+
 def bench_backward(api, _lib, torch, steps: int, seed: int):
     """Gradient of the score matrix, dE = d<G, S(E)>/dE, at m = 1000, n = 50000 (Laplace
     shocks, p = 1): E is the GPU VAR fit's residual matrix, G a seeded N(0, 1) cotangent.
@@ -268,6 +324,8 @@ def main():
                     help="skip the original iterative DirectLiNGAM search on the fit's residuals")
     ap.add_argument("--no-lag-select", action="store_true",
                     help="skip the VAR lag-order selection section")
+    ap.add_argument("--no-prune", action="store_true",
+                    help="skip the adaptive-lasso pruning section")
     ap.add_argument("--only", choices=("batch", "backward"), default=None,
                     help="profiling runs: run just one extra section and print its JSON")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -389,6 +447,8 @@ def main():
         out["iterative"] = bench_iterative(api, torch, fit.E, stage_ms, 3)
     if not args.no_lag_select:
         out["lag_select"] = bench_lag_select(api, torch, X, 2 * p, 5)
+    if not args.no_prune:
+        out["prune"] = bench_prune(api, torch, X, fit, 2)
     if not args.no_batch:
         out["batched"] = bench_batched(api, torch, max(3, args.steps // 2), args.seed)
     if not args.no_backward:

@@ -213,6 +213,36 @@ int estimate_B(const double* Cov, const double* M, const int32_t* order, int64_t
                void* stream);
 
 /* ------------------------------------------------------------------------------------- */
+/* Pruning of B0 / B_tau, the step after the fit that the paper names (Sec. 7, future work) */
+/* without specifying it.  Adaptive lasso (Zou 2006, weight exponent 1): variable i, at     */
+/* position k of the order, is regressed with intercept on its k predecessors at lag 0 and  */
+/* on all m variables at lags 1..p over t = p .. n-1 (d = k + m p columns); column j is      */
+/* scaled by |b_j|, b = the unpruned coefficients (B0[i,:], B_tau[i,:], which are exactly    */
+/* that regression's least-squares solution), and the lasso path is followed by LARS with   */
+/* the lasso modification (Efron, Hastie, Johnstone and Tibshirani 2004).  Of its knots     */
+/* (knot 0 = all zero) the one minimising BIC = T ln(RSS/T) + df ln T, df = nonzero          */
+/* coefficients, is kept (the first on ties); a column with b_j = 0 stays 0.  The path ends  */
+/* at the least-squares fit, once the active correlation falls below 1e-12 of its start,     */
+/* or after max_steps steps (0: 8 d).  FP64 throughout, from an FP64 covariance of the FP32  */
+/* series.                                                                                  */
+/* X          in, n x m float32 (leading dimension ldx >= m), the series of the fit.         */
+/* order      in, m int32, a permutation (causal order, most exogenous first).                */
+/* B0, Blag   in, m x m and p x m x m float64, the unpruned estimates (estimate_B's layout). */
+/* B0_out, Blag_out  out, same layouts: the pruned matrices (exact zeros where pruned).      */
+/* info       out, nullable, 3 m int32: per variable (path steps, chosen knot, nonzeros).    */
+/* Workspace: the m (p+1) square covariance plus, per variable, the inverse of its active    */
+/* Gram (up to min(d, max_steps + 1) squared doubles) and 14 d doubles of path state.        */
+/* Host errors: m < 1, p < 1, max_steps < 0, m (p+1) > 4096 or n - p <= m (p+1) + 1 ->       */
+/* VL_ERR_SHAPE.  Status: VL_ERR_NONFINITE (the series), VL_ERR_INVALID_ARG (order not a     */
+/* permutation).  B0 and Blag must be finite.                                                */
+/* ------------------------------------------------------------------------------------- */
+size_t varlingam_prune_workspace_bytes(int64_t n, int64_t m, int p, int64_t max_steps);
+int varlingam_prune(const float* X, int64_t n, int64_t m, int64_t ldx, int p,
+                    const int32_t* order, const double* B0, const double* Blag, int64_t max_steps,
+                    double* B0_out, double* Blag_out, int32_t* info, void* ws, size_t ws_bytes,
+                    int32_t* dev_status, void* stream);
+
+/* ------------------------------------------------------------------------------------- */
 /* Batched fit: many independent VarLiNGAM problems of uneven size (for instance rolling     */
 /* windows or many datasets) through the whole path -- VAR fit (Sec. 2.1), pairwise         */
 /* precompute (Sec. 4.2, Eq. 1-2), ordering (Alg. 1, Eq. 3), B0 / B_tau -- with one kernel  */

@@ -181,16 +181,20 @@ def regression_design(X: np.ndarray, p: int, order, i_pos: int):
 
 
 def prune(X: np.ndarray, p: int, order, B0: np.ndarray, B_lags: np.ndarray,
-          max_steps: int = 0) -> dict:
+          max_steps: int = 0, positions=None) -> dict:
     """Adaptive-lasso pruning of B0 / B_tau (readings in the module header).  Returns the
     pruned B0 (m x m), B_lags (p x m x m) and per variable the path events, the chosen knot, its
-    df and the BIC / step-length gaps that tests use to recognise near-ties."""
+    df and the BIC / step-length gaps that tests use to recognise near-ties.  With positions,
+    only the variables at those positions of the order are computed (the other rows stay 0
+    and info lists the computed ones)."""
     X = np.asarray(X, dtype=np.float64)
     n, m = X.shape
     B0p = np.zeros((m, m))
     Blp = np.zeros((p, m, m))
     info = []
-    for pos, i in enumerate([int(v) for v in order]):
+    order = [int(v) for v in order]
+    for pos in (range(m) if positions is None else positions):
+        i = order[pos]
         y, Z, cols = regression_design(X, p, order, pos)
         b = np.array([B0[i, v] if tau == 0 else B_lags[tau - 1][i, v] for tau, v in cols])
         keep = np.flatnonzero(b != 0.0)
@@ -204,7 +208,7 @@ def prune(X: np.ndarray, p: int, order, B0: np.ndarray, B_lags: np.ndarray,
                 B0p[i, v] = beta[jj]
             else:
                 Blp[tau - 1][i, v] = beta[jj]
-        info.append({"var": i, "d": len(keep), "steps": len(path["events"]),
+        info.append({"var": i, "pos": pos, "d": len(keep), "steps": len(path["events"]),
                      "knot": sel["knot"], "df": int(np.count_nonzero(beta)),
                      "events": [(e, int(keep[j]) if j >= 0 else -1) for e, j in path["events"]],
                      "bic_gap": sel["gap"], "min_step_gap": min(path["gaps"], default=math.inf)})

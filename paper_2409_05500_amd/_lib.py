@@ -55,6 +55,9 @@ SIGNATURES = {
     "varlingam_order_iterative": (_i32, [_p, _i64, _i64, _i64, _i32, _p, _p, _p, _sz, _p, _p]),
     "estimate_B_workspace_bytes": (_sz, [_i64, _i32]),
     "estimate_B": (_i32, [_p, _p, _p, _i64, _i32, _p, _p, _p, _sz, _p, _p]),
+    "varlingam_prune_workspace_bytes": (_sz, [_i64, _i64, _i32, _i64]),
+    "varlingam_prune": (_i32, [_p, _i64, _i64, _i64, _i32, _p, _p, _p, _i64, _p, _p, _p, _p,
+                               _sz, _p, _p]),
     "varlingam_batch_create": (_i32, [C.POINTER(VlInstance), _i32, _i32,
                                       C.POINTER(C.c_void_p)]),
     "varlingam_batch_workspace_bytes": (_sz, [_p]),

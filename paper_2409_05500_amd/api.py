@@ -242,6 +242,32 @@ def estimate_B(Cov: torch.Tensor, M: torch.Tensor, order: torch.Tensor,
     return B0, Bl[:p]
 
 
+def prune(X: torch.Tensor, p: int, order: torch.Tensor, B0: torch.Tensor, B_lags: torch.Tensor,
+          max_steps: int = 0, status: "DeviceStatus | None" = None):
+    """Adaptive-lasso pruning of (B0, B_lags) on the series X (n x m float32) of the fit:
+    (B0 [m, m], B_lags [p, m, m]) f64 with exact zeros, and info [m, 3] int32 (path steps,
+    chosen knot, nonzeros) per variable."""
+    _require(X, torch.float32, "X")
+    n, m = X.shape
+    dev = X.device
+    B0o = torch.empty((m, m), dtype=torch.float64, device=dev)
+    Blo = torch.empty((p, m, m), dtype=torch.float64, device=dev)
+    info = torch.empty((m, 3), dtype=torch.int32, device=dev)
+    ws = _workspace(lib.varlingam_prune_workspace_bytes(n, m, p, max_steps), dev)
+    st = status if status is not None else DeviceStatus(dev)
+    K = order.to(torch.int32).contiguous()
+    B0c = B0.to(torch.float64).contiguous()
+    Blc = B_lags.to(torch.float64).contiguous()
+    check(lib.varlingam_prune(X.data_ptr(), n, m, X.stride(0), p, K.data_ptr(), B0c.data_ptr(),
+                              Blc.data_ptr(), max_steps, B0o.data_ptr(), Blo.data_ptr(),
+                              info.data_ptr(),
+                              ws.data_ptr(), ws.numel(), st.ptr, _stream_ptr(dev)),
+          "varlingam_prune")
+    if status is None:
+        st.read("varlingam_prune")
+    return B0o, Blo, info
+
+
 @dataclass
 class FitResult:
     M: torch.Tensor

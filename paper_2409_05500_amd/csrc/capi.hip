@@ -4,6 +4,7 @@
 #include "iterative.hpp"
 #include "order.hpp"
 #include "pairwise.hpp"
+#include "prune.hpp"
 #include "var_fit.hpp"
 
 using namespace vl;
@@ -228,6 +229,36 @@ int estimate_B(const double* Cov, const double* M, const int32_t* order, int64_t
   int rc = begin(dev_status, s);
   if (rc) return rc;
   return run_estimate_b(w, Cov, M, order, m, p, B0, Blag, dev_status, s);
+}
+
+// ----------------------------------------------------------------------------------------
+static bool prune_shape_ok(int64_t n, int64_t m, int p, int64_t max_steps) {
+  return m >= 1 && p >= 1 && max_steps >= 0 && m * (p + 1) <= 4096 &&
+         n - p > m * (p + 1) + 1;
+}
+
+size_t varlingam_prune_workspace_bytes(int64_t n, int64_t m, int p, int64_t max_steps) {
+  if (!prune_shape_ok(n, m, p, max_steps)) return 0;
+  return prune_ws_bytes(n, m, p, max_steps, nullptr, nullptr);
+}
+
+int varlingam_prune(const float* X, int64_t n, int64_t m, int64_t ldx, int p,
+                    const int32_t* order, const double* B0, const double* Blag, int64_t max_steps,
+                    double* B0_out, double* Blag_out, int32_t* info, void* ws, size_t ws_bytes,
+                    int32_t* dev_status, void* stream) {
+  if (!X || !order || !B0 || !Blag || !B0_out || !Blag_out || !dev_status)
+    return VL_ERR_INVALID_ARG;
+  if (!prune_shape_ok(n, m, p, max_steps)) return VL_ERR_SHAPE;
+  if (ldx < m) return VL_ERR_INVALID_ARG;
+  const size_t need = prune_ws_bytes(n, m, p, max_steps, nullptr, nullptr);
+  if (!ws || ws_bytes < need || !aligned256(ws)) return VL_ERR_WORKSPACE;
+  PruneWs w;
+  prune_ws_bytes(n, m, p, max_steps, ws, &w);
+  hipStream_t s = as_stream(stream);
+  int rc = begin(dev_status, s);
+  if (rc) return rc;
+  return run_prune(n, m, p, w, X, ldx, order, B0, Blag, max_steps, B0_out, Blag_out, info,
+                   dev_status, s);
 }
 
 }  // extern "C"

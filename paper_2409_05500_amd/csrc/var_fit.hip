@@ -203,6 +203,24 @@ static int var_normal_equations(const VarPlan& v, const VarWs& w, const float* X
   return VL_OK;
 }
 
+size_t lag_cov_scratch_doubles(int64_t n, int64_t m, int p) {
+  const int64_t nc = m * (p + 1), n_eff = n - p;
+  const size_t s1 = (size_t)colmean_splits(n_eff) * nc;
+  const size_t s2 = (size_t)gram_splits(nc, nc, n_eff) * nc * nc;
+  return s1 > s2 ? s1 : s2;
+}
+
+int lag_covariance(int64_t n, int64_t m, int p, const float* X, int64_t ldx, int64_t* colmap,
+                   double* mu, double* C, double* scratch, int32_t* st, hipStream_t stream) {
+  const int64_t nc = m * (p + 1), n_eff = n - p;
+  lag_colmap_kernel<<<(unsigned)ceil_div(nc, 256), 256, 0, stream>>>(m, p, ldx, colmap);
+  VL_LAUNCH_CHECK();
+  int rc = colmeans(X, ldx, colmap, nc, n_eff, mu, scratch, st, stream);
+  if (rc) return rc;
+  return gram_tn(X, ldx, colmap, mu, nc, X, ldx, colmap, mu, nc, n_eff, GramMode::kFp64, 1.0, C,
+                 nc, scratch, stream, true);
+}
+
 int run_var(const VarPlan& v, const VarWs& w, const float* X, int64_t ldx, int prec, double* M,
             double* intercept, float* E, int64_t lde, int32_t* st, hipStream_t stream) {
   const int64_t m = v.m, dz = v.dz, n_eff = v.n_eff;

@@ -39,6 +39,14 @@ size_t var_ws_bytes(const VarPlan& v, void* base, VarWs* out);
 int run_var(const VarPlan& v, const VarWs& w, const float* X, int64_t ldx, int prec, double* M,
             double* intercept, float* E, int64_t lde, int32_t* st, hipStream_t stream);
 
+// C = centred cross-products (not divided by the sample count) of the m (p + 1) lag-embedded
+// columns x(t), x(t-1), .., x(t-p) over t = p .. n-1, FP64 from the FP32 data, both triangles;
+// column tau m + i is x_i(t - tau).  colmap, mu: m (p + 1) each; scratch:
+// lag_cov_scratch_doubles() doubles.
+size_t lag_cov_scratch_doubles(int64_t n, int64_t m, int p);
+int lag_covariance(int64_t n, int64_t m, int p, const float* X, int64_t ldx, int64_t* colmap,
+                   double* mu, double* C, double* scratch, int32_t* st, hipStream_t stream);
+
 // v = plan_var(n, m, p_max).  logdet / aic / bic: p_max doubles each; best: {p_AIC, p_BIC}.
 size_t lag_ws_bytes(const VarPlan& v, void* base, LagWs* out);
 int run_lag_select(const VarPlan& v, const LagWs& w, const float* X, int64_t ldx, double* logdet,

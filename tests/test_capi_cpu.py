@@ -140,6 +140,32 @@ def test_iterative_and_lag_selection_host_checks(L):
         L.VL_ERR_WORKSPACE
 
 
+def test_prune_host_checks(L):
+    lib = L.lib
+    big = 1 << 40
+    assert lib.varlingam_prune_workspace_bytes(10000, 400, 2, 0) > 8 * 1200 * 1200
+    assert lib.varlingam_prune_workspace_bytes(10000, 400, 2, 30) < \
+        lib.varlingam_prune_workspace_bytes(10000, 400, 2, 0)
+    assert lib.varlingam_prune_workspace_bytes(100, 40, 2, 0) == 0      # n - p <= m (p+1) + 1
+    assert lib.varlingam_prune_workspace_bytes(10000, 2100, 1, 0) == 0  # m (p+1) > 4096
+    pr = lib.varlingam_prune
+    args = dict(X=FAKE, n=10000, m=40, ldx=40, p=2, order=FAKE, B0=FAKE, Bl=FAKE, steps=0,
+                B0o=FAKE, Blo=FAKE, info=None, ws=FAKE, nb=big, st=FAKE)
+
+    def call(**kw):
+        a = dict(args, **kw)
+        return pr(a["X"], a["n"], a["m"], a["ldx"], a["p"], a["order"], a["B0"], a["Bl"],
+                  a["steps"], a["B0o"], a["Blo"], a["info"], a["ws"], a["nb"], a["st"], None)
+
+    assert call(order=None) == L.VL_ERR_INVALID_ARG
+    assert call(Blo=None) == L.VL_ERR_INVALID_ARG
+    assert call(p=0) == L.VL_ERR_SHAPE
+    assert call(steps=-1) == L.VL_ERR_SHAPE
+    assert call(n=100) == L.VL_ERR_SHAPE
+    assert call(ldx=39) == L.VL_ERR_INVALID_ARG
+    assert call(nb=4096) == L.VL_ERR_WORKSPACE
+
+
 def test_build_flags_disable_packed_fp32():
     from paper_2409_05500_amd import build
     f = build.FLAGS

@@ -161,3 +161,18 @@ def test_intercept_absorbs_constant_offsets():
     assert np.array_equal(a["B0"] != 0, b["B0"] != 0)
     np.testing.assert_allclose(b["B0"], a["B0"], rtol=0, atol=1e-9)
     np.testing.assert_allclose(b["B_lags"], a["B_lags"], rtol=0, atol=1e-9)
+
+
+def test_duplicate_column_is_excluded():
+    """A column equal to an active one cannot enter (its Schur complement is 0): the knots are
+    those of the path without it, and its coefficient stays 0."""
+    rng = np.random.default_rng(1)
+    Z = rng.normal(size=(300, 8))
+    y = Z[:, :3] @ np.array([1.0, -0.5, 0.3]) + rng.laplace(size=300)
+    Z, y = Z - Z.mean(0), y - y.mean()
+    a = P.lars_lasso_path(Z, y)
+    b = P.lars_lasso_path(np.hstack([Z, Z[:, [1]]]), y)
+    Ka, Kb = np.array(a["knots"]), np.array(b["knots"])
+    assert Ka.shape[0] == Kb.shape[0]
+    assert np.abs(Kb[:, :8] - Ka).max() <= 1e-12 * np.abs(Ka).max()
+    assert np.all(Kb[:, 8] == 0.0)
