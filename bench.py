@@ -10,7 +10,7 @@ rate, the stage breakdown, the plain-FP32 and BF16 step times, the roofline of t
 kernel (from HIP events recorded on its launch stream during the timed loop), the oracle's CPU
 rate on a bounded sample, and sections for the original iterative DirectLiNGAM search on the
 same residuals, VAR lag-order selection and adaptive-lasso pruning on the same series, the
-256-problem batched workload and the score backward.
+bootstrap / rolling-window ensembles, the 256-problem batched workload and the score backward.
 """
 from __future__ import annotations
 
@@ -255,6 +255,71 @@ def bench_prune(api, torch, X, fit, steps):
             "path_bytes": byts, "path_GB_per_s": byts / (ms / 1e3) / 1e9}
 
 
+def bench_ensembles(api, torch, steps: int, seed: int):
+    """Ensembles on the batched path.
+    * Residual bootstrap of the m = 100, n = 5000, p = 1 series (Laplace shocks): 100 resamples
+      per step -- VAR fit of the series, 100 simulated series, their batched fit, aggregation.
+    * Rolling windows of an m = 50, n = 20000, p = 1 series: windows of 2000 rows every 100
+      rows (181 windows) per step -- batched fit of the window views, aggregation.
+    Buffers are allocated once; a step ends with the aggregation's count read (one sync)."""
+    import numpy as np
+    import synth
+    dev = torch.device("cuda:0")
+    out = {}
+    wl = synth.MEDIUM
+    X = torch.from_numpy(synth.make_instance(wl, seed).X32).to(dev)
+    R, T = 100, wl.n - wl.p
+    idx = torch.from_numpy(np.random.default_rng(seed).integers(0, T, (R, T)).astype(np.int32))
+    idx = idx.to(dev)
+    series = torch.empty((R, wl.n, wl.m), dtype=torch.float32, device=dev)
+    ef = api.EnsembleFitter(list(series), wl.p, "mixed", 0.05)
+    st = api.DeviceStatus(dev)
+
+    def boot():
+        M, c, E = api.fit_var(X, wl.p, status=st)
+        api.var_simulate(M, c, X[:wl.p].contiguous(), E, idx, out=series, status=st)
+        ef.run()
+        return ef.aggregate()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps * 1e3
+
+    boot_ms = timed(boot)
+    st.read("bootstrap bench")
+    assert ef.count == R, ef.check()
+    from paper_2409_05500_amd import _lib
+    _lib.profile_enable("*")
+    boot()
+    torch.cuda.synchronize()
+    stages = {k: round(_lib.profile_read(k)[0], 4)
+              for k in ("var_gram", "var_solve", "var_residual", "simulate", "batch_var",
+                        "batch_pairwise", "batch_moments", "batch_order_b")}
+    _lib.profile_enable(None)
+    out["bootstrap"] = {"workload": wl.name, "resamples": R, "ms": boot_ms,
+                        "resamples_per_s": R / (boot_ms / 1e3), "stage_ms": stages}
+    inst = synth.make_custom(50, 20000, 1, "laplace", seed, edge_prob=0.1, w_lo=0.1, w_hi=0.5)
+    Xr = torch.from_numpy(inst.X32).to(dev)
+    starts = list(range(0, 20000 - 2000 + 1, 100))
+    er = api.EnsembleFitter([Xr[s: s + 2000] for s in starts], 1, "mixed", 0.05)
+
+    def roll():
+        er.run()
+        return er.aggregate()
+
+    roll_ms = timed(roll)
+    assert er.count == len(starts), er.check()
+    out["rolling"] = {"workload": "m50_n20000_p1_laplace, windows of 2000 every 100",
+                      "windows": len(starts), "ms": roll_ms,
+                      "windows_per_s": len(starts) / (roll_ms / 1e3)}
+    return out
+
+
 def bench_backward(api, _lib, torch, steps: int, seed: int):
     """Gradient of the score matrix, dE = d<G, S(E)>/dE, at m = 1000, n = 50000 (Laplace
     shocks, p = 1): E is the GPU VAR fit's residual matrix, G a seeded N(0, 1) cotangent.
@@ -326,6 +391,8 @@ def main():
                     help="skip the VAR lag-order selection section")
     ap.add_argument("--no-prune", action="store_true",
                     help="skip the adaptive-lasso pruning section")
+    ap.add_argument("--no-ensembles", action="store_true",
+                    help="skip the bootstrap / rolling-window section")
     ap.add_argument("--only", choices=("batch", "backward"), default=None,
                     help="profiling runs: run just one extra section and print its JSON")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -449,6 +516,8 @@ def main():
         out["lag_select"] = bench_lag_select(api, torch, X, 2 * p, 5)
     if not args.no_prune:
         out["prune"] = bench_prune(api, torch, X, fit, 2)
+    if not args.no_ensembles:
+        out["ensembles"] = bench_ensembles(api, torch, 3, args.seed)
     if not args.no_batch:
         out["batched"] = bench_batched(api, torch, max(3, args.steps // 2), args.seed)
     if not args.no_backward:

@@ -243,6 +243,44 @@ int varlingam_prune(const float* X, int64_t n, int64_t m, int64_t ldx, int p,
                     int32_t* dev_status, void* stream);
 
 /* ------------------------------------------------------------------------------------- */
+/* Ensembles of the fit (rolling windows, residual bootstrap) run on the batched fit below; */
+/* these two calls generate bootstrap series and aggregate the ensemble's results.          */
+/*                                                                                        */
+/* varlingam_var_simulate: residual bootstrap of the VAR of Sec. 2.1 (the model-based time- */
+/* series bootstrap).  Resample b is rows 0 .. p+T-1 of Xout + b * series_stride (leading    */
+/* dimension ldxo): rows 0..p-1 copy X0, then                                              */
+/*   x*(t) = intercept + sum_{tau=1..p} M_tau x*(t - tau) + E[idx[b*T + t - p]]             */
+/* in FP64 from the FP32 rows already written, stored as FP32.  M (p x m x m) and intercept  */
+/* are varlingam_fit_var's outputs; E is an n_e x m float32 pool of residual rows (leading   */
+/* dimension lde); idx (R x T int32) are the draws, made by the caller.                      */
+/* Host errors: m < 1, p < 1, m p > 4096, m (p+1) > 8192, n_e < 1, R < 1, T < 1 ->            */
+/* VL_ERR_SHAPE; ldx0, lde or ldxo < m, or series_stride < (p+T) ldxo -> VL_ERR_INVALID_ARG.  */
+/* Status: VL_ERR_INVALID_ARG for a draw outside [0, n_e) (the nearest row is used).         */
+/*                                                                                        */
+/* varlingam_edge_frequency: over the K problems whose problem_status is VL_OK (all when    */
+/* problem_status is NULL; *count = their number):                                          */
+/*   P0[i*m+j]      = fraction with |B0_k[i][j]| > threshold                                 */
+/*   Plag[..]       = the same for every B_tau (p x m x m; NULL when p = 0)                  */
+/*   P_order[i*m+j] = fraction in which j precedes i in order_k                              */
+/* orders K x m int32 (permutations), B0s K x m x m, Blags K x p x m x m float64, contiguous  */
+/* stacks.  Exact: integer counts divided once.  threshold >= 0.                             */
+/* Host errors: K < 1, m < 1, m > 65536, p < 0 -> VL_ERR_SHAPE; null pointers or a negative  */
+/* threshold -> VL_ERR_INVALID_ARG.                                                          */
+/* ------------------------------------------------------------------------------------- */
+size_t varlingam_var_simulate_workspace_bytes(int64_t m, int p);
+int varlingam_var_simulate(const double* M, const double* intercept, int64_t m, int p,
+                           const float* X0, int64_t ldx0, const float* E, int64_t n_e,
+                           int64_t lde, const int32_t* idx, int64_t R, int64_t T, float* Xout,
+                           int64_t ldxo, int64_t series_stride, void* ws, size_t ws_bytes,
+                           int32_t* dev_status, void* stream);
+size_t varlingam_edge_frequency_workspace_bytes(int64_t K, int64_t m);
+int varlingam_edge_frequency(const int32_t* orders, const double* B0s, const double* Blags,
+                             int64_t K, int64_t m, int p, double threshold,
+                             const int32_t* problem_status, double* P0, double* Plag,
+                             double* P_order, int32_t* count, void* ws, size_t ws_bytes,
+                             int32_t* dev_status, void* stream);
+
+/* ------------------------------------------------------------------------------------- */
 /* Batched fit: many independent VarLiNGAM problems of uneven size (for instance rolling     */
 /* windows or many datasets) through the whole path -- VAR fit (Sec. 2.1), pairwise         */
 /* precompute (Sec. 4.2, Eq. 1-2), ordering (Alg. 1, Eq. 3), B0 / B_tau -- with one kernel  */
@@ -299,7 +337,8 @@ void varlingam_batch_destroy(vl_batch* batch);
 /* a comma-separated list; NULL or "" = off) and clears earlier totals.  Stage names:       */
 /*   var_gram, var_solve, var_residual, var_refine, pairwise_cov, pairwise_prep,            */
 /*   pairwise_moments, pairwise_combine, backward_prep, backward_owner, backward_tail,       */
-/*   order, estimate_b, batch_var, batch_pairwise, batch_moments, batch_order_b.            */
+/*   order, estimate_b, batch_var, batch_pairwise, batch_moments, batch_order_b, iterative, */
+/*   lag_scores, prune, simulate.                                                           */
 /* varlingam_profile_read() waits for the recorded events of one stage and returns the      */
 /* accumulated milliseconds and the number of recorded launches.  Thread-safe.              */
 /* ------------------------------------------------------------------------------------- */

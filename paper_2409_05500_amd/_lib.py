@@ -23,6 +23,7 @@ _p = C.c_void_p
 _i64 = C.c_int64
 _i32 = C.c_int
 _sz = C.c_size_t
+_f64 = C.c_double
 
 # name -> (restype, argtypes); the names and argument order are those of include/varlingam.h
 class VlInstance(C.Structure):
@@ -55,6 +56,12 @@ SIGNATURES = {
     "varlingam_order_iterative": (_i32, [_p, _i64, _i64, _i64, _i32, _p, _p, _p, _sz, _p, _p]),
     "estimate_B_workspace_bytes": (_sz, [_i64, _i32]),
     "estimate_B": (_i32, [_p, _p, _p, _i64, _i32, _p, _p, _p, _sz, _p, _p]),
+    "varlingam_var_simulate_workspace_bytes": (_sz, [_i64, _i32]),
+    "varlingam_var_simulate": (_i32, [_p, _p, _i64, _i32, _p, _i64, _p, _i64, _i64, _p, _i64,
+                                      _i64, _p, _i64, _i64, _p, _sz, _p, _p]),
+    "varlingam_edge_frequency_workspace_bytes": (_sz, [_i64, _i64]),
+    "varlingam_edge_frequency": (_i32, [_p, _p, _p, _i64, _i64, _i32, _f64, _p, _p, _p, _p,
+                                        _p, _p, _sz, _p, _p]),
     "varlingam_prune_workspace_bytes": (_sz, [_i64, _i64, _i32, _i64]),
     "varlingam_prune": (_i32, [_p, _i64, _i64, _i64, _i32, _p, _p, _p, _i64, _p, _p, _p, _p,
                                _sz, _p, _p]),

@@ -438,6 +438,153 @@ class BatchFitter:
             self._h = None
 
 
+def var_simulate(M: torch.Tensor, intercept: torch.Tensor, X0: torch.Tensor, E: torch.Tensor,
+                 idx: torch.Tensor, out: "torch.Tensor | None" = None,
+                 status: "DeviceStatus | None" = None) -> torch.Tensor:
+    """Residual-bootstrap series of a fitted VAR: (R, p + T, m) float32 from M [p, m, m],
+    intercept [m] (f64), the first p rows X0 [p, m], a residual pool E [n_e, m] (f32) and the
+    draws idx [R, T] (int32, rows of E)."""
+    p, m, _ = M.shape
+    R, T = idx.shape
+    dev = M.device
+    if out is None:
+        out = torch.empty((R, p + T, m), dtype=torch.float32, device=dev)
+    assert out.shape == (R, p + T, m) and out.stride(2) == 1 and out.stride(1) == m
+    Mc, cc = M.contiguous(), intercept.contiguous()
+    Ic = idx.to(torch.int32).contiguous()
+    _require(X0, torch.float32, "X0")
+    _require(E, torch.float32, "E")
+    ws = _workspace(lib.varlingam_var_simulate_workspace_bytes(m, p), dev)
+    st = status if status is not None else DeviceStatus(dev)
+    check(lib.varlingam_var_simulate(Mc.data_ptr(), cc.data_ptr(), m, p, X0.data_ptr(),
+                                     X0.stride(0), E.data_ptr(), E.shape[0], E.stride(0),
+                                     Ic.data_ptr(), R, T, out.data_ptr(), m, out.stride(0),
+                                     ws.data_ptr(), ws.numel(), st.ptr, _stream_ptr(dev)),
+          "varlingam_var_simulate")
+    if status is None:
+        st.read("varlingam_var_simulate")
+    return out
+
+
+def edge_frequency(orders: torch.Tensor, B0s: torch.Tensor, B_lags: torch.Tensor,
+                   threshold: float = 0.0, problem_status: "torch.Tensor | None" = None,
+                   status: "DeviceStatus | None" = None):
+    """Aggregate K fits: (P0 [m, m], P_lags [p, m, m], P_order [m, m]) f64 and the number of
+    problems used (status VL_OK)."""
+    K, m = orders.shape
+    p = B_lags.shape[1] if B_lags is not None else 0
+    dev = orders.device
+    f64 = dict(dtype=torch.float64, device=dev)
+    P0, Pl, Po = torch.empty((m, m), **f64), torch.empty((max(p, 1), m, m), **f64), \
+        torch.empty((m, m), **f64)
+    cnt = torch.empty(1, dtype=torch.int32, device=dev)
+    Oc = orders.to(torch.int32).contiguous()
+    Bc = B0s.contiguous()
+    Lc = B_lags.contiguous() if p > 0 else None
+    Sc = problem_status.to(torch.int32).contiguous() if problem_status is not None else None
+    ws = _workspace(lib.varlingam_edge_frequency_workspace_bytes(K, m), dev)
+    st = status if status is not None else DeviceStatus(dev)
+    check(lib.varlingam_edge_frequency(Oc.data_ptr(), Bc.data_ptr(),
+                                       Lc.data_ptr() if p > 0 else None, K, m, p,
+                                       float(threshold),
+                                       Sc.data_ptr() if Sc is not None else None, P0.data_ptr(),
+                                       Pl.data_ptr() if p > 0 else None, Po.data_ptr(),
+                                       cnt.data_ptr(), ws.data_ptr(), ws.numel(), st.ptr,
+                                       _stream_ptr(dev)), "varlingam_edge_frequency")
+    if status is None:
+        st.read("varlingam_edge_frequency")
+    return P0, Pl[:p], Po, int(cnt.item())
+
+
+class EnsembleFitter:
+    """K fits of one dataset's problems (equal n, m, p) on the batched path: rolling windows or
+    bootstrap resamples.  The inputs are views into caller buffers (a window of a series, a
+    resample of a stack), so nothing is copied; outputs are stacked: order [K, m], B0 [K, m, m],
+    B_lags [K, p, m, m], M, intercept, E.  run() enqueues the batched fit and the aggregation
+    on the current stream without synchronising."""
+
+    def __init__(self, views, p: int = 1, prec="mixed", threshold: float = 0.0):
+        K = len(views)
+        n, m = views[0].shape
+        dev = views[0].device
+        self.views, self.p, self.prec, self.threshold = list(views), p, _prec(prec), threshold
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.M = torch.empty((K, p, m, m), **f64)
+        self.intercept = torch.empty((K, m), **f64)
+        self.E = torch.empty((K, n - p, m), dtype=torch.float32, device=dev)
+        self.order = torch.empty((K, m), dtype=torch.int32, device=dev)
+        self.B0 = torch.empty((K, m, m), **f64)
+        self.B_lags = torch.empty((K, p, m, m), **f64)
+        desc = (_lib.VlInstance * K)()
+        for k, X in enumerate(views):
+            assert X.shape == (n, m) and X.dtype == torch.float32 and X.stride(1) == 1
+            d = desc[k]
+            d.X, d.n, d.m, d.ldx, d.p = X.data_ptr(), n, m, X.stride(0), p
+            d.M, d.intercept = self.M[k].data_ptr(), self.intercept[k].data_ptr()
+            d.E, d.lde = self.E[k].data_ptr(), m
+            d.S, d.margin = None, None
+            d.order, d.B0, d.Blag = self.order[k].data_ptr(), self.B0[k].data_ptr(), \
+                self.B_lags[k].data_ptr()
+        handle = C.c_void_p()
+        check(lib.varlingam_batch_create(desc, K, self.prec, C.byref(handle)),
+              "varlingam_batch_create")
+        self._h = handle
+        self.ws = _workspace(lib.varlingam_batch_workspace_bytes(handle), dev)
+        self.status = torch.zeros(K, dtype=torch.int32, device=dev)
+        check(lib.varlingam_batch_bind(handle, self.ws.data_ptr(), self.ws.numel(),
+                                       _stream_ptr(dev)), "varlingam_batch_bind")
+        self.agg_status = DeviceStatus(dev)
+        self.P0 = self.P_lags = self.P_order = None
+        self.count = None
+
+    def run(self) -> None:
+        check(lib.varlingam_fit_batched(self._h, self.ws.data_ptr(), self.status.data_ptr(),
+                                        _stream_ptr(self.status.device)), "varlingam_fit_batched")
+
+    def aggregate(self):
+        """(P0, P_lags, P_order, count) over the problems that succeeded."""
+        self.P0, self.P_lags, self.P_order, self.count = edge_frequency(
+            self.order, self.B0, self.B_lags, self.threshold, self.status)
+        return self.P0, self.P_lags, self.P_order, self.count
+
+    def check(self) -> list:
+        return [int(v) for v in self.status.cpu().tolist()]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib.varlingam_batch_destroy(h)
+            self._h = None
+
+
+def rolling_windows(X: torch.Tensor, p: int, window: int, stride: int, threshold: float = 0.0,
+                    prec="mixed") -> EnsembleFitter:
+    """Fit every window X[k stride : k stride + window] (no copies) and aggregate."""
+    _require(X, torch.float32, "X")
+    starts = list(range(0, X.shape[0] - window + 1, stride))
+    ef = EnsembleFitter([X[s: s + window] for s in starts], p, prec, threshold)
+    ef.starts = starts
+    ef.run()
+    ef.aggregate()
+    return ef
+
+
+def bootstrap(X: torch.Tensor, p: int, idx, threshold: float = 0.0, prec="mixed"):
+    """Residual bootstrap: fit the VAR of X, regenerate one series per row of the draws idx
+    (R x (n - p), rows of the residual matrix), fit every resample on the batched path and
+    aggregate.  Returns the EnsembleFitter (its views are the resampled series)."""
+    _require(X, torch.float32, "X")
+    n, m = X.shape
+    M, c, E = fit_var(X, p, prec)
+    idx = torch.as_tensor(idx, dtype=torch.int32).to(X.device)
+    series = var_simulate(M, c, X[:p].contiguous(), E, idx)
+    ef = EnsembleFitter(list(series), p, prec, threshold)
+    ef.series = series
+    ef.run()
+    ef.aggregate()
+    return ef
+
+
 def fit_batched(Xs, p: int = 1, prec="mixed", autotune: bool = False):
     """Fit every series in Xs (a list of n_b x m_b arrays or tensors) in one batched pass.
     Returns (results, status codes)."""

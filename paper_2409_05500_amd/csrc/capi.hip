@@ -1,5 +1,6 @@
 // extern "C" entry points: argument validation, workspace carving, status handling.
 #include "backward.hpp"
+#include "ensemble.hpp"
 #include "estimate_b.hpp"
 #include "iterative.hpp"
 #include "order.hpp"
@@ -259,6 +260,56 @@ int varlingam_prune(const float* X, int64_t n, int64_t m, int64_t ldx, int p,
   if (rc) return rc;
   return run_prune(n, m, p, w, X, ldx, order, B0, Blag, max_steps, B0_out, Blag_out, info,
                    dev_status, s);
+}
+
+// ----------------------------------------------------------------------------------------
+static bool sim_shape_ok(int64_t m, int p, int64_t n_e, int64_t R, int64_t T) {
+  return m >= 1 && p >= 1 && m * p <= 4096 && m * (p + 1) <= kSimMaxRing && n_e >= 1 &&
+         R >= 1 && R <= 0x7fffffff && T >= 1;
+}
+
+size_t varlingam_var_simulate_workspace_bytes(int64_t m, int p) {
+  if (!sim_shape_ok(m, p, 1, 1, 1)) return 0;
+  return sim_ws_bytes(m, p);
+}
+
+int varlingam_var_simulate(const double* M, const double* intercept, int64_t m, int p,
+                           const float* X0, int64_t ldx0, const float* E, int64_t n_e,
+                           int64_t lde, const int32_t* idx, int64_t R, int64_t T, float* Xout,
+                           int64_t ldxo, int64_t series_stride, void* ws, size_t ws_bytes,
+                           int32_t* dev_status, void* stream) {
+  if (!M || !intercept || !X0 || !E || !idx || !Xout || !dev_status) return VL_ERR_INVALID_ARG;
+  if (!sim_shape_ok(m, p, n_e, R, T)) return VL_ERR_SHAPE;
+  if (ldx0 < m || lde < m || ldxo < m || series_stride < (p + T) * ldxo)
+    return VL_ERR_INVALID_ARG;
+  if (!ws || ws_bytes < sim_ws_bytes(m, p) || !aligned256(ws)) return VL_ERR_WORKSPACE;
+  hipStream_t s = as_stream(stream);
+  int rc = begin(dev_status, s);
+  if (rc) return rc;
+  return run_var_simulate(M, intercept, m, p, X0, ldx0, E, n_e, lde, idx, R, T, Xout, ldxo,
+                          series_stride, ws, dev_status, s);
+}
+
+size_t varlingam_edge_frequency_workspace_bytes(int64_t K, int64_t m) {
+  if (K < 1 || m < 1 || m > 65536) return 0;
+  return freq_ws_bytes(K, m);
+}
+
+int varlingam_edge_frequency(const int32_t* orders, const double* B0s, const double* Blags,
+                             int64_t K, int64_t m, int p, double threshold,
+                             const int32_t* problem_status, double* P0, double* Plag,
+                             double* P_order, int32_t* count, void* ws, size_t ws_bytes,
+                             int32_t* dev_status, void* stream) {
+  if (!orders || !B0s || !P0 || !P_order || !count || !dev_status) return VL_ERR_INVALID_ARG;
+  if (K < 1 || m < 1 || m > 65536 || p < 0) return VL_ERR_SHAPE;
+  if (p > 0 && (!Blags || !Plag)) return VL_ERR_INVALID_ARG;
+  if (!(threshold >= 0.0)) return VL_ERR_INVALID_ARG;
+  if (!ws || ws_bytes < freq_ws_bytes(K, m) || !aligned256(ws)) return VL_ERR_WORKSPACE;
+  hipStream_t s = as_stream(stream);
+  int rc = begin(dev_status, s);
+  if (rc) return rc;
+  return run_edge_frequency(orders, B0s, Blags, K, m, p, threshold, problem_status, P0, Plag,
+                            P_order, count, ws, dev_status, s);
 }
 
 }  // extern "C"

@@ -166,6 +166,41 @@ def test_prune_host_checks(L):
     assert call(nb=4096) == L.VL_ERR_WORKSPACE
 
 
+def test_ensemble_host_checks(L):
+    lib = L.lib
+    big = 1 << 30
+    assert lib.varlingam_var_simulate_workspace_bytes(100, 2) >= 8 * 2 * 100 * 100
+    assert lib.varlingam_var_simulate_workspace_bytes(3000, 2) == 0     # m (p+1) > 8192
+    sim = lib.varlingam_var_simulate
+    ok = (FAKE, FAKE, 10, 1, FAKE, 10, FAKE, 50, 10, FAKE, 4, 49, FAKE, 10, 500, FAKE, big,
+          FAKE, None)
+
+    def call(changes):
+        a = list(ok)
+        for k, v in changes.items():
+            a[k] = v
+        return sim(*a)
+
+    assert call({0: None}) == L.VL_ERR_INVALID_ARG             # M
+    assert call({9: None}) == L.VL_ERR_INVALID_ARG             # idx
+    assert call({3: 0}) == L.VL_ERR_SHAPE                      # p
+    assert call({7: 0}) == L.VL_ERR_SHAPE                      # n_e
+    assert call({11: 0}) == L.VL_ERR_SHAPE                     # T
+    assert call({13: 9}) == L.VL_ERR_INVALID_ARG               # ldxo < m
+    assert call({14: 499}) == L.VL_ERR_INVALID_ARG             # series overlap
+    assert call({16: 8}) == L.VL_ERR_WORKSPACE
+    fr = lib.varlingam_edge_frequency
+    assert lib.varlingam_edge_frequency_workspace_bytes(0, 5) == 0
+    assert fr(FAKE, FAKE, FAKE, 0, 5, 1, 0.0, None, FAKE, FAKE, FAKE, FAKE, FAKE, big, FAKE,
+              None) == L.VL_ERR_SHAPE
+    assert fr(FAKE, FAKE, None, 3, 5, 1, 0.0, None, FAKE, FAKE, FAKE, FAKE, FAKE, big, FAKE,
+              None) == L.VL_ERR_INVALID_ARG
+    assert fr(FAKE, FAKE, FAKE, 3, 5, 1, -1.0, None, FAKE, FAKE, FAKE, FAKE, FAKE, big, FAKE,
+              None) == L.VL_ERR_INVALID_ARG
+    assert fr(FAKE, FAKE, FAKE, 3, 5, 1, 0.0, None, FAKE, FAKE, FAKE, FAKE, FAKE, 4, FAKE,
+              None) == L.VL_ERR_WORKSPACE
+
+
 def test_build_flags_disable_packed_fp32():
     from paper_2409_05500_amd import build
     f = build.FLAGS
