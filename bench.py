@@ -393,7 +393,7 @@ def main():
                     help="skip the adaptive-lasso pruning section")
     ap.add_argument("--no-ensembles", action="store_true",
                     help="skip the bootstrap / rolling-window section")
-    ap.add_argument("--only", choices=("batch", "backward"), default=None,
+    ap.add_argument("--only", choices=("batch", "backward", "prune", "ensembles"), default=None,
                     help="profiling runs: run just one extra section and print its JSON")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a plain copy "
@@ -416,6 +416,18 @@ def main():
     if args.only == "backward":
         print(json.dumps({"backward": bench_backward(api, _lib, torch, max(3, args.steps // 2),
                                                      args.seed)}), flush=True)
+        return
+    if args.only == "ensembles":
+        print(json.dumps({"ensembles": bench_ensembles(api, torch, max(3, args.steps // 2),
+                                                       args.seed)}), flush=True)
+        return
+    if args.only == "prune":
+        wl = synth.FINANCE
+        X = torch.from_numpy(synth.make_instance(wl, args.seed).X32).to("cuda:0")
+        fit = api.Fitter(wl.n, wl.m, wl.p, "mixed", X.device)
+        fit.run(X)
+        print(json.dumps({"prune": bench_prune(api, torch, X, fit, max(2, args.steps // 4))}),
+              flush=True)
         return
 
     wl = synth.FINANCE
@@ -510,18 +522,28 @@ def main():
         "bf16_vs_mixed": bf16_dev,
         "stage_ms": stage_ms,
     }
+    def progress(msg):
+        print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+    progress("fit timings done")
     if not args.no_iterative:
         out["iterative"] = bench_iterative(api, torch, fit.E, stage_ms, 3)
+    progress("iterative done")
     if not args.no_lag_select:
         out["lag_select"] = bench_lag_select(api, torch, X, 2 * p, 5)
+    progress("lag selection done")
     if not args.no_prune:
         out["prune"] = bench_prune(api, torch, X, fit, 2)
+    progress("pruning done")
     if not args.no_ensembles:
         out["ensembles"] = bench_ensembles(api, torch, 3, args.seed)
+    progress("ensembles done")
     if not args.no_batch:
         out["batched"] = bench_batched(api, torch, max(3, args.steps // 2), args.seed)
+    progress("batched done")
     if not args.no_backward:
         out["backward"] = bench_backward(api, _lib, torch, 3, args.seed)
+    progress("backward done")
     if not args.no_cpu_baseline:
         from oracle import varlingam as O  # noqa: F401  (CPU baseline only)
         out["cpu_baseline"] = cpu_baseline(fit.E.cpu().numpy().astype(np.float64), args.cpu_cols)
