@@ -203,9 +203,9 @@ def bench_prune(api, torch, X, fit, steps):
     """Adaptive-lasso pruning of the fit's B0 / B_tau (complete LARS-lasso paths, BIC knot),
     through the C entry point with preallocated outputs (no synchronisation inside the loop).
     Reports the algorithmic bytes of the path arithmetic: per step the inverse of the active
-    Gram is read and written once (the bordering pass, which also applies the previous
-    bordering's deferred rank-one term: 2 |A|^2 doubles), and |A| entries of the covariance are
-    read for every inactive column (|A| (d - |A|) doubles)."""
+    Gram is read once (to form G_A^{-1} b) and read and written once per 8 steps (the deferred
+    rank-one terms applied together): (1 + 2/8) |A|^2 doubles; |A| entries of the covariance
+    are read for every inactive column (|A| (d - |A|) doubles)."""
     import numpy as np
     from paper_2409_05500_amd._lib import lib
     n, m = X.shape
@@ -247,7 +247,7 @@ def bench_prune(api, torch, X, fit, steps):
         # model: the active set grows by one column per step (exact when no column leaves)
         d = pos + m * p
         a = np.minimum(np.arange(1, int(inf[order[pos]][0]) + 1, dtype=np.float64), d)
-        byts += int(8 * (2 * a * a + a * (d - a)).sum())
+        byts += int(8 * (1.25 * a * a + a * (d - a)).sum())
     nnz0 = int((B0o != 0).sum().item())
     return {"m": m, "n": n, "p": p, "ms": ms, "workspace_bytes": nb,
             "path_steps_total": int(inf[:, 0].sum()), "df_mean": float(inf[:, 2].mean()),

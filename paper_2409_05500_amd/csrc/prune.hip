@@ -11,9 +11,9 @@
 // variable's path on it.  Its state lives in a region of global memory of its own:
 //   Gi   inverse of the (unsigned) Gram of the active columns, updated by bordering when a
 //        column joins and by the Schur complement when one leaves (O(|A|^2) each).  The
-//        rank-one part of a bordering is deferred and applied by the pass that next reads Gi
-//        (the next bordering, which also forms G_A^{-1} b, or a leaving column), so a joining
-//        column costs one read and one write of Gi;
+//        rank-one parts of up to kPruneDefer borderings are kept as a thin factor and applied
+//        together, so a joining column costs one read of Gi (to form G_A^{-1} b) and Gi is
+//        rewritten once per kPruneDefer joins (and before a column leaves);
 //   q    G_A^{-1} s, bordered along with Gi (recomputed from Gi after a column leaves);
 //   c    correlations z~_j^T r with the current residual, updated by c -= gamma a;
 //   beta the scaled coefficients, best the coefficients of the best knot so far.
@@ -102,40 +102,6 @@ __device__ inline void row_axpy(double* __restrict__ M, int64_t ld, int x, doubl
   for (; y < n; ++y) M[(int64_t)y * ld + x] += a * f[y];
 }
 
-// Row x of a column-major matrix: adds a deferred rank-one term a f[y] to M[y ld + x] for
-// y < n1 (stored back) and returns sum_{y < n} M[y ld + x] b[y] of the updated row.
-__device__ inline double row_update_dot(double* __restrict__ M, int64_t ld, int x, double a,
-                                        const double* __restrict__ f, int n1,
-                                        const double* __restrict__ b, int n) {
-  double s[4] = {0.0, 0.0, 0.0, 0.0};
-  int y = 0;
-  for (; y + kU <= n1; y += kU) {
-    double v[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) v[u] = M[(int64_t)(y + u) * ld + x];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      v[u] += a * f[y + u];
-      M[(int64_t)(y + u) * ld + x] = v[u];
-      s[u & 3] += v[u] * b[y + u];
-    }
-  }
-  for (; y < n1; ++y) {
-    const double v = M[(int64_t)y * ld + x] + a * f[y];
-    M[(int64_t)y * ld + x] = v;
-    s[0] += v * b[y];
-  }
-  for (; y + kU <= n; y += kU) {
-    double v[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) v[u] = M[(int64_t)(y + u) * ld + x];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) s[u & 3] += v[u] * b[y + u];
-  }
-  for (; y < n; ++y) s[0] += M[(int64_t)y * ld + x] * b[y];
-  return (s[0] + s[1]) + (s[2] + s[3]);
-}
-
 // Workgroup sum, the same bits in every thread (lane 0 of each wave, waves in a fixed order).
 __device__ inline double wg_sum(double v, double* red) {
   v = wave_sum_d(v);
@@ -171,6 +137,78 @@ __device__ inline void wg_argmin(double& g, int& j, double* rg, int* rj) {
   for (int w = 1; w < kPW; ++w) take_min(g, j, rg[w], rj[w]);
 }
 
+// Values every thread of the workgroup holds alike (read back from LDS after a reduction),
+// declared uniform so they live in scalar registers and branch without divergence.
+__device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline int64_t uni64(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Workgroup sums of kPruneDefer values at once, the same bits in every thread.
+__device__ inline void wg_sum_vec(double (&v)[kPruneDefer], double* red) {
+#pragma unroll
+  for (int q = 0; q < kPruneDefer; ++q) v[q] = wave_sum_d(v[q]);
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+#pragma unroll
+    for (int q = 0; q < kPruneDefer; ++q) red[q * kPW + threadIdx.x / kWave] = v[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kPruneDefer; ++q) {
+    double s = red[q * kPW];
+    for (int w = 1; w < kPW; ++w) s += red[q * kPW + w];
+    v[q] = s;
+  }
+}
+
+constexpr int kFC = 256;  // rows of the deferred factor staged in LDS per flush chunk
+
+// Gi(x, y) += sum_q U_q[x] w_q U_q[y] for x, y < n: the deferred rank-one terms applied in one
+// read and one write of Gi.  us: kPruneDefer x kFC doubles of LDS.
+__device__ inline void flush_deferred(double* __restrict__ Gi, int64_t dA,
+                                      const double* __restrict__ U, int64_t ldu,
+                                      const double* __restrict__ w, int nU, int n,
+                                      double* __restrict__ us) {
+  for (int y0 = 0; y0 < n; y0 += kFC) {
+    const int ny = min(kFC, n - y0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < kPruneDefer * kFC; e += kPT) {
+      const int q = e / kFC, yy = e % kFC;
+      us[e] = q < nU && yy < ny ? U[(int64_t)q * ldu + y0 + yy] * w[q] : 0.0;
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < n; x += kPT) {
+      double ux[kPruneDefer];
+#pragma unroll
+      for (int q = 0; q < kPruneDefer; ++q) ux[q] = q < nU ? U[(int64_t)q * ldu + x] : 0.0;
+      constexpr int kF = 4;  // rows of Gi in flight per group (register budget)
+      int yy = 0;
+      for (; yy + kF <= ny; yy += kF) {
+        double v[kF];
+#pragma unroll
+        for (int u = 0; u < kF; ++u) v[u] = Gi[(int64_t)(y0 + yy + u) * dA + x];
+#pragma unroll
+        for (int u = 0; u < kF; ++u) {
+          double sum = 0.0;
+#pragma unroll
+          for (int q = 0; q < kPruneDefer; ++q) sum += ux[q] * us[q * kFC + yy + u];
+          Gi[(int64_t)(y0 + yy + u) * dA + x] = v[u] + sum;
+        }
+      }
+      for (; yy < ny; ++yy) {
+        double sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < kPruneDefer; ++q) sum += ux[q] * us[q * kFC + yy];
+        Gi[(int64_t)(y0 + yy) * dA + x] += sum;
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // permutation check of the order (one workgroup; m <= 4096)
 __global__ __launch_bounds__(256) void prune_check_order_kernel(const int32_t* __restrict__ order,
                                                                 int64_t m, int32_t* st) {
@@ -192,6 +230,9 @@ __global__ __launch_bounds__(kPT) void prune_lars_kernel(PruneArgs a) {
   __shared__ double rg[kPW];
   __shared__ int rj[kPW];
   __shared__ int slot;
+  __shared__ double redv[kPruneDefer * kPW];
+  __shared__ double wq[kPruneDefer];  // weights 1 / delta of the deferred terms
+  __shared__ double us[kPruneDefer * kFC];
   const int t = threadIdx.x;
   const int64_t m = a.m, mp = m * a.p, ldc = a.ldc;
   const int64_t pos = m - 1 - (int64_t)blockIdx.x;  // the longest designs start first
@@ -200,7 +241,7 @@ __global__ __launch_bounds__(kPT) void prune_lars_kernel(PruneArgs a) {
   // this variable's region: after the regions of positions 0 .. pos-1
   double off = 0.0;
   for (int64_t k = t; k < pos; k += kPT) off += (double)prune_region_doubles(k + mp, a.cap);
-  const int64_t base = (int64_t)wg_sum(off, red);
+  const int64_t base = uni64((int64_t)wg_sum(off, red));
   const int64_t d = pos + mp;
   const int64_t dA = prune_active_cap(d, a.cap);
   double* Gi = a.regions + base;
@@ -214,9 +255,9 @@ __global__ __launch_bounds__(kPT) void prune_lars_kernel(PruneArgs a) {
   double* qv = sv + d;    // G_A^{-1} s of the active slots
   double* dd = qv + d;    // direction of each active slot
   double* bv = dd + d;    // scaled direction, then the bordering column
-  double* pg = bv + d;    // vector of the deferred rank-one term of Gi
-  double* gn = pg + d;    // G_A^{-1} times the bordering column
-  int* idx = reinterpret_cast<int*>(gn + d);  // column of C of each design column
+  double* gn = bv + d;    // G_A^{-1} times the bordering column
+  double* U = gn + d;     // deferred rank-one terms of Gi, kPruneDefer columns of d
+  int* idx = reinterpret_cast<int*>(U + (int64_t)kPruneDefer * d);  // column of C per column
   int* state = idx + d;                       // 0 inactive, 1 active, 2 excluded
   int* act = state + d;                       // design column of each active slot
   int* ac = act + d;                          // its column of C
@@ -250,8 +291,9 @@ __global__ __launch_bounds__(kPT) void prune_lars_kernel(PruneArgs a) {
     nkeep += s > 0.0 ? 1.0 : 0.0;
     if (ok) take_min(g0, j0, -fabs(cj0), (int)j);
   }
-  const int64_t n_keep = (int64_t)wg_sum(nkeep, red);
+  const int64_t n_keep = uni((int)wg_sum(nkeep, red));
   wg_argmin(g0, j0, rg, rj);
+  j0 = uni(j0);
   const double C0 = j0 == kNone ? 0.0 : -g0;
   const double T = (double)a.T, lnT = log(T);
   const double yy = a.C[(int64_t)i * ldc + i];
@@ -274,10 +316,10 @@ __global__ __launch_bounds__(kPT) void prune_lars_kernel(PruneArgs a) {
     __syncthreads();
   }
 
-  // Gi carries a deferred rank-one term pg pg^T prd on its leading n1 x n1 block (n1 = 0:
-  // none), applied by the pass that next reads Gi.
-  int n1 = 0;
-  double prd = 0.0;
+  // The inverse of the active Gram is Gi + sum_{q < nU} U_q wq[q] U_q^T: the rank-one parts of
+  // the last nU borderings are kept as columns of U (zero in the rows of slots added after
+  // them) and applied to Gi every kPruneDefer borderings, or before a column leaves.
+  int nU = 0;
   while (nA > 0 && steps < cap) {
     // A_A = (s^T q)^(-1/2), direction dd = A_A q
     double part = 0.0;
@@ -310,6 +352,7 @@ __global__ __launch_bounds__(kPT) void prune_lars_kernel(PruneArgs a) {
       }
     }
     wg_argmin(gh, jh, rg, rj);
+    jh = uni(jh);
     // first active coefficient to change sign (gamma~)
     double gt = INFINITY;
     int lt = kNone;
@@ -321,6 +364,7 @@ __global__ __launch_bounds__(kPT) void prune_lars_kernel(PruneArgs a) {
       }
     }
     wg_argmin(gt, lt, rg, rj);
+    lt = uni(lt);
     if (jh == kNone) gh = full;
     int event;
     double gamma;
@@ -334,6 +378,7 @@ __global__ __launch_bounds__(kPT) void prune_lars_kernel(PruneArgs a) {
       event = 0;
       gamma = full;
     }
+    event = uni(event);
     // move along the direction
     for (int r = t; r < nA; r += kPT) beta[act[r]] += gamma * dd[r];
     for (int64_t j = t; j < d; j += kPT)
@@ -343,16 +388,15 @@ __global__ __launch_bounds__(kPT) void prune_lars_kernel(PruneArgs a) {
     __syncthreads();
 
     if (event == -1) {
-      if (n1 > 0) {
-        for (int x = t; x < n1; x += kPT) row_axpy(Gi, dA, x, pg[x] * prd, pg, n1);
-        n1 = 0;
-        __syncthreads();
+      if (nU > 0) {
+        flush_deferred(Gi, dA, U, d, wq, nU, nA, us);
+        nU = 0;
       }
       // slot of the leaving column; swap it with the last slot, then take the Schur complement
       for (int r = t; r < nA; r += kPT)
         if (act[r] == lt) slot = r;
       __syncthreads();
-      const int r0 = slot, L = nA - 1;
+      const int r0 = uni(slot), L = nA - 1;
       if (r0 != L) {
         for (int x = t; x < nA; x += kPT) {  // rows
           const double u = Gi[(int64_t)x * dA + r0];
@@ -397,16 +441,28 @@ __global__ __launch_bounds__(kPT) void prune_lars_kernel(PruneArgs a) {
       const double sk = sc[k];
       for (int r = t; r < nA; r += kPT) bv[r] = sc[act[r]] * sk * a.C[(int64_t)ac[r] * ldc + ck];
       __syncthreads();
-      // g = G_A^{-1} b in the same pass that applies the deferred term
+      // g = G_A^{-1} b = Gi b + sum_q U_q wq[q] (U_q^T b): one read of Gi
+      double tv[kPruneDefer];
+#pragma unroll
+      for (int q = 0; q < kPruneDefer; ++q) tv[q] = 0.0;
+      for (int r = t; r < nA; r += kPT) {
+        const double br = bv[r];
+#pragma unroll
+        for (int q = 0; q < kPruneDefer; ++q)
+          if (q < nU) tv[q] += U[(int64_t)q * d + r] * br;
+      }
+      wg_sum_vec(tv, redv);
+#pragma unroll
+      for (int q = 0; q < kPruneDefer; ++q) tv[q] = q < nU ? tv[q] * wq[q] : 0.0;
       double bg = 0.0;
       for (int r = t; r < nA; r += kPT) {
-        const bool pend = r < n1;
-        const double g = row_update_dot(Gi, dA, r, pend ? pg[r] * prd : 0.0, pg, pend ? n1 : 0,
-                                        bv, nA);
+        double g = col_dot(Gi, dA, r, bv, nA);
+#pragma unroll
+        for (int q = 0; q < kPruneDefer; ++q)
+          if (q < nU) g += U[(int64_t)q * d + r] * tv[q];
         gn[r] = g;
         bg += bv[r] * g;
       }
-      n1 = 0;
       const double gkk = sk * sk * a.C[(int64_t)ck * ldc + ck];
       const double delta = gkk - wg_sum(bg, red);
       if (delta <= kCollinearRel * gkk) {
@@ -424,6 +480,7 @@ __global__ __launch_bounds__(kPT) void prune_lars_kernel(PruneArgs a) {
           Gi[(int64_t)nA * dA + x] = -gn[x] * rd;
           Gi[(int64_t)x * dA + nA] = -gn[x] * rd;
           qv[x] += gn[x] * ((gs - sk1) * rd);
+          U[(int64_t)nU * d + x] = gn[x];
         }
         if (t == 0) {
           Gi[(int64_t)nA * dA + nA] = rd;
@@ -432,15 +489,17 @@ __global__ __launch_bounds__(kPT) void prune_lars_kernel(PruneArgs a) {
           sv[nA] = sk1;
           qv[nA] = (sk1 - gs) * rd;
           state[k] = 1;
+          for (int q = 0; q <= nU; ++q) U[(int64_t)q * d + nA] = 0.0;
+          wq[nU] = rd;
         }
-        double* tmp = pg;
-        pg = gn;
-        gn = tmp;
-        prd = rd;
-        n1 = nA;
+        ++nU;
         ++nA;
       }
       __syncthreads();
+      if (nU == kPruneDefer) {
+        flush_deferred(Gi, dA, U, d, wq, nU, nA, us);
+        nU = 0;
+      }
     }
     ++steps;
     // the knot: RSS from the correlations, df = nonzero coefficients

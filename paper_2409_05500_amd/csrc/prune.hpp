@@ -16,11 +16,15 @@ struct PruneWs {
 __host__ __device__ inline int64_t prune_active_cap(int64_t d, int64_t cap) {
   return cap > 0 && cap + 1 < d ? cap + 1 : d;
 }
+// Rank-one updates of the inverse of the active Gram kept aside and applied together.
+constexpr int kPruneDefer = 8;
+
 // Doubles of the region of a variable with d design columns: the inverse of the active Gram
-// (capacity^2), twelve FP64 vectors of d and four int32 vectors of d.
+// (capacity^2), eleven FP64 vectors of d, the kPruneDefer deferred columns of d and four int32
+// vectors of d.
 __host__ __device__ inline int64_t prune_region_doubles(int64_t d, int64_t cap) {
   const int64_t a = prune_active_cap(d, cap);
-  return round_up(a * a + 14 * d, 32);
+  return round_up(a * a + (13 + kPruneDefer) * d, 32);
 }
 
 size_t prune_ws_bytes(int64_t n, int64_t m, int p, int64_t cap, void* base, PruneWs* out);

@@ -52,33 +52,67 @@ __global__ void add_f64_kernel(double* __restrict__ a, const double* __restrict_
 
 // Convergence of the BF16-mode refinement: the last correction d must be below
 // kRefineTol * max|c| (and finite), else the design is too ill-conditioned for a BF16 Gram and
-// VL_ERR_SINGULAR is raised.  One workgroup.
+// VL_ERR_SINGULAR is raised.  Per-workgroup partials into the split scratch, then one workgroup.
 constexpr double kRefineTol = 1e-6;
 
-__global__ __launch_bounds__(256) void refine_check_kernel(const double* __restrict__ d,
-                                                           const double* __restrict__ c,
-                                                           int64_t n, int32_t* st) {
-  __shared__ double sd[256], sc[256];
-  double md = 0.0, mc = 0.0;
-  bool bad = false;
-  for (int64_t e = threadIdx.x; e < n; e += 256) {
+constexpr int kCheckBlocks = 256;
+
+// Per workgroup: max |d|, max |c| and a non-finite flag over a grid-stride slice.
+__global__ __launch_bounds__(256) void refine_partial_kernel(const double* __restrict__ d,
+                                                             const double* __restrict__ c,
+                                                             int64_t n, double* __restrict__ part) {
+  __shared__ double sd[256], sc[256], sb[256];
+  double md = 0.0, mc = 0.0, bad = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
     const double dv = d[e], cv = c[e];
-    bad |= !isfinite(dv) || !isfinite(cv);
+    if (!isfinite(dv) || !isfinite(cv)) bad = 1.0;
     md = fmax(md, fabs(dv));
     mc = fmax(mc, fabs(cv));
   }
   sd[threadIdx.x] = md;
   sc[threadIdx.x] = mc;
+  sb[threadIdx.x] = bad;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
     if ((int)threadIdx.x < h) {
       sd[threadIdx.x] = fmax(sd[threadIdx.x], sd[threadIdx.x + h]);
       sc[threadIdx.x] = fmax(sc[threadIdx.x], sc[threadIdx.x + h]);
+      sb[threadIdx.x] = fmax(sb[threadIdx.x], sb[threadIdx.x + h]);
     }
     __syncthreads();
   }
-  if (bad) raise_status(st, VL_ERR_SINGULAR);
-  if (threadIdx.x == 0 && !(sd[0] <= kRefineTol * sc[0])) raise_status(st, VL_ERR_SINGULAR);
+  if (threadIdx.x == 0) {
+    part[3 * blockIdx.x] = sd[0];
+    part[3 * blockIdx.x + 1] = sc[0];
+    part[3 * blockIdx.x + 2] = sb[0];
+  }
+}
+
+// One workgroup over the partials: the correction must be finite and below kRefineTol of the
+// solution.
+__global__ __launch_bounds__(256) void refine_check_kernel(const double* __restrict__ part,
+                                                           int nb, int32_t* st) {
+  __shared__ double sd[256], sc[256], sb[256];
+  double md = 0.0, mc = 0.0, bad = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) {
+    md = fmax(md, part[3 * b]);
+    mc = fmax(mc, part[3 * b + 1]);
+    bad = fmax(bad, part[3 * b + 2]);
+  }
+  sd[threadIdx.x] = md;
+  sc[threadIdx.x] = mc;
+  sb[threadIdx.x] = bad;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      sd[threadIdx.x] = fmax(sd[threadIdx.x], sd[threadIdx.x + h]);
+      sc[threadIdx.x] = fmax(sc[threadIdx.x], sc[threadIdx.x + h]);
+      sb[threadIdx.x] = fmax(sb[threadIdx.x], sb[threadIdx.x + h]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && (sb[0] != 0.0 || !(sd[0] <= kRefineTol * sc[0])))
+    raise_status(st, VL_ERR_SINGULAR);
 }
 
 __global__ __launch_bounds__(256) void var_residual_kernel(
@@ -151,6 +185,7 @@ size_t var_ws_bytes(const VarPlan& v, void* base, VarWs* out) {
   size_t s3 = (size_t)gram_splits(v.dz, v.m, v.n_eff) * v.dz * v.m;
   size_t s = s1 > s2 ? s1 : s2;
   s = s > s3 ? s : s3;
+  s = s > (size_t)(3 * kCheckBlocks) ? s : (size_t)(3 * kCheckBlocks);  // refinement check
   w.scratch = c.take<double>(s);
   if (out) *out = w;
   return c.used;
@@ -261,7 +296,11 @@ int run_var(const VarPlan& v, const VarWs& w, const float* X, int64_t ldx, int p
       add_f64_kernel<<<(unsigned)ceil_div(dz * m, 256), 256, 0, stream>>>(w.Coef, w.Rres, dz * m);
       VL_LAUNCH_CHECK();
     }
-    refine_check_kernel<<<1, 256, 0, stream>>>(w.Rres, w.Coef, dz * m, st);
+    const int64_t nbl = ceil_div(dz * m, 256);
+    const int nb = (int)(nbl < kCheckBlocks ? nbl : kCheckBlocks);
+    refine_partial_kernel<<<nb, 256, 0, stream>>>(w.Rres, w.Coef, dz * m, w.scratch);
+    VL_LAUNCH_CHECK();
+    refine_check_kernel<<<1, 256, 0, stream>>>(w.scratch, nb, st);
     VL_LAUNCH_CHECK();
   }
   {
