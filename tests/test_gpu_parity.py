@@ -371,3 +371,35 @@ def test_error_order_not_permutation(api, dev):
     with pytest.raises(VarLiNGAMError) as ei:
         api.estimate_B(_dev(Cov, dev), _dev(M, dev), _dev(np.array([0, 1, 1, 3], np.int32), dev))
     assert ei.value.code == VL_ERR_INVALID_ARG
+
+
+def test_var_fit_largest_design(api, dev):
+    """m p = 4096 (m = 2048, p = 2), the largest design the library accepts.  For sampled
+    equations the residual must be orthogonal to every centred regressor (the normal equations
+    of least squares; an error d in one coefficient shows as ~d in its own column's
+    correlation), to 1e-5 of the scale of the terms (FP32 storage of E leaves ~1e-7).  The
+    series are independent AR(2) processes; with 4096 regressors on 8298 samples the
+    least-squares estimates themselves are biased by O(m p / T), so recovery of the generating
+    coefficients is not the check."""
+    rng = np.random.default_rng(17)
+    m, p, n = 2048, 2, 8300
+    x = np.zeros((n + 200, m))
+    a1, a2 = rng.uniform(0.2, 0.5, m), rng.uniform(-0.3, 0.1, m)
+    e = rng.laplace(size=(n + 200, m))
+    for t in range(2, n + 200):
+        x[t] = a1 * x[t - 1] + a2 * x[t - 2] + e[t]
+    X32 = np.ascontiguousarray(x[200:].astype(np.float32))
+    print(f"var fit m={m} p={p} n={n}", flush=True)
+    M, c, E = api.fit_var(_dev(X32, dev), p, "mixed")
+    E = E.cpu().numpy().astype(np.float64)
+    X64 = X32.astype(np.float64)
+    cols = np.concatenate([[0, 1, m - 1], rng.choice(np.arange(2, m - 1), 5, replace=False)])
+    Z = np.hstack([X64[p - 1: n - 1], X64[p - 2: n - 2]])
+    Zc = Z - Z.mean(0)
+    Ec = E[:, cols]
+    G = Zc.T @ Ec
+    scale = np.sqrt((Zc * Zc).sum(0))[:, None] * np.sqrt((Ec * Ec).sum(0))[None, :]
+    err = np.abs(G / scale).max()
+    print(f"  max |z^T e| / (|z| |e|) over all regressors: {err:.1e}", flush=True)
+    assert err <= 1e-5
+    assert np.abs(E.mean(0)).max() <= 1e-5 * np.abs(E).max()      # the intercept

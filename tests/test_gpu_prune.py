@@ -200,3 +200,25 @@ def test_prune_edge_cases(api):
     bad[3] = bad[4]
     with pytest.raises(VarLiNGAMError):
         _run(api, inst.X32, 1, bad, B0, ref["B_lags"])
+
+
+def test_prune_largest_design_step_limit(api):
+    """m (p + 1) = 4095 (m = 1365, p = 2: designs of 1365 .. 4094 columns), step limit 10, weights
+    drawn at random: the first and last variables of the order against the oracle."""
+    rng = np.random.default_rng(21)
+    m, p, n = 1365, 2, 5000
+    x = np.zeros((n + 100, m))
+    e = rng.laplace(size=(n + 100, m))
+    for t in range(1, n + 100):
+        x[t] = 0.4 * x[t - 1] + e[t]
+        x[t, 1:] += 0.3 * x[t, :-1]
+    X32 = np.ascontiguousarray(x[100:].astype(np.float32))
+    order = rng.permutation(m).astype(np.int32)
+    B0 = rng.uniform(0.1, 1.0, (m, m))
+    Bl = rng.uniform(0.1, 1.0, (p, m, m))
+    print("prune m=1365 p=2 step limit 10", flush=True)
+    got = _run(api, X32, p, order, B0, Bl, 10)
+    assert np.all(got[2][:, 0] <= 10)
+    want = P.prune(X32.astype(np.float64), p, order, B0, Bl, max_steps=10,
+                   positions=[0, m - 1])
+    _compare(got, want)
