@@ -6,8 +6,8 @@ namespace vl {
 
 // Row splits used by colmeans(); scratch must hold colmean_splits(K) * ncol doubles.
 inline int colmean_splits(int64_t K) {
-  int64_t s = K / 512;
-  return (int)(s < 1 ? 1 : (s > 64 ? 64 : s));
+  int64_t s = K / 128;
+  return (int)(s < 1 ? 1 : (s > 256 ? 256 : s));
 }
 
 // mean[c] = (1/K) sum_{t<K} A[map(c) + t*lda]  (FP64);  raises VL_ERR_NONFINITE on NaN/Inf.

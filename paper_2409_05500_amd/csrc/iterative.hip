@@ -43,11 +43,24 @@ __global__ __launch_bounds__(256) void iter_select_kernel(const double* __restri
     }
     return;
   }
+  // S is antisymmetric bit for bit (S_ji = -S_ij), so min(0, S_ij)^2 = max(0, S_ji)^2: the
+  // same sum in the same order, read along columns (consecutive threads, consecutive words)
+  // (16 loads in flight, then summed in j order)
+  constexpr int kL = 16;
   for (int64_t i = tid; i < u; i += 256) {
     double s = 0.0;
-    for (int64_t j = 0; j < u; ++j) {
-      const double v = S[i * u + j];
-      if (j != i && v < 0.0) s += v * v;
+    int64_t j = 0;
+    for (; j + kL <= u; j += kL) {
+      double v[kL];
+#pragma unroll
+      for (int q = 0; q < kL; ++q) v[q] = S[(j + q) * u + i];
+#pragma unroll
+      for (int q = 0; q < kL; ++q)
+        if (j + q != i && v[q] > 0.0) s += v[q] * v[q];
+    }
+    for (; j < u; ++j) {
+      const double v = S[j * u + i];
+      if (j != i && v > 0.0) s += v * v;
     }
     Mv[i] = s;
   }
