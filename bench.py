@@ -35,8 +35,8 @@ TRANS_PER_EVAL = 3
 # exactly: x1).  Keyed by the SHA-256 of the kernel sources the counters were taken with
 # (kernel_source_digest); any other source reports null.
 MEASURED_TRAFFIC = {
-    # FETCH_SIZE 34933.4 KiB x 2, WRITE_SIZE 8510.7 KiB x 1 per dispatch (15 dispatches)
-    "159500c59dc7e228286794dec56690d9643c3532ac34256ae6ddd31b7d10ba7b": 80258560,
+    # FETCH_SIZE 34929.6 KiB x 2, WRITE_SIZE 8508.7 KiB x 1 per dispatch (15 dispatches)
+    "463560af90cf3f9ebb236cf3daacf386283135ce864a7e78a6d6feb883bb24f2": 80248644,
 }
 STAGES = ("var_gram", "var_solve", "var_residual", "var_refine", "pairwise_cov",
           "pairwise_prep", "pairwise_moments", "pairwise_combine", "order", "estimate_b")

@@ -44,12 +44,20 @@ __device__ inline void hx_block(const float* __restrict__ Xs, int64_t n_pad, int
   __shared__ double ra[4], rb[4];
   const float* x = Xs + i * n_pad;
   double sa = 0.0, sb = 0.0;
-  for (int64_t t = threadIdx.x; t < n_eff; t += 256) {
-    const float u = x[t];
+  auto term = [&](float u) {
     const float a = fabsf(u);
     sa += (double)(a + log1pf(expf(-2.f * a)) - (float)kLn2);
     sb += (double)(u * expf(-0.5f * u * u));
+  };
+  int64_t t = threadIdx.x;
+  for (; t + 7 * 256 < n_eff; t += 8 * 256) {  // eight loads in flight, summed in order
+    float u[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) u[q] = x[t + q * 256];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) term(u[q]);
   }
+  for (; t < n_eff; t += 256) term(x[t]);
   sa = wave_sum_d(sa);
   sb = wave_sum_d(sb);
   if ((threadIdx.x & 63) == 0) {
