@@ -5,9 +5,10 @@ C ABI (include/varlingam.h).
 `import paper_2409_05500_amd` loads nothing; the HIP library is loaded on first use of the
 API (`paper_2409_05500_amd.api`), which raises if libvarlingam.so has not been built.
 """
-_API = ("fit", "fit_var", "pairwise_stats", "approx_order", "estimate_B", "FitResult",
-        "DeviceStatus", "pairwise_stats_backward", "pairwise_stats_save", "pairwise_score", "PairwiseScore",
-        "BatchFitter", "fit_batched")
+_API = ("fit", "fit_var", "pairwise_stats", "approx_order", "estimate_B", "FitResult", "Fitter",
+        "DeviceStatus", "pairwise_stats_backward", "pairwise_stats_save", "pairwise_score",
+        "PairwiseScore", "BatchFitter", "fit_batched", "order_iterative", "select_lag", "prune",
+        "var_simulate", "edge_frequency", "EnsembleFitter", "rolling_windows", "bootstrap")
 
 
 def __getattr__(name):
