@@ -33,7 +33,8 @@ namespace vl {
 namespace {
 
 constexpr int kPT = 512;            // threads per variable
-constexpr int kU = 8;               // independent loads in flight per thread
+constexpr int kU = 8;               // independent loads in flight per thread (row updates)
+constexpr int kUD = 16;             // independent loads in flight per thread (dot products)
 constexpr int kPW = kPT / kWave;
 constexpr double kGammaRel = 1e-12;
 constexpr double kCollinearRel = 1e-12;
@@ -60,12 +61,12 @@ __device__ inline double col_dot(const double* __restrict__ M, int64_t ld, int r
                                  const double* __restrict__ v, int n) {
   double s[4] = {0.0, 0.0, 0.0, 0.0};
   int k = 0;
-  for (; k + kU <= n; k += kU) {
-    double x[kU];
+  for (; k + kUD <= n; k += kUD) {
+    double x[kUD];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) x[u] = M[(int64_t)(k + u) * ld + r];
+    for (int u = 0; u < kUD; ++u) x[u] = M[(int64_t)(k + u) * ld + r];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) s[u & 3] += x[u] * v[k + u];
+    for (int u = 0; u < kUD; ++u) s[u & 3] += x[u] * v[k + u];
   }
   for (; k < n; ++k) s[0] += M[(int64_t)k * ld + r] * v[k];
   return (s[0] + s[1]) + (s[2] + s[3]);
@@ -77,12 +78,12 @@ __device__ inline double gather_dot(const double* __restrict__ Cj, int64_t ld,
                                     int n) {
   double s[4] = {0.0, 0.0, 0.0, 0.0};
   int r = 0;
-  for (; r + kU <= n; r += kU) {
-    double x[kU];
+  for (; r + kUD <= n; r += kUD) {
+    double x[kUD];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) x[u] = Cj[(int64_t)col[r + u] * ld];
+    for (int u = 0; u < kUD; ++u) x[u] = Cj[(int64_t)col[r + u] * ld];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) s[u & 3] += x[u] * w[r + u];
+    for (int u = 0; u < kUD; ++u) s[u & 3] += x[u] * w[r + u];
   }
   for (; r < n; ++r) s[0] += Cj[(int64_t)col[r] * ld] * w[r];
   return (s[0] + s[1]) + (s[2] + s[3]);
