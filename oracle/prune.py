@@ -27,8 +27,10 @@ unspecified.  Readings taken here (each also listed in the design notes):
 
 Pinned by (tests marked "not gpu"): the lasso optimality (KKT) conditions at every knot,
 agreement of the knots with scikit-learn's lars_path(method="lasso"), the least-squares end of
-the path, the closed form of a one-regressor path, the scale invariance of the adaptive lasso,
-and recovery of the true support on long strongly identified series.
+the path, the closed form of a one-regressor path, BIC as the Gaussian likelihood criterion
+(an independent density routine), the Frisch-Waugh identity behind the weights, invariance
+under rescaling and under constant offsets, a zero weight leaving its column out, a duplicated
+column never entering, and recovery of the true support on long strongly identified series.
 """
 from __future__ import annotations
 
