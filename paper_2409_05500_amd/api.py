@@ -165,6 +165,19 @@ def pairwise_stats_backward(E: torch.Tensor, G: torch.Tensor, prec="mixed",
     return dE
 
 
+def edge_influence(E: torch.Tensor, i: int, j: int, prec="mixed",
+                   saved: "torch.Tensor | None" = None) -> torch.Tensor:
+    """Per-sample influence of the residuals on one edge direction: dS[i, j]/dE (n_eff x m
+    f32), the backward with a one-hot cotangent.  Row t, column k: how S[i, j] (positive when
+    the data favour j -> i over i -> j) moves with e_k(t)."""
+    m = E.shape[1]
+    if not (0 <= i < m and 0 <= j < m):
+        raise ValueError(f"edge ({i}, {j}) outside 0 .. {m - 1}")
+    G = torch.zeros((m, m), dtype=torch.float64, device=E.device)
+    G[i, j] = 1.0
+    return pairwise_stats_backward(E, G, prec, saved=saved)
+
+
 class PairwiseScore(torch.autograd.Function):
     """S = score(E) with a backward through the HIP gradient kernels; the forward keeps the
     O(m^2) block of statistics the backward needs (no recompute of the moments)."""

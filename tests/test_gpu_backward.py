@@ -184,3 +184,28 @@ def test_backward_zero_variance_raises(api, dev):
     E32[:, 3] = 1.5
     with pytest.raises(VarLiNGAMError):
         api.pairwise_stats_backward(_dev(E32, dev), _dev(np.ones((5, 5)), dev))
+
+
+def test_edge_influence(api, dev):
+    """dS[i, j]/dE for single edges: the one-hot cotangent's gradient against the FP64
+    reference, the antisymmetry dS[j, i] = -dS[i, j], and a zero diagonal edge."""
+    m, n = 7, 900
+    E32 = _residuals(m, n, 12)
+    Ed = _dev(E32, dev)
+    for i, j in ((0, 1), (5, 2), (6, 3)):
+        G = np.zeros((m, m))
+        G[i, j] = 1.0
+        dE = api.edge_influence(Ed, i, j).cpu().numpy().astype(np.float64)
+        ref = OB.grad_E(E32.astype(np.float64), G).numpy()
+        _, mag, cmag = OB.grad_E_columns(E32.astype(np.float64), G, list(range(m)),
+                                         with_scale=True)
+        bound = K_ULP * UNIT * mag + DA * cmag
+        err = np.abs(dE - ref)
+        live = bound > 0                  # columns outside the edge: exactly zero on both sides
+        assert np.all(err[~live] == 0.0)
+        ratio = float((err[live] / bound[live]).max())
+        print(f"  edge ({i}, {j}): max err / bound {ratio:.3f}", flush=True)
+        assert ratio <= 1.0
+        back = api.edge_influence(Ed, j, i).cpu().numpy()
+        assert np.array_equal(back, -dE)
+    assert torch.count_nonzero(api.edge_influence(Ed, 4, 4)).item() == 0
