@@ -203,10 +203,14 @@ def approx_order(S: np.ndarray):
 # ---------------------------------------------------------------------------------------------
 # Sec. 3 steps 1-5 -- the original iterative DirectLiNGAM ordering (comparator only)
 # ---------------------------------------------------------------------------------------------
-def directlingam_iterative(E: np.ndarray):
+def directlingam_iterative(E: np.ndarray, k_exact: int | None = None):
     """Original DirectLiNGAM causal-order search: score all pairs on the current data, pick the
     most independent variable, then replace every remaining column by its residual on it
-    (Sec. 3 step 5) and repeat.  O(m^3 n).  Returns the order."""
+    (Sec. 3 step 5) and repeat.  O(m^3 n).  Returns the order.
+
+    With k_exact, a hybrid: the first k_exact picks as above, then the heuristic of Sec. 4.2 /
+    Alg. 1 on the refined data of the remaining variables (one pairwise precompute, lookup-only
+    selection).  k_exact = 0 is the heuristic on E; k_exact >= m - 1 the original search."""
     X = np.array(E, dtype=np.float64, copy=True)
     m = X.shape[1]
     U = list(range(m))
@@ -214,6 +218,11 @@ def directlingam_iterative(E: np.ndarray):
     while U:
         if len(U) == 1:
             order.append(U.pop())
+            break
+        if k_exact is not None and len(order) == k_exact:
+            _, _, S_rest = pairwise_stats(X[:, U])
+            rest, _ = approx_order(S_rest)
+            order.extend(U[int(r)] for r in rest)
             break
         Xs = {i: standardize(X[:, i]) for i in U}
         H = {i: entropy(Xs[i]) for i in U}

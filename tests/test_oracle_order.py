@@ -141,3 +141,30 @@ def test_exhaustive_tiny_permutations():
         oP, _ = O.approx_order(S[np.ix_(P, P)])
         # variable k of the permuted problem is variable P[k] of the original one
         assert list(P[oP]) == list(order)
+
+
+def test_hybrid_reduces_to_the_two_searches():
+    """k exact steps then the heuristic on the refined data: k = 0 is Alg. 1 on E, k >= m - 1
+    the original search, and any k keeps the original search's first k picks."""
+    for seed in range(3):
+        inst = synth.make_custom(6, 1500, 1, "laplace", 40 + seed, edge_prob=0.4)
+        _, _, E = O.fit_var(inst.X_parity, 1)
+        _, _, S = O.pairwise_stats(E)
+        heur, _ = O.approx_order(S)
+        full = O.directlingam_iterative(E)
+        assert list(O.directlingam_iterative(E, k_exact=0)) == list(heur)
+        assert list(O.directlingam_iterative(E, k_exact=5)) == list(full)
+        assert list(O.directlingam_iterative(E, k_exact=6)) == list(full)
+        for k in (1, 2, 3):
+            hyb = O.directlingam_iterative(E, k_exact=k)
+            assert sorted(hyb.tolist()) == list(range(6))
+            assert list(hyb[:k]) == list(full[:k])
+
+
+def test_hybrid_recovers_the_generating_order():
+    """Strongly non-Gaussian data with a known DAG: every split point gives an order consistent
+    with the generating B0."""
+    inst = synth.make_custom(5, 6000, 1, "uniform", 3, edge_prob=0.6, w_lo=0.5, w_hi=0.9)
+    _, _, E = O.fit_var(inst.X_parity, 1)
+    for k in range(6):
+        assert _order_violations(O.directlingam_iterative(E, k_exact=k), inst.B0) == 0, k
