@@ -149,10 +149,22 @@ def bench_iterative(api, torch, E, stage_ms, steps):
     heur = sum(stage_ms.get(k, 0.0) for k in ("pairwise_cov", "pairwise_prep", "pairwise_moments",
                                               "pairwise_combine", "order"))
     evals = sum(u * (u - 1) for u in range(2, m + 1)) * n_eff
-    return {"m": m, "n_eff": n_eff, "ms": it_ms, "sample_evals": evals,
-            "sample_evals_per_s": evals / (it_ms / 1e3),
-            "heuristic_precompute_plus_order_ms": heur,
-            "speedup_heuristic_vs_iterative": it_ms / heur if heur else None}
+    out = {"m": m, "n_eff": n_eff, "ms": it_ms, "sample_evals": evals,
+           "sample_evals_per_s": evals / (it_ms / 1e3),
+           "heuristic_precompute_plus_order_ms": heur,
+           "speedup_heuristic_vs_iterative": it_ms / heur if heur else None}
+    for k in (10,):                                 # hybrid: k exact picks, then the heuristic
+        if k >= m - 1:
+            continue
+        api.order_hybrid(E, k)
+        torch.cuda.synchronize()
+        t0.record()
+        for _ in range(steps):
+            api.order_hybrid(E, k)
+        t1.record()
+        torch.cuda.synchronize()
+        out[f"hybrid_k{k}_ms"] = t0.elapsed_time(t1) / steps
+    return out
 
 
 def bench_lag_select(api, torch, X, p_max, steps):

@@ -193,6 +193,19 @@ int varlingam_order_iterative(const float* E, int64_t n_eff, int64_t m, int64_t 
                               int32_t* dev_status, void* stream);
 
 /* ------------------------------------------------------------------------------------- */
+/* Hybrid ordering: the first k_exact picks of the original search above (with its residual */
+/* updates), then the heuristic (Sec. 4.2, Alg. 1) on the refined data of the remaining     */
+/* variables: one pairwise precompute and the lookup-only selection.  k_exact = 0 orders E */
+/* exactly as pairwise_stats + approx_order do; k_exact >= m - 1 is the original search.   */
+/* Arguments, workspace and errors as varlingam_order_iterative; order / margin entries     */
+/* from k_exact on are the heuristic's.  k_exact < 0 -> VL_ERR_INVALID_ARG.                 */
+/* ------------------------------------------------------------------------------------- */
+size_t varlingam_order_hybrid_workspace_bytes(int64_t n_eff, int64_t m, int prec);
+int varlingam_order_hybrid(const float* E, int64_t n_eff, int64_t m, int64_t lde, int prec,
+                           int64_t k_exact, int32_t* order, double* margin, void* ws,
+                           size_t ws_bytes, int32_t* dev_status, void* stream);
+
+/* ------------------------------------------------------------------------------------- */
 /* B0 and lag matrices from the order (Sec. 4: estimation of the instantaneous matrix B0; */
 /* Sec. 2.1: VarLiNGAM lag matrices).                                                     */
 /*   B0[K_k, K_<k] = least-squares coefficients of e_{K_k} on its predecessors, obtained   */

@@ -7,9 +7,9 @@ API (`paper_2409_05500_amd.api`), which raises if libvarlingam.so has not been b
 """
 _API = ("fit", "fit_var", "pairwise_stats", "approx_order", "estimate_B", "FitResult", "Fitter",
         "DeviceStatus", "pairwise_stats_backward", "pairwise_stats_save", "pairwise_score",
-        "PairwiseScore", "BatchFitter", "fit_batched", "order_iterative", "select_lag", "prune",
-        "var_simulate", "edge_frequency", "EnsembleFitter", "rolling_windows", "bootstrap",
-        "edge_influence")
+        "PairwiseScore", "BatchFitter", "fit_batched", "order_iterative", "order_hybrid",
+        "select_lag", "prune", "var_simulate", "edge_frequency", "EnsembleFitter",
+        "rolling_windows", "bootstrap", "edge_influence")
 
 
 def __getattr__(name):

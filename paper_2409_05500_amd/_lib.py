@@ -54,6 +54,9 @@ SIGNATURES = {
     "approx_order": (_i32, [_p, _i64, _p, _p, _p, _sz, _p, _p]),
     "varlingam_order_iterative_workspace_bytes": (_sz, [_i64, _i64, _i32]),
     "varlingam_order_iterative": (_i32, [_p, _i64, _i64, _i64, _i32, _p, _p, _p, _sz, _p, _p]),
+    "varlingam_order_hybrid_workspace_bytes": (_sz, [_i64, _i64, _i32]),
+    "varlingam_order_hybrid": (_i32, [_p, _i64, _i64, _i64, _i32, _i64, _p, _p, _p, _sz, _p,
+                                      _p]),
     "estimate_B_workspace_bytes": (_sz, [_i64, _i32]),
     "estimate_B": (_i32, [_p, _p, _p, _i64, _i32, _p, _p, _p, _sz, _p, _p]),
     "varlingam_var_simulate_workspace_bytes": (_sz, [_i64, _i32]),

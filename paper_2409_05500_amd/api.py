@@ -235,6 +235,26 @@ def order_iterative(E: torch.Tensor, prec="mixed", status: "DeviceStatus | None"
     return order, margin
 
 
+def order_hybrid(E: torch.Tensor, k_exact: int, prec="mixed",
+                 status: "DeviceStatus | None" = None):
+    """(order [m] int32, margin [m] f64): the original search's first k_exact picks, then the
+    heuristic's lookup-only ordering of the remaining variables on their refined data."""
+    _require(E, torch.float32, "E")
+    n_eff, m = E.shape
+    dev = E.device
+    order = torch.empty(m, dtype=torch.int32, device=dev)
+    margin = torch.empty(m, dtype=torch.float64, device=dev)
+    ws = _workspace(lib.varlingam_order_hybrid_workspace_bytes(n_eff, m, _prec(prec)), dev)
+    st = status if status is not None else DeviceStatus(dev)
+    check(lib.varlingam_order_hybrid(E.data_ptr(), n_eff, m, E.stride(0), _prec(prec), k_exact,
+                                     order.data_ptr(), margin.data_ptr(), ws.data_ptr(),
+                                     ws.numel(), st.ptr, _stream_ptr(dev)),
+          "varlingam_order_hybrid")
+    if status is None:
+        st.read("varlingam_order_hybrid")
+    return order, margin
+
+
 def estimate_B(Cov: torch.Tensor, M: torch.Tensor, order: torch.Tensor,
                status: "DeviceStatus | None" = None):
     """(B0 [m, m], B_lags [p, m, m]) f64 from the residual covariance, VAR matrices and order."""

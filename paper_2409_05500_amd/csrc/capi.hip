@@ -134,7 +134,28 @@ int varlingam_order_iterative(const float* E, int64_t n_eff, int64_t m, int64_t 
   hipStream_t s = as_stream(stream);
   int rc = begin(dev_status, s);
   if (rc) return rc;
-  return run_order_iterative(E, n_eff, m, lde, prec, order, margin, w, dev_status, s);
+  return run_order_iterative(E, n_eff, m, lde, prec, m, order, margin, w, dev_status, s);
+}
+
+size_t varlingam_order_hybrid_workspace_bytes(int64_t n_eff, int64_t m, int prec) {
+  return varlingam_order_iterative_workspace_bytes(n_eff, m, prec);
+}
+
+int varlingam_order_hybrid(const float* E, int64_t n_eff, int64_t m, int64_t lde, int prec,
+                           int64_t k_exact, int32_t* order, double* margin, void* ws,
+                           size_t ws_bytes, int32_t* dev_status, void* stream) {
+  if (!E || !order || !margin || !dev_status || !valid_prec(prec) || k_exact < 0)
+    return VL_ERR_INVALID_ARG;
+  if (m < 1 || m > 4096 || n_eff < 2) return VL_ERR_SHAPE;
+  if (lde < m) return VL_ERR_INVALID_ARG;
+  const size_t need = iter_ws_bytes(n_eff, m, nullptr, nullptr);
+  if (!ws || ws_bytes < need || !aligned256(ws)) return VL_ERR_WORKSPACE;
+  IterWs w;
+  iter_ws_bytes(n_eff, m, ws, &w);
+  hipStream_t s = as_stream(stream);
+  int rc = begin(dev_status, s);
+  if (rc) return rc;
+  return run_order_iterative(E, n_eff, m, lde, prec, k_exact, order, margin, w, dev_status, s);
 }
 
 // ----------------------------------------------------------------------------------------

@@ -10,6 +10,7 @@
 // sum_u u^2 n = O(m^3 n) sample-evals in all.  The loop is launched from the host without
 // synchronisation: the pick stays on the device.
 #include "iterative.hpp"
+#include "order.hpp"
 #include "pairwise.hpp"
 #include "profile.hpp"
 
@@ -130,6 +131,17 @@ __global__ void iter_refine_kernel(const float* __restrict__ Ek, int64_t ldk, in
   if (t == 0) idx_out[jp] = idx_in[j];
 }
 
+// Hybrid finish: the remaining variables' lookup order, mapped to original indices.
+__global__ void iter_map_kernel(const int32_t* __restrict__ osub,
+                                const int32_t* __restrict__ idx, int64_t u,
+                                int32_t* __restrict__ order) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= u) return;
+  int32_t v = osub[r];
+  v = v < 0 ? 0 : (v >= u ? (int32_t)u - 1 : v);
+  order[r] = idx[v];
+}
+
 size_t iter_ws_bytes(int64_t n_eff, int64_t m, void* base, IterWs* out) {
   Carver c(base);
   IterWs w;
@@ -146,13 +158,15 @@ size_t iter_ws_bytes(int64_t n_eff, int64_t m, void* base, IterWs* out) {
   for (int64_t u = 2; u <= m; ++u)
     pw = std::max(pw, pairwise_ws_bytes(plan_pairwise(n_eff, u), nullptr, nullptr));
   w.pw = c.take<char>(pw);
+  w.osub = c.take<int32_t>(m);
+  w.M0 = c.take<double>(m);
   if (out) *out = w;
   return c.used;
 }
 
 int run_order_iterative(const float* E, int64_t n_eff, int64_t m, int64_t lde, int prec,
-                        int32_t* order, double* margin, const IterWs& w, int32_t* st,
-                        hipStream_t stream) {
+                        int64_t k_exact, int32_t* order, double* margin, const IterWs& w,
+                        int32_t* st, hipStream_t stream) {
   if (m > kIterMaxM) return VL_ERR_SHAPE;
   ProfileScope ps("iterative", stream);
   iter_init_kernel<<<(unsigned)ceil_div(m, (int64_t)256), 256, 0, stream>>>(w.idx[0], m);
@@ -168,6 +182,14 @@ int run_order_iterative(const float* E, int64_t n_eff, int64_t m, int64_t lde, i
       pairwise_ws_bytes(p, w.pw, &pw);
       int rc = run_pairwise(p, pw, cur, ldc, prec, w.Hx, w.Hr, w.S, w.Cov, nullptr, st, stream);
       if (rc) return rc;
+      if (k == k_exact) {             // hybrid: the heuristic orders the remaining variables
+        rc = run_order(w.S, u, w.osub, margin + k, w.M0, st, stream);
+        if (rc) return rc;
+        iter_map_kernel<<<(unsigned)ceil_div(u, (int64_t)256), 256, 0, stream>>>(
+            w.osub, idx_in, u, order + k);
+        VL_LAUNCH_CHECK();
+        return VL_OK;
+      }
     }
     iter_select_kernel<<<1, 256, 0, stream>>>(w.S, u, idx_in, k, order, margin, w.pick);
     VL_LAUNCH_CHECK();

@@ -51,21 +51,16 @@ def b_rel_error(B, B_ref):
     return float(np.max(np.abs(B - B_ref) / np.maximum(np.abs(B_ref), floor)))
 
 
-def iterative_order_violations(order, E, tie=ORDER_TIE):
-    """Walk a GPU order of the original iterative DirectLiNGAM search (Sec. 3 steps 1-5) with
-    the oracle's arithmetic: at each step the oracle's aggregates on its current data must put
-    the GPU's pick within `tie` of their minimum; the oracle's data is then refined with the
-    GPU's pick.  Returns the list of (step, gpu_pick, gap) that fail."""
-    X = np.array(E, dtype=np.float64, copy=True)
-    m = X.shape[1]
-    U = list(range(m))
-    bad = []
-    for k, c in enumerate(np.asarray(order).tolist()):
+def _iterative_walk(order, X, U, steps, tie, bad):
+    """The first `steps` picks of a GPU order checked with the oracle's arithmetic on its current
+    data X (columns U), which is then refined with the GPU's pick (Sec. 3 step 5)."""
+    for k, c in enumerate(np.asarray(order).tolist()[:steps]):
         if c not in U:
             bad.append((k, c, np.inf))
-            break
+            return False
         if len(U) == 1:
-            break
+            U.remove(c)
+            return True
         Xs = {i: O.standardize(X[:, i]) for i in U}
         H = {i: O.entropy(Xs[i]) for i in U}
         Hr = {(i, j): O.entropy(O.standardize(O.residual(Xs[i], Xs[j])))
@@ -78,4 +73,33 @@ def iterative_order_violations(order, E, tie=ORDER_TIE):
         U.remove(c)
         for j in U:
             X[:, j] = O.residual(Xs[j], Xs[c])
+    return True
+
+
+def iterative_order_violations(order, E, tie=ORDER_TIE):
+    """Walk a GPU order of the original iterative DirectLiNGAM search (Sec. 3 steps 1-5) with
+    the oracle's arithmetic: at each step the oracle's aggregates on its current data must put
+    the GPU's pick within `tie` of their minimum; the oracle's data is then refined with the
+    GPU's pick.  Returns the list of (step, gpu_pick, gap) that fail."""
+    X = np.array(E, dtype=np.float64, copy=True)
+    U = list(range(X.shape[1]))
+    bad = []
+    _iterative_walk(order, X, U, X.shape[1], tie, bad)
     return bad
+
+
+def hybrid_order_violations(order, E, k_exact, tie=ORDER_TIE):
+    """A GPU hybrid order: its first k_exact picks walked as in iterative_order_violations,
+    the rest checked with order_violations against the oracle's precompute of its data refined
+    with the GPU's picks."""
+    X = np.array(E, dtype=np.float64, copy=True)
+    U = list(range(X.shape[1]))
+    bad = []
+    if not _iterative_walk(order, X, U, k_exact, tie, bad) or len(U) < 2:
+        return bad
+    rest = np.asarray(order).tolist()[k_exact:]
+    if sorted(rest) != sorted(U):
+        return bad + [(k_exact, -1, np.inf)]
+    _, _, S_rest = O.pairwise_stats(X[:, U])
+    local = [U.index(v) for v in rest]
+    return bad + [(k_exact + s, v, g) for s, v, g in order_violations(local, S_rest, tie)]

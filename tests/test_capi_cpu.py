@@ -122,6 +122,14 @@ def test_iterative_and_lag_selection_host_checks(L):
     assert it(FAKE, 100, 4, 3, 1, FAKE, FAKE, FAKE, big, FAKE, None) == L.VL_ERR_INVALID_ARG
     assert it(FAKE, 100, 4, 4, 7, FAKE, FAKE, FAKE, big, FAKE, None) == L.VL_ERR_INVALID_ARG
     assert it(FAKE, 100, 4, 4, 1, FAKE, FAKE, FAKE, 16, FAKE, None) == L.VL_ERR_WORKSPACE
+    # hybrid ordering: the same checks, and k_exact >= 0
+    assert lib.varlingam_order_hybrid_workspace_bytes(1000, 40, 1) == \
+        lib.varlingam_order_iterative_workspace_bytes(1000, 40, 1)
+    hy = lib.varlingam_order_hybrid
+    assert hy(FAKE, 100, 4, 4, 1, -1, FAKE, FAKE, FAKE, big, FAKE, None) == L.VL_ERR_INVALID_ARG
+    assert hy(FAKE, 100, 5000, 5000, 1, 3, FAKE, FAKE, FAKE, big, FAKE, None) == L.VL_ERR_SHAPE
+    assert hy(FAKE, 100, 4, 3, 1, 2, FAKE, FAKE, FAKE, big, FAKE, None) == L.VL_ERR_INVALID_ARG
+    assert hy(FAKE, 100, 4, 4, 1, 2, FAKE, FAKE, FAKE, 16, FAKE, None) == L.VL_ERR_WORKSPACE
     # lag selection: p_max >= 1, n - p_max > m p_max + 1, m p_max <= 4096
     assert lib.varlingam_select_lag_workspace_bytes(1000, 10, 4) > 0
     assert lib.varlingam_select_lag_workspace_bytes(30, 10, 4) == 0

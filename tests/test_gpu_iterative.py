@@ -91,3 +91,47 @@ def test_iterative_degenerate_raises(api):
     E[:, 5] = 0.25
     with pytest.raises(VarLiNGAMError):
         api.order_iterative(torch.from_numpy(E).cuda())
+
+
+@pytest.mark.parametrize("case", CASES[2:], ids=lambda c: c[0].workload.name)
+def test_hybrid_order_matches_oracle(api, case):
+    """k exact picks of the original search, then the lookup ordering on the refined data of
+    the rest: walked with parity.hybrid_order_violations at several splits.  k = 0 is the
+    heuristic's order of E itself and k >= m - 1 the original search's."""
+    inst, p = case
+    E = _residuals(inst, p)
+    m = E.shape[1]
+    Ed = torch.from_numpy(E).cuda()
+    _, _, S, _ = api.pairwise_stats(Ed)
+    he, mh = api.approx_order(S)
+    it, mi = api.order_iterative(Ed)
+    for k in sorted({0, 1, min(3, m), m // 2, m - 1, m, m + 5}):
+        print(f"hybrid {inst.workload.name} k={k}", flush=True)
+        order, margin = api.order_hybrid(Ed, k)
+        assert sorted(order.cpu().tolist()) == list(range(m))
+        assert np.isinf(float(margin[-1]))
+        if k == 0:
+            assert torch.equal(order, he) and torch.equal(margin, mh)
+        if k >= m - 1:
+            assert torch.equal(order, it) and torch.equal(margin, mi)
+        if 0 < k < m - 1:
+            assert torch.equal(order[:k], it[:k])
+            bad = PA.hybrid_order_violations(order.cpu().numpy(), E, k)
+            assert bad == [], (k, bad)
+
+
+def test_hybrid_recovers_the_generating_order(api):
+    """Strongly non-Gaussian data with a known DAG, every split k walked against the oracle.
+    The heuristic tail is an approximation: here, as in the oracle's own hybrid, k <= 1 puts
+    two effects before their causes, and from k = 2 on the order is a topological order of
+    the generating B0."""
+    inst = synth.make_custom(8, 20000, 1, "uniform", 5, edge_prob=0.4, w_lo=0.5, w_hi=0.9)
+    E = _residuals(inst, 1)
+    Ed = torch.from_numpy(E).cuda()
+    for k in range(9):
+        order = api.order_hybrid(Ed, k)[0].cpu().numpy()
+        assert PA.hybrid_order_violations(order, E, k) == [], k
+        pos = {int(v): s for s, v in enumerate(order)}
+        viol = [(i, j) for i in range(8) for j in range(8)
+                if inst.B0[i, j] != 0 and pos[j] > pos[i]]
+        assert (viol == []) == (k >= 2), (k, viol)

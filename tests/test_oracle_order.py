@@ -168,3 +168,21 @@ def test_hybrid_recovers_the_generating_order():
     _, _, E = O.fit_var(inst.X_parity, 1)
     for k in range(6):
         assert _order_violations(O.directlingam_iterative(E, k_exact=k), inst.B0) == 0, k
+
+
+def test_hybrid_walker_accepts_the_oracle_and_rejects_a_swap():
+    """The GPU tests' hybrid walker: the oracle's own hybrid order passes it; the same order
+    with two clearly separated picks of the heuristic tail swapped does not."""
+    import parity as PA
+    inst = synth.make_custom(6, 1500, 1, "laplace", 41, edge_prob=0.4)
+    _, _, E = O.fit_var(inst.X_parity, 1)
+    for k in (1, 2, 3):
+        hyb = O.directlingam_iterative(E, k_exact=k)
+        assert PA.hybrid_order_violations(hyb, E, k) == []
+        bad = hyb.copy()
+        bad[k], bad[-1] = bad[-1], bad[k]
+        v = PA.hybrid_order_violations(bad, E, k)
+        assert v and v[0][0] == k
+        early = hyb.copy()
+        early[0], early[-1] = early[-1], early[0]
+        assert PA.hybrid_order_violations(early, E, k)[0][0] == 0
