@@ -14,9 +14,12 @@ inline int colmean_splits(int64_t K) {
 int colmeans(const float* A, int64_t lda, const int64_t* colmap, int64_t ncol, int64_t K,
              double* mean, double* scratch, int32_t* st, hipStream_t stream);
 
-// Split-K factor of gram_tn(); scratch must hold gram_splits(M,N,K) * M * N doubles.
+// Split-K factor of gram_tn(); scratch must hold gram_splits(M,N,K) * M * N doubles.  About
+// 1024 workgroups (four per CU): with M == N the tiles counted are the lower triangle's, which
+// is all a symmetric Gram launches (a square non-symmetric one then gets the same splits).
 inline int gram_splits(int64_t M, int64_t N, int64_t K) {
-  int64_t tiles = ceil_div(M, 64) * ceil_div(N, 64);
+  const int64_t tm = ceil_div(M, 64);
+  int64_t tiles = M == N ? tm * (tm + 1) / 2 : tm * ceil_div(N, 64);
   int64_t s = ceil_div(1024, tiles);
   int64_t smax = K / 256;
   if (smax < 1) smax = 1;

@@ -166,39 +166,38 @@ __device__ inline void var_residual_tile_f64(
 }
 
 // ------------------------------------------------------------------------------------------
-// Wide FP64 residual tile: 128 samples x 64 variables per workgroup; wave (wi, wj) of the 2 x 2
-// waves owns 64 x 32 = 4 x 2 blocks of v_mfma_f64_16x16x4f64.  Stages of kRK lags through LDS
+// FP64 residual tile: RT samples x 64 variables per workgroup; wave (wi, wj) of the 2 x 2 waves
+// owns RT/2 x 32 = RT/32 x 2 blocks of v_mfma_f64_16x16x4f64.  Stages of RK lags through LDS
 // (the centred lag values widened to FP64 once, at load); the next stage's global loads are in
-// flight during the products.  Same arithmetic and result as var_residual_tile_f64.
+// flight during the products.  Every output element sums its products in lag order four at a
+// time whatever RT and RK, so all shapes give the same bits, and the same as
+// var_residual_tile_f64.
 // ------------------------------------------------------------------------------------------
-constexpr int kRT = 128;       // samples per tile
 constexpr int kRJ = 64;        // variables per tile
-constexpr int kRK = 16;        // lags per stage
-constexpr int kRZ = kRT + 1;   // LDS row strides (doubles)
-constexpr int kRC = kRJ + 1;
 
-template <class TOut>
+template <class TOut, int RT, int RK>
 __device__ inline void var_residual_tile_f64w(
     const float* __restrict__ X, int64_t ldx, const int64_t* __restrict__ colmap,
     const double* __restrict__ mu, int64_t m, int p, int64_t n_eff,
     const double* __restrict__ Coef, TOut* __restrict__ E, int64_t lde, int64_t t0, int64_t j0) {
-  __shared__ double Zs[kRK][kRZ];
-  __shared__ double Cs[kRK][kRC];
+  constexpr int XB = RT / 32;                  // 16-row blocks per wave
+  __shared__ double Zs[RK][RT + 1];
+  __shared__ double Cs[RK][kRJ + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wi = wave >> 1, wj = wave & 1, li = lane & 15, lk = lane >> 4;
   const int64_t dz = m * p;
   const int64_t* mapZ = colmap + m;
   const double* muZ = mu + m;
-  f64x4 acc[4][2];
+  f64x4 acc[XB][2];
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
+  for (int x = 0; x < XB; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = f64x4{0.0, 0.0, 0.0, 0.0};
-  constexpr int kZRows = 256 / kRK;            // Z loader: kRK lags x kZRows sample rows a pass
-  constexpr int kZPass = kRT / kZRows;
-  const int zk = tid % kRK, zt = tid / kRK;
+  constexpr int kZRows = 256 / RK;             // Z loader: RK lags x kZRows sample rows a pass
+  constexpr int kZPass = RT / kZRows;
+  const int zk = tid % RK, zt = tid / RK;
   const int cj = tid & 63, ck = tid >> 6;      // Coef loader: 64 variables x 4 lags per pass
-  double rz[kZPass], rc[kRK / 4];
+  double rz[kZPass], rc[RK / 4];
   // Every load reads a clamped in-bounds address and the padding is selected afterwards, so
   // the loads of a stage issue back to back (no branch, no wait per load).
   const int64_t jc = j0 + cj < m ? j0 + cj : m - 1;
@@ -215,7 +214,7 @@ __device__ inline void var_residual_tile_f64w(
       xv[u] = X[off + (t < n_eff ? t : n_eff - 1) * ldx];
     }
 #pragma unroll
-    for (int u = 0; u < kRK / 4; ++u) {
+    for (int u = 0; u < RK / 4; ++u) {
       const int64_t kq = k0 + ck + 4 * u;
       const double cv = Coef[(kq < dz ? kq : dz - 1) * m + jc];
       rc[u] = mask_f64(cv, kq < dz && vj);
@@ -227,22 +226,22 @@ __device__ inline void var_residual_tile_f64w(
     }
   };
   load(0);
-  for (int64_t k0 = 0; k0 < dz; k0 += kRK) {
+  for (int64_t k0 = 0; k0 < dz; k0 += RK) {
 #pragma unroll
     for (int u = 0; u < kZPass; ++u) Zs[zk][zt + kZRows * u] = rz[u];
 #pragma unroll
-    for (int u = 0; u < kRK / 4; ++u) Cs[ck + 4 * u][cj] = rc[u];
+    for (int u = 0; u < RK / 4; ++u) Cs[ck + 4 * u][cj] = rc[u];
     __syncthreads();
-    if (k0 + kRK < dz) load(k0 + kRK);
+    if (k0 + RK < dz) load(k0 + RK);
 #pragma unroll
-    for (int kk = 0; kk < kRK; kk += 4) {
-      double a[4], b[2];
+    for (int kk = 0; kk < RK; kk += 4) {
+      double a[XB], b[2];
 #pragma unroll
-      for (int x = 0; x < 4; ++x) a[x] = Zs[kk + lk][wi * 64 + x * 16 + li];
+      for (int x = 0; x < XB; ++x) a[x] = Zs[kk + lk][wi * (RT / 2) + x * 16 + li];
 #pragma unroll
       for (int y = 0; y < 2; ++y) b[y] = Cs[kk + lk][wj * 32 + y * 16 + li];
 #pragma unroll
-      for (int x = 0; x < 4; ++x)
+      for (int x = 0; x < XB; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y)
           acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
@@ -250,12 +249,12 @@ __device__ inline void var_residual_tile_f64w(
     __syncthreads();
   }
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
+  for (int x = 0; x < XB; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t t = t0 + wi * 64 + x * 16 + lk + 4 * r;     // f64 D layout
+        const int64_t t = t0 + wi * (RT / 2) + x * 16 + lk + 4 * r;     // f64 D layout
         const int64_t j = j0 + wj * 32 + y * 16 + li;
         if (t < n_eff && j < m) {
           const double yv = (double)X[colmap[j] + t * ldx] - mu[j];

@@ -123,13 +123,33 @@ __global__ __launch_bounds__(256) void var_residual_kernel(
                         (int64_t)blockIdx.y * 64, (int64_t)blockIdx.x * 64);
 }
 
-template <class TOut>
+template <class TOut, int RT, int RK>
 __global__ __launch_bounds__(256) void var_residual_f64w_kernel(
     const float* __restrict__ X, int64_t ldx, const int64_t* __restrict__ colmap,
     const double* __restrict__ mu, int64_t m, int p, int64_t n_eff,
     const double* __restrict__ Coef, TOut* __restrict__ E, int64_t lde) {
-  var_residual_tile_f64w<TOut>(X, ldx, colmap, mu, m, p, n_eff, Coef, E, lde,
-                               (int64_t)blockIdx.y * kRT, (int64_t)blockIdx.x * kRJ);
+  var_residual_tile_f64w<TOut, RT, RK>(X, ldx, colmap, mu, m, p, n_eff, Coef, E, lde,
+                                       (int64_t)blockIdx.y * RT, (int64_t)blockIdx.x * kRJ);
+}
+
+// The residual's tile shape.  The loop is bound by load latency, so occupancy decides: below
+// ~8 workgroups per CU at 64 samples a tile, 32-sample tiles with 32 lags a stage (four waves
+// per SIMD) beat the wider tiles (m = 400, n = 10000, p = 2: 194 us against 224 us at 64 x 16
+// and 288 us at 128 x 16, the same bits); above it 64 x 16 is ~2% ahead.
+template <class TOut>
+static void launch_residual_f64w(const float* X, int64_t ldx, const int64_t* colmap,
+                                 const double* mu, int64_t m, int p, int64_t n_eff,
+                                 const double* Coef, TOut* E, int64_t lde, hipStream_t stream) {
+  const int64_t tj = ceil_div(m, (int64_t)kRJ);
+  if (ceil_div(n_eff, (int64_t)64) * tj >= 8 * 256) {
+    dim3 grid((unsigned)tj, (unsigned)ceil_div(n_eff, (int64_t)64));
+    var_residual_f64w_kernel<TOut, 64, 16><<<grid, 256, 0, stream>>>(X, ldx, colmap, mu, m, p,
+                                                                     n_eff, Coef, E, lde);
+  } else {
+    dim3 grid((unsigned)tj, (unsigned)ceil_div(n_eff, (int64_t)32));
+    var_residual_f64w_kernel<TOut, 32, 32><<<grid, 256, 0, stream>>>(X, ldx, colmap, mu, m, p,
+                                                                     n_eff, Coef, E, lde);
+  }
 }
 
 // M[(tau-1) m m + i m + k] = Coef[(tau-1) m + k][i]
@@ -194,9 +214,8 @@ size_t var_ws_bytes(const VarPlan& v, void* base, VarWs* out) {
 static int var_residual(const VarPlan& v, const VarWs& w, const float* X, int64_t ldx, float* E,
                         int64_t lde, bool fp64, hipStream_t stream) {
   if (fp64) {
-    dim3 grid((unsigned)ceil_div(v.m, (int64_t)kRJ), (unsigned)ceil_div(v.n_eff, (int64_t)kRT));
-    var_residual_f64w_kernel<float><<<grid, 256, 0, stream>>>(X, ldx, w.colmap, w.mu, v.m, v.p,
-                                                              v.n_eff, w.Coef, E, lde);
+    launch_residual_f64w<float>(X, ldx, w.colmap, w.mu, v.m, v.p, v.n_eff, w.Coef, E, lde,
+                                stream);
     VL_LAUNCH_CHECK();
     return VL_OK;
   }
@@ -278,12 +297,9 @@ int run_var(const VarPlan& v, const VarWs& w, const float* X, int64_t ldx, int p
   if (refine) {
     ProfileScope ps("var_refine", stream);
     for (int it = 0; it < kBf16RefineSteps; ++it) {
-      {
-        dim3 grid((unsigned)ceil_div(m, (int64_t)kRJ), (unsigned)ceil_div(n_eff, (int64_t)kRT));
-        var_residual_f64w_kernel<double><<<grid, 256, 0, stream>>>(X, ldx, w.colmap, w.mu, m,
-                                                                   v.p, n_eff, w.Coef, w.E64, m);
-        VL_LAUNCH_CHECK();
-      }
+      launch_residual_f64w<double>(X, ldx, w.colmap, w.mu, m, v.p, n_eff, w.Coef, w.E64, m,
+                                   stream);
+      VL_LAUNCH_CHECK();
       rc = gram_tn_f64b(X, ldx, mapZ, muZ, dz, w.E64, m, m, n_eff, w.Rres, m, w.scratch, stream);
       if (rc) return rc;
       // correction L^{-T} L^{-1} Rres (two triangular products with the explicit inverse)
