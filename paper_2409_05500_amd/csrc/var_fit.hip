@@ -200,9 +200,11 @@ size_t var_ws_bytes(const VarPlan& v, void* base, VarWs* out) {
   w.Tmp = c.take<double>(v.dz * v.m);
   w.chol = c.take<double>(chol_ws_doubles(v.dz));
   w.E64 = c.take<double>(v.n_eff * v.m);
+  w.F = c.take<double>(v.m * nc);
+  w.mu0 = c.take<double>(nc);
   size_t s1 = (size_t)colmean_splits(v.n_eff) * nc;
-  size_t s2 = (size_t)gram_splits(v.dz, v.dz, v.n_eff) * v.dz * v.dz;
-  size_t s3 = (size_t)gram_splits(v.dz, v.m, v.n_eff) * v.dz * v.m;
+  size_t s2 = (size_t)gram_splits(v.m, nc, v.n_eff) * v.m * nc;
+  size_t s3 = (size_t)gram_splits(v.dz, v.m, v.n_eff) * v.dz * v.m;   // refinement Gram
   size_t s = s1 > s2 ? s1 : s2;
   s = s > s3 ? s : s3;
   s = s > (size_t)(3 * kCheckBlocks) ? s : (size_t)(3 * kCheckBlocks);  // refinement check
@@ -229,14 +231,57 @@ static int var_residual(const VarPlan& v, const VarWs& w, const float* X, int64_
   return VL_OK;
 }
 
+// mu0[h m + j] = mu[j]: every lag block of the lag products is centred by the lag-0 means.
+__global__ void lag_mu0_kernel(const double* __restrict__ mu, int64_t m, int64_t nc,
+                               double* __restrict__ mu0) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nc) mu0[e] = mu[e % m];
+}
+
+// G (dz x dz, both triangles) and R (dz x m) of the VAR normal equations from the lag products
+// F (see var_normal_equations).  Column (tau, i) of the regression is x_i(t - tau), t = p .. n-1,
+// with window mean mu[tau m + i]; xt = x - mu_0 and d_tau = mu_tau - mu_0.  For tau1 >= tau2,
+// h = tau1 - tau2, the window sum sum_t xt_j(t - tau2) xt_i(t - tau1) is F_h[j][i] with the
+// tau2 rows that the window gains at its start added and the tau2 rows it loses at its end taken
+// away, and G = that sum - n_eff d_tau1[i] d_tau2[j].  R's block tau is F_tau^T (d_0 = 0).
+__global__ void var_assemble_kernel(const float* __restrict__ X, int64_t ldx,
+                                    const double* __restrict__ F, const double* __restrict__ mu,
+                                    int64_t m, int p, int64_t n, double* __restrict__ G,
+                                    double* __restrict__ R) {
+  const int64_t dz = m * p, nc = m * (p + 1);
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < dz * dz) {
+    const int64_t r = e / dz, c = e % dz;
+    if (c > r) return;
+    const int64_t t1 = r / m + 1, i = r % m, t2 = c / m + 1, j = c % m, h = t1 - t2;
+    const double ci = mu[i], cj = mu[j];
+    double wv = F[j * nc + h * m + i];
+    for (int64_t s = p - t2; s < p; ++s)
+      wv += ((double)X[s * ldx + j] - cj) * ((double)X[(s - h) * ldx + i] - ci);
+    for (int64_t s = n - t2; s < n; ++s)
+      wv -= ((double)X[s * ldx + j] - cj) * ((double)X[(s - h) * ldx + i] - ci);
+    const double di = mu[t1 * m + i] - ci, dj = mu[t2 * m + j] - cj;
+    const double g = wv - (double)(n - p) * di * dj;
+    G[r * dz + c] = g;
+    G[c * dz + r] = g;
+    return;
+  }
+  e -= dz * dz;
+  if (e >= dz * m) return;
+  const int64_t r = e / m, j = e % m;
+  R[r * m + j] = F[j * nc + m + r];
+}
+
 // Column map, means, G = Zc^T Zc and R = Zc^T Yc (R into Tmp, where the forward substitution
-// of the factorisation works on it).
+// of the factorisation works on it).  The p^2 + p blocks of G and R are shifted windows of p + 1
+// lag products F_h[i][j] = sum_{s = p}^{n-1} xt_i(s) xt_j(s - h), h = 0 .. p, so one Gram of
+// the lag-0 columns against all m (p + 1) columns (every one centred by the lag-0 means) and a
+// rank-2p boundary correction per entry give them: m^2 (p + 1) n products instead of
+// (p^2 / 2 + p) m^2 n.
 static int var_normal_equations(const VarPlan& v, const VarWs& w, const float* X, int64_t ldx,
                                 GramMode gmode, int32_t* st, hipStream_t stream) {
   const int64_t m = v.m, dz = v.dz, n_eff = v.n_eff;
   const int64_t nc = m * (v.p + 1);
-  const int64_t* mapZ = w.colmap + m;
-  const double* muZ = w.mu + m;
   int rc;
   {
     ProfileScope ps("var_gram", stream);
@@ -246,13 +291,14 @@ static int var_normal_equations(const VarPlan& v, const VarWs& w, const float* X
     VL_LAUNCH_CHECK();
     rc = colmeans(X, ldx, w.colmap, nc, n_eff, w.mu, w.scratch, st, stream);
     if (rc) return rc;
-    // G = Zc^T Zc, R = Zc^T Yc (R into Tmp, where the substitution works on it)
-    rc = gram_tn(X, ldx, mapZ, muZ, dz, X, ldx, mapZ, muZ, dz, n_eff, gmode, 1.0, w.G, dz,
-                 w.scratch, stream, true);
+    lag_mu0_kernel<<<(unsigned)ceil_div(nc, 256), 256, 0, stream>>>(w.mu, m, nc, w.mu0);
+    VL_LAUNCH_CHECK();
+    rc = gram_tn(X, ldx, w.colmap, w.mu, m, X, ldx, w.colmap, w.mu0, nc, n_eff, gmode, 1.0, w.F,
+                 nc, w.scratch, stream);
     if (rc) return rc;
-    rc = gram_tn(X, ldx, mapZ, muZ, dz, X, ldx, w.colmap, w.mu, m, n_eff, gmode, 1.0, w.Tmp, m,
-                 w.scratch, stream);
-    if (rc) return rc;
+    var_assemble_kernel<<<(unsigned)ceil_div(dz * dz + dz * m, 256), 256, 0, stream>>>(
+        X, ldx, w.F, w.mu, m, v.p, v.n, w.G, w.Tmp);
+    VL_LAUNCH_CHECK();
   }
   return VL_OK;
 }

@@ -21,6 +21,8 @@ struct VarWs {
   double* Tmp = nullptr;      // dz x m intermediate of the two triangular solves
   double* chol = nullptr;     // factorisation scratch kept for the solves
   double* E64 = nullptr;      // n_eff x m FP64 residual of the refinement step
+  double* F = nullptr;        // m x m (p+1) lag products F_h (see var_normal_equations)
+  double* mu0 = nullptr;      // m (p+1): the lag-0 means repeated for every lag block
   double* scratch = nullptr;  // split-K partials
 };
 
