@@ -203,10 +203,12 @@ size_t var_ws_bytes(const VarPlan& v, void* base, VarWs* out) {
   w.F = c.take<double>(v.m * nc);
   w.mu0 = c.take<double>(nc);
   size_t s1 = (size_t)colmean_splits(v.n_eff) * nc;
-  size_t s2 = (size_t)gram_splits(v.m, nc, v.n_eff) * v.m * nc;
-  size_t s3 = (size_t)gram_splits(v.dz, v.m, v.n_eff) * v.dz * v.m;   // refinement Gram
+  size_t s2 = (size_t)gram_splits(v.m, nc, v.n_eff) * v.m * nc;      // lag products
+  size_t s3 = (size_t)gram_splits(v.dz, v.m, v.n_eff) * v.dz * v.m;   // R, refinement Gram
+  size_t s4 = (size_t)gram_splits(v.dz, v.dz, v.n_eff) * v.dz * v.dz; // direct G
   size_t s = s1 > s2 ? s1 : s2;
   s = s > s3 ? s : s3;
+  s = s > s4 ? s : s4;
   s = s > (size_t)(3 * kCheckBlocks) ? s : (size_t)(3 * kCheckBlocks);  // refinement check
   w.scratch = c.take<double>(s);
   if (out) *out = w;
@@ -273,11 +275,18 @@ __global__ void var_assemble_kernel(const float* __restrict__ X, int64_t ldx,
 }
 
 // Column map, means, G = Zc^T Zc and R = Zc^T Yc (R into Tmp, where the forward substitution
-// of the factorisation works on it).  The p^2 + p blocks of G and R are shifted windows of p + 1
-// lag products F_h[i][j] = sum_{s = p}^{n-1} xt_i(s) xt_j(s - h), h = 0 .. p, so one Gram of
-// the lag-0 columns against all m (p + 1) columns (every one centred by the lag-0 means) and a
-// rank-2p boundary correction per entry give them: m^2 (p + 1) n products instead of
-// (p^2 / 2 + p) m^2 n.
+// of the factorisation works on it).
+// * FP64 products (kFp64): the p^2 + p blocks of G and R are shifted windows of p + 1 lag
+//   products F_h[i][j] = sum_{s = p}^{n-1} xt_i(s) xt_j(s - h), h = 0 .. p, so one Gram of the
+//   lag-0 columns against all m (p + 1) columns (every one centred by the lag-0 means) and a
+//   rank-2p boundary correction per entry give them: m^2 (p + 1) n products instead of
+//   (p^2 / 2 + p) m^2 n.  The products are exact, so the assembled G equals the direct one to
+//   FP64 rounding.
+// * FP32 and BF16 products: the direct Grams.  A Gram of rounded data is the exact Gram of
+//   slightly different data, hence positive semidefinite; G assembled from rounded lag
+//   products and exact corrections is not the Gram of anything and loses definiteness at
+//   BF16's 2^-9 (an emulation at m = 70, p = 4, cond(G) = 1e4: smallest eigenvalue 136 exact,
+//   136 direct, -307 assembled).
 static int var_normal_equations(const VarPlan& v, const VarWs& w, const float* X, int64_t ldx,
                                 GramMode gmode, int32_t* st, hipStream_t stream) {
   const int64_t m = v.m, dz = v.dz, n_eff = v.n_eff;
@@ -291,14 +300,25 @@ static int var_normal_equations(const VarPlan& v, const VarWs& w, const float* X
     VL_LAUNCH_CHECK();
     rc = colmeans(X, ldx, w.colmap, nc, n_eff, w.mu, w.scratch, st, stream);
     if (rc) return rc;
-    lag_mu0_kernel<<<(unsigned)ceil_div(nc, 256), 256, 0, stream>>>(w.mu, m, nc, w.mu0);
-    VL_LAUNCH_CHECK();
-    rc = gram_tn(X, ldx, w.colmap, w.mu, m, X, ldx, w.colmap, w.mu0, nc, n_eff, gmode, 1.0, w.F,
-                 nc, w.scratch, stream);
+    if (gmode == GramMode::kFp64) {
+      lag_mu0_kernel<<<(unsigned)ceil_div(nc, 256), 256, 0, stream>>>(w.mu, m, nc, w.mu0);
+      VL_LAUNCH_CHECK();
+      rc = gram_tn(X, ldx, w.colmap, w.mu, m, X, ldx, w.colmap, w.mu0, nc, n_eff, gmode, 1.0,
+                   w.F, nc, w.scratch, stream);
+      if (rc) return rc;
+      var_assemble_kernel<<<(unsigned)ceil_div(dz * dz + dz * m, 256), 256, 0, stream>>>(
+          X, ldx, w.F, w.mu, m, v.p, v.n, w.G, w.Tmp);
+      VL_LAUNCH_CHECK();
+      return VL_OK;
+    }
+    const int64_t* mapZ = w.colmap + m;
+    const double* muZ = w.mu + m;
+    rc = gram_tn(X, ldx, mapZ, muZ, dz, X, ldx, mapZ, muZ, dz, n_eff, gmode, 1.0, w.G, dz,
+                 w.scratch, stream, true);
     if (rc) return rc;
-    var_assemble_kernel<<<(unsigned)ceil_div(dz * dz + dz * m, 256), 256, 0, stream>>>(
-        X, ldx, w.F, w.mu, m, v.p, v.n, w.G, w.Tmp);
-    VL_LAUNCH_CHECK();
+    rc = gram_tn(X, ldx, mapZ, muZ, dz, X, ldx, w.colmap, w.mu, m, n_eff, gmode, 1.0, w.Tmp, m,
+                 w.scratch, stream);
+    if (rc) return rc;
   }
   return VL_OK;
 }
