@@ -457,9 +457,16 @@ size_t lag_ws_bytes(const VarPlan& v, void* base, LagWs* out) {
   w.A = c.take<double>(m * m);
   w.Li = c.take<double>(m * m);
   w.chol = c.take<double>(chol_ws_doubles(m));
-  w.gscr = c.take<double>((size_t)gram_splits(m, m, v.n_eff) * m * m);
   if (out) *out = w;
   return c.used;
+}
+
+__global__ void lag_syy_kernel(const double* __restrict__ F, int64_t m, int64_t ldf,
+                               double* __restrict__ Syy) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m * m) return;
+  const int64_t i = e / m, j = e % m;
+  Syy[e] = i >= j ? F[i * ldf + j] : F[j * ldf + i];
 }
 
 int run_lag_select(const VarPlan& v, const LagWs& w, const float* X, int64_t ldx, double* logdet,
@@ -474,10 +481,11 @@ int run_lag_select(const VarPlan& v, const LagWs& w, const float* X, int64_t ldx
     if (rc) return rc;
   }
   ProfileScope ps("lag_scores", stream);
-  // T Sigma_0 = Yc^T Yc (the lag-0 columns: the first m of the column map)
-  rc = gram_tn(X, ldx, vw.colmap, vw.mu, m, X, ldx, vw.colmap, vw.mu, m, n_eff, GramMode::kFp64,
-               1.0, w.Syy, m, w.gscr, stream, true);
-  if (rc) return rc;
+  // T Sigma_0 = Yc^T Yc: the lag product F_0 of the normal equations (lag-0 columns centred by
+  // their own means), its lower triangle mirrored
+  lag_syy_kernel<<<(unsigned)ceil_div(m * m, 256), 256, 0, stream>>>(vw.F, m, m * (v.p + 1),
+                                                                     w.Syy);
+  VL_LAUNCH_CHECK();
   const double T = (double)n_eff;
   for (int p = 1; p <= v.p; ++p) {
     const double* Wp = vw.Tmp + (int64_t)(p - 1) * m * m;

@@ -33,7 +33,6 @@ struct LagWs {
   double* A = nullptr;      // copy factored for the log-determinant
   double* Li = nullptr;     // its L^{-1}
   double* chol = nullptr;   // factorisation scratch (m)
-  double* gscr = nullptr;   // split-K partials of Yc^T Yc
 };
 
 VarPlan plan_var(int64_t n, int64_t m, int p);
