@@ -40,11 +40,12 @@ __device__ inline double rsqrt_f64(double d) {
 // ------------------------------------------------------------------------------------------
 constexpr int kLeaf = 16;
 
+// One v_mov_b64_dpp into a fresh register (64-bit DPP takes row_newbcast on gfx950; every source
+// lane of a row broadcast exists, so bound_ctrl changes nothing).  The 32-bit-pair form with a
+// zeroed "old" operand took four instructions per broadcast.
 template <int N>
 __device__ __attribute__((always_inline)) inline double row_bcast(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x150 + N, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x150 + N, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
+  return __builtin_amdgcn_mov_dpp(v, 0x150 + N, 0xF, 0xF, true);
 }
 
 template <int C, int Q>
