@@ -16,8 +16,10 @@ namespace vl {
 template <int kCtrl>
 __device__ inline double dpp_f64(double v) {
   const int lo = __double2loint(v), hi = __double2hiint(v);
-  return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, kCtrl, 0xF, 0xF, false),
-                          __builtin_amdgcn_update_dpp(0, lo, kCtrl, 0xF, 0xF, false));
+  // mov_dpp writes a fresh register (no zeroed "old" operand to set up); the mirror and quad
+  // permutations used here give every lane a source lane, so bound_ctrl changes nothing
+  return __hiloint2double(__builtin_amdgcn_mov_dpp(hi, kCtrl, 0xF, 0xF, true),
+                          __builtin_amdgcn_mov_dpp(lo, kCtrl, 0xF, 0xF, true));
 }
 
 template <class T>
@@ -56,10 +58,10 @@ __device__ inline double wave_min_f64(double v) {
 }
 
 __device__ inline int wave_min_i32(int v) {
-  v = min(v, __builtin_amdgcn_update_dpp(0, v, kDppRowMirror, 0xF, 0xF, false));
-  v = min(v, __builtin_amdgcn_update_dpp(0, v, kDppHalfMirror, 0xF, 0xF, false));
-  v = min(v, __builtin_amdgcn_update_dpp(0, v, kDppQuadXor2, 0xF, 0xF, false));
-  v = min(v, __builtin_amdgcn_update_dpp(0, v, kDppQuadXor1, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_mov_dpp(v, kDppRowMirror, 0xF, 0xF, true));
+  v = min(v, __builtin_amdgcn_mov_dpp(v, kDppHalfMirror, 0xF, 0xF, true));
+  v = min(v, __builtin_amdgcn_mov_dpp(v, kDppQuadXor2, 0xF, 0xF, true));
+  v = min(v, __builtin_amdgcn_mov_dpp(v, kDppQuadXor1, 0xF, 0xF, true));
   v = min(v, partner16(v));
   v = min(v, partner32(v));
   return v;
