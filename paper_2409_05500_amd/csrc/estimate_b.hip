@@ -8,6 +8,7 @@
 // L^{-1} = diag(Lc) Lc^{-1}, and diag(Lc) = 1 / diag(Lc^{-1}): only Lc^{-1} is formed (by the
 // fused factorisation).  Then B_tau = (I - B0) M_tau.
 #include "estimate_b.hpp"
+#include "chol_dev.hpp"
 #include "linalg.hpp"
 #include "profile.hpp"
 
@@ -52,9 +53,14 @@ __global__ void assemble_b0_kernel(const double* __restrict__ Linv, const int32_
   B0[(int64_t)ka * m + kb] = b < a ? -Linv[a * m + b] / Linv[a * m + a] : 0.0;
 }
 
-__global__ void copy_f64_kernel(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n) b[e] = a[e];
+// B_tau = M_tau - B0 M_tau for every lag in one launch (blockIdx.z = tau - 1): the FP64 MFMA
+// GEMM block with its beta term read from M_tau, so no copy of M_tau into B_tau first.
+__global__ __launch_bounds__(256) void blag_kernel(const double* __restrict__ B0,
+                                                   const double* __restrict__ M, int64_t m,
+                                                   double* __restrict__ Blag) {
+  const int64_t off = (int64_t)blockIdx.z * m * m;
+  gemm_f64_block(m, m, m, -1.0, B0, m, 0, M + off, m, 0, 1.0, Blag + off, m, 0, 0,
+                 (int64_t)blockIdx.y * 32, (int64_t)blockIdx.x * 32, M + off);
 }
 
 size_t b_ws_bytes(int64_t m, void* base, BWs* out) {
@@ -82,13 +88,10 @@ int run_estimate_b(const BWs& w, const double* Cov, const double* M, const int32
   if (rc) return rc;
   assemble_b0_kernel<<<g, 256, 0, stream>>>(w.Linv, K, m, B0);
   VL_LAUNCH_CHECK();
-  for (int tau = 0; tau < p; ++tau) {
-    const double* Mt = M + (int64_t)tau * m * m;
-    double* Bt = Blag + (int64_t)tau * m * m;
-    copy_f64_kernel<<<g, 256, 0, stream>>>(Mt, Bt, m * m);
+  if (p > 0) {
+    dim3 grid((unsigned)ceil_div(m, (int64_t)32), (unsigned)ceil_div(m, (int64_t)32), (unsigned)p);
+    blag_kernel<<<grid, 256, 0, stream>>>(B0, M, m, Blag);
     VL_LAUNCH_CHECK();
-    rc = gemm_f64(m, m, m, -1.0, B0, m, false, Mt, m, false, 1.0, Bt, m, false, stream);
-    if (rc) return rc;
   }
   return VL_OK;
 }
