@@ -60,13 +60,29 @@ __global__ __launch_bounds__(256) void colsum_partial_kernel(const float* __rest
     part[(int64_t)blockIdx.y * ncol + c] = ((red[0][cc] + red[1][cc]) + red[2][cc]) + red[3][cc];
 }
 
+// sum_{z < splits} P[z * stride + e] in split order.  Eight loads are issued before they are
+// added (the same sum): colmean_final has a few thousand threads at most, so their latency is
+// hidden by loads in flight, not by other waves.
+__device__ inline double sum_splits_at(const double* __restrict__ P, int splits, int64_t stride,
+                                       int64_t e) {
+  double s = 0.0;
+  int z = 0;
+  for (; z + 8 <= splits; z += 8) {
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = P[(int64_t)(z + q) * stride + e];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s += v[q];
+  }
+  for (; z < splits; ++z) s += P[(int64_t)z * stride + e];
+  return s;
+}
+
 __global__ void colmean_final_kernel(const double* __restrict__ part, int64_t ncol, int splits,
                                      int64_t K, double* __restrict__ mean) {
   int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncol) return;
-  double s = 0.0;
-  for (int z = 0; z < splits; ++z) s += part[(int64_t)z * ncol + c];
-  mean[c] = s / (double)K;
+  mean[c] = sum_splits_at(part, splits, ncol, c) / (double)K;
 }
 
 int colmeans(const float* A, int64_t lda, const int64_t* colmap, int64_t ncol, int64_t K,
@@ -226,8 +242,7 @@ __global__ void sum_splits_kernel(const double* __restrict__ P, int splits, int6
                                   double scale, double* __restrict__ C, int64_t ldc) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= M * N) return;
-  double s = 0.0;
-  for (int z = 0; z < splits; ++z) s += P[(int64_t)z * M * N + e];
+  const double s = sum_splits_at(P, splits, M * N, e);
   C[(e / N) * ldc + (e % N)] = s * scale;
 }
 
@@ -239,8 +254,7 @@ __global__ void sum_splits_sym_kernel(const double* __restrict__ P, int splits, 
   if (e >= M * M) return;
   const int64_t i = e / M, j = e % M;
   if (j > i) return;
-  double s = 0.0;
-  for (int z = 0; z < splits; ++z) s += P[(int64_t)z * M * M + e];
+  const double s = sum_splits_at(P, splits, M * M, e);
   C[i * ldc + j] = s * scale;
   C[j * ldc + i] = s * scale;
 }
