@@ -291,7 +291,7 @@ __global__ __launch_bounds__(256) void bat_prep_kernel(BTables T, int32_t* st0) 
   const int b = bat_locate(T, kMapPrep, blockIdx.x, lb);
   const BInst& d = T.inst[b];
   if (lb < d.m)
-    hx_block(d.Xs, d.n_pad, d.n_eff, d.Hx, d.momx, lb);
+    hx_block<256>(d.Xs, d.n_pad, d.n_eff, d.Hx, d.momx, lb);
   else
     pair_coef_elem(d.cov, d.m, d.m_pad, d.coef, st0 + b, (lb - d.m) * 256 + threadIdx.x);
 }

@@ -36,12 +36,14 @@ __device__ inline void standardize_tile(
 }
 
 // ------------------------------------------------------------------------------------------
-// Stage 2b: moments of the standardised columns -> Hx.  One block per variable; accurate
+// Stage 2b: moments of the standardised columns -> Hx.  One NT-thread block per variable; accurate
 // library exp/log (O(mn) work, not on the critical path).
 // ------------------------------------------------------------------------------------------
+template <int NT>
 __device__ inline void hx_block(const float* __restrict__ Xs, int64_t n_pad, int64_t n_eff,
                                 double* __restrict__ Hx, double* __restrict__ momx, int64_t i) {
-  __shared__ double ra[4], rb[4];
+  constexpr int kW = NT / 64;
+  __shared__ double ra[kW], rb[kW];
   const float* x = Xs + i * n_pad;
   double sa = 0.0, sb = 0.0;
   auto term = [&](float u) {
@@ -50,14 +52,14 @@ __device__ inline void hx_block(const float* __restrict__ Xs, int64_t n_pad, int
     sb += (double)(u * expf(-0.5f * u * u));
   };
   int64_t t = threadIdx.x;
-  for (; t + 7 * 256 < n_eff; t += 8 * 256) {  // eight loads in flight, summed in order
+  for (; t + 7 * NT < n_eff; t += 8 * NT) {  // eight loads in flight, summed in order
     float u[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) u[q] = x[t + q * 256];
+    for (int q = 0; q < 8; ++q) u[q] = x[t + q * NT];
 #pragma unroll
     for (int q = 0; q < 8; ++q) term(u[q]);
   }
-  for (; t < n_eff; t += 256) term(x[t]);
+  for (; t < n_eff; t += NT) term(x[t]);
   sa = wave_sum_d(sa);
   sb = wave_sum_d(sb);
   if ((threadIdx.x & 63) == 0) {
@@ -66,8 +68,14 @@ __device__ inline void hx_block(const float* __restrict__ Xs, int64_t n_pad, int
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    const double A = (((ra[0] + ra[1]) + ra[2]) + ra[3]) / (double)n_eff;
-    const double B = (((rb[0] + rb[1]) + rb[2]) + rb[3]) / (double)n_eff;
+    double A = 0.0, B = 0.0;
+#pragma unroll
+    for (int w = 0; w < kW; ++w) {
+      A += ra[w];
+      B += rb[w];
+    }
+    A /= (double)n_eff;
+    B /= (double)n_eff;
     Hx[i] = kHGauss - kK1 * (A - kGamma) * (A - kGamma) - kK2 * B * B;
     if (momx) {
       momx[2 * i] = A;
