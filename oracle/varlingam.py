@@ -38,7 +38,11 @@ equal first picks for any m, tiny-m agreement with the iterative algorithm, reco
 generating order, VAR orthogonality and the AR(1) closed form, the exact OLS identity
 (I - B0) Sigma (I - B0)^T diagonal, the generator identity (I - B0) M_tau = B_tau, and for the
 lag selection the univariate closed form, nested monotonicity, scale invariance and recovery
-of the generating lag order by BIC on long series.
+of the generating lag order by BIC on long series; the ordering margins by hand-computed values
+on a small integer score matrix (the runner-up is not the next pick there); the Sec. 3 step 5
+refinement by its exact identities (each refined column is centred, orthogonal to the pick and
+has variance 1 - rho^2) and by a sample-orthogonal construction whose refined column is the
+hidden noise exactly; estimate_B_cov by agreement with the per-variable least squares.
 Parity unpinned: the literal digits of k1 and gamma (pinned by citation of the published
 constants only).
 """
@@ -119,7 +123,26 @@ def standardize_columns(E: np.ndarray) -> np.ndarray:
     return np.column_stack([standardize(E[:, i]) for i in range(E.shape[1])])
 
 
-def pairwise_stats(E: np.ndarray, return_moments: bool = False):
+def pair_row(X: np.ndarray, i: int):
+    """Row i of the precompute from the standardised columns X: A[i, j], B[i, j] and
+    Hr[i, j] for every j != i (0 on the diagonal), one pair at a time (Eq. 1 residual,
+    re-standardised, Eq. 2 moments)."""
+    m = X.shape[1]
+    A = np.zeros(m)
+    B = np.zeros(m)
+    Hr = np.zeros(m)
+    for j in range(m):
+        if i == j:
+            continue
+        r = residual(X[:, i], X[:, j])
+        if not r.std() > 1e-6:       # 1 - rho_ij^2 below 1e-12
+            raise ValueError("degenerate pair: residual has (near) zero variance")
+        A[j], B[j] = entropy_moments(standardize(r))
+        Hr[j] = entropy_from_moments(A[j], B[j])
+    return A, B, Hr
+
+
+def pairwise_stats(E: np.ndarray, return_moments: bool = False, rows=None):
     """Precompute Hx[i] = H(x_i) and Hr[i, j] = H(std(r_{i<-j})) for every ordered pair, and
     the antisymmetric pairwise score S[i, j] = T_{j<-i} - T_{i<-j}
                                             = (Hx[j] + Hr[i, j]) - (Hx[i] + Hr[j, i]).
@@ -127,6 +150,10 @@ def pairwise_stats(E: np.ndarray, return_moments: bool = False):
 
     With `return_moments`, also returns the per-pair moment matrices A[i, j] =
     E[log cosh u_{i<-j}], B[i, j] = E[u_{i<-j} exp(-u_{i<-j}^2/2)] and Ax, Bx (size m).
+
+    `rows` may hold pair_row(standardize_columns(E), i) for i = 0 .. m-1, computed elsewhere
+    (for instance by worker processes, the rows being independent); the result is then
+    bit-identical to computing them here.
     """
     X = standardize_columns(E)
     m = X.shape[1]
@@ -135,18 +162,13 @@ def pairwise_stats(E: np.ndarray, return_moments: bool = False):
     for i in range(m):
         Ax[i], Bx[i] = entropy_moments(X[:, i])
     Hx = np.array([entropy_from_moments(Ax[i], Bx[i]) for i in range(m)])
-    A = np.zeros((m, m))
-    B = np.zeros((m, m))
-    Hr = np.zeros((m, m))
-    for i in range(m):
-        for j in range(m):
-            if i == j:
-                continue
-            r = residual(X[:, i], X[:, j])
-            if not r.std() > 1e-6:       # 1 - rho_ij^2 below 1e-12
-                raise ValueError("degenerate pair: residual has (near) zero variance")
-            A[i, j], B[i, j] = entropy_moments(standardize(r))
-            Hr[i, j] = entropy_from_moments(A[i, j], B[i, j])
+    if rows is None:
+        rows = [pair_row(X, i) for i in range(m)]
+    if len(rows) != m:
+        raise ValueError("rows must hold one pair_row result per variable")
+    A = np.array([r[0] for r in rows]).reshape(m, m)
+    B = np.array([r[1] for r in rows]).reshape(m, m)
+    Hr = np.array([r[2] for r in rows]).reshape(m, m)
     S = np.zeros((m, m))
     for i in range(m):
         for j in range(m):
@@ -243,9 +265,18 @@ def directlingam_iterative(E: np.ndarray, k_exact: int | None = None):
         c = U[best]
         order.append(c)
         del U[best]
-        for j in U:                                   # Sec. 3 step 5: data refinement
-            X[:, j] = residual(Xs[j], Xs[c])
+        refine(X, U, c)
     return np.array(order, dtype=np.int64)
+
+
+def refine(X: np.ndarray, U, c: int) -> None:
+    """Sec. 3 step 5: after variable c is taken, every remaining column j in U is replaced (in
+    place) by the least-squares residual of its standardised data on the standardised x_c,
+    x_j <- std(x_j) - rho_jc std(x_c)  (Eq. 1 between standardised columns)."""
+    xc = standardize(X[:, c])
+    for j in U:
+        if j != c:
+            X[:, j] = residual(standardize(X[:, j]), xc)
 
 
 # ---------------------------------------------------------------------------------------------
@@ -330,14 +361,44 @@ def estimate_B(E: np.ndarray, order, M: np.ndarray):
     return B0, Bl
 
 
+def estimate_B_cov(Sigma: np.ndarray, order, M: np.ndarray):
+    """The same estimator as estimate_B written as normal equations on the population
+    covariance Sigma of the residuals (for an OLS with intercept the centred normal equations
+    are exactly Sigma_PP b = Sigma_Pv, P = the predecessors of v): B0[v, P] = Sigma_PP^-1
+    Sigma_Pv for every v after the first; B_tau = (I - B0) M_tau.  One m x m matrix instead of
+    the data, so the larger workloads stay quick."""
+    Sigma = np.asarray(Sigma, dtype=np.float64)
+    m = Sigma.shape[0]
+    B0 = np.zeros((m, m))
+    order = [int(v) for v in order]
+    for k in range(1, m):
+        v = order[k]
+        P = order[:k]
+        B0[v, P] = np.linalg.solve(Sigma[np.ix_(P, P)], Sigma[P, v])
+    Bl = np.stack([(np.eye(m) - B0) @ M[t] for t in range(M.shape[0])])
+    return B0, Bl
+
+
+def population_cov(E: np.ndarray) -> np.ndarray:
+    """Covariance of the columns of E with the 1/n divisor."""
+    E = np.asarray(E, dtype=np.float64)
+    C = E - E.mean(axis=0)
+    return C.T @ C / E.shape[0]
+
+
 # ---------------------------------------------------------------------------------------------
 # The whole heuristic fit
 # ---------------------------------------------------------------------------------------------
-def fit(X: np.ndarray, p: int) -> dict:
-    """VAR fit -> precompute (Hx, Hr, S) -> Alg. 1 ordering -> B0, B_tau."""
+def fit(X: np.ndarray, p: int, b_from_cov: bool = False, rows=None) -> dict:
+    """VAR fit -> precompute (Hx, Hr, S) -> Alg. 1 ordering -> B0, B_tau.  `b_from_cov` takes
+    B from estimate_B_cov (normal equations on the residual covariance) instead of one
+    least-squares fit of the data per variable; `rows` goes to pairwise_stats."""
     M, c, E = fit_var(X, p)
-    Hx, Hr, S = pairwise_stats(E)
+    Hx, Hr, S = pairwise_stats(E, rows=rows)
     order, margin = approx_order(S)
-    B0, Bl = estimate_B(E, order, M)
+    if b_from_cov:
+        B0, Bl = estimate_B_cov(population_cov(E), order, M)
+    else:
+        B0, Bl = estimate_B(E, order, M)
     return {"M": M, "intercept": c, "E": E, "Hx": Hx, "Hr": Hr, "S": S,
             "order": order, "margin": margin, "B0": B0, "B_lags": Bl}

@@ -71,8 +71,7 @@ def _iterative_walk(order, X, U, steps, tie, bad):
         if gap > tie:
             bad.append((k, c, gap))
         U.remove(c)
-        for j in U:
-            X[:, j] = O.residual(Xs[j], Xs[c])
+        O.refine(X, U, c)
     return True
 
 

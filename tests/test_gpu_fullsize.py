@@ -1,0 +1,56 @@
+"""End-to-end parity of the whole fit at the m = 400, n = 10 000, p = 2 Student-t workload (the
+benchmark's series), seeds 0-2, against the FP64 oracle's own fit of the same float32 series.
+
+* order: walked with parity.order_violations on the oracle's score matrix (the GPU's pick must
+  be within 1e-9 of the oracle's minimum over the GPU's current candidate set);
+* B0 / B_tau: against the oracle's B for the same order (the oracle's order when the two
+  agree, else the oracle's estimator run on the GPU's order), 1e-5 relative in the mixed mode,
+  1e-3 with the BF16 Gram; plain FP32 is held to parity.B_TOL_PLAIN and its error printed;
+* S: max |S - S_ref| within the pairwise bound TOL_S of the small-size tests (6e-6).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import varlingam as O
+import parity as PA
+
+pytestmark = pytest.mark.gpu
+
+TOL_S = 6e-6
+B_TOL = {"mixed": PA.B_TOL_FP32, "bf16": PA.B_TOL_BF16, "fp32": PA.B_TOL_PLAIN}
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2409_05500_amd import api as _api
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return _api
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_fit_benchmark_workload_end_to_end(api, fullsize_oracle, seed):
+    print(f"full-size fit m400_n10000_p2_t4 seed {seed}: waiting for the oracle", flush=True)
+    ref = fullsize_oracle("m400_n10000_p2_t4", seed)
+    X = torch.from_numpy(ref["X32"]).to("cuda:0")
+    for prec in ("mixed", "bf16", "fp32"):
+        print(f"  {prec}", flush=True)
+        g = api.fit(X, 2, prec)
+        order = g.order.cpu().numpy()
+        S = g.S.cpu().numpy()
+        assert sorted(order.tolist()) == list(range(400))
+        bad = PA.order_violations(order, ref["S"])
+        assert bad == [], (prec, bad[:5])
+        ds = float(np.max(np.abs(S - ref["S"])))
+        assert ds < TOL_S, (prec, ds)
+        if np.array_equal(order, ref["order"]):
+            B0_ref, Bl_ref = ref["B0"], ref["B_lags"]
+        else:
+            B0_ref, Bl_ref = O.estimate_B_cov(ref["Cov"], order, ref["M"])
+        e0 = PA.b_rel_error(g.B0.cpu().numpy(), B0_ref)
+        e1 = PA.b_rel_error(g.B_lags.cpu().numpy(), Bl_ref)
+        same = int(np.array_equal(order, ref["order"]))
+        print(f"  {prec}: same order {same}, max|dS| {ds:.2e}, B0 {e0:.2e}, B_lags {e1:.2e}",
+              flush=True)
+        assert max(e0, e1) <= B_TOL[prec], (prec, e0, e1)

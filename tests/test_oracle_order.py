@@ -186,3 +186,38 @@ def test_hybrid_walker_accepts_the_oracle_and_rejects_a_swap():
         early = hyb.copy()
         early[0], early[-1] = early[-1], early[0]
         assert PA.hybrid_order_violations(early, E, k)[0][0] == 0
+
+
+def test_margins_by_hand():
+    """Margins of Alg. 1 on a small integer score matrix, worked out by hand:
+    S01 = 1, S02 = -2, S03 = 3, S12 = 1, S13 = -1, S23 = 2 (S = -S^T).
+      U = {0,1,2,3}: M = (4, 1 + 1, 1, 9 + 4) = (4, 2, 1, 13)  -> pick 2, margin 2 - 1 = 1
+      U = {0,1,3}:   M = (0, 1 + 1, 9)                         -> pick 0, margin 2 - 0 = 2
+      U = {1,3}:     M = (1, 0)                                -> pick 3, margin 1 - 0 = 1
+      U = {1}:                                                  -> pick 1, margin +inf
+    At the first step the runner-up (variable 1) is not the next pick (variable 0), so a
+    margin taken against the next pick, the largest M or a removed variable fails here, as
+    does the sign of the difference."""
+    S = np.zeros((4, 4))
+    for (i, j), v in {(0, 1): 1.0, (0, 2): -2.0, (0, 3): 3.0, (1, 2): 1.0, (1, 3): -1.0,
+                      (2, 3): 2.0}.items():
+        S[i, j], S[j, i] = v, -v
+    order, margin = O.approx_order(S)
+    assert list(order) == [2, 0, 3, 1]
+    assert list(margin) == [1.0, 2.0, 1.0, np.inf]
+    # a relabelling moves the same margins with the variables
+    P = np.array([3, 1, 0, 2])
+    oP, mP = O.approx_order(S[np.ix_(P, P)])
+    assert list(P[oP]) == [2, 0, 3, 1] and list(mP) == [1.0, 2.0, 1.0, np.inf]
+
+
+def test_margin_is_exact_second_minus_first_with_fractional_scores():
+    """Scores that are exact binary fractions, so every M is exact: U = {0,1,2},
+    S01 = -0.5, S02 = 0.25, S12 = -0.75: M = (0.25, 0.5625, 0.0625) -> pick 2, margin
+    0.25 - 0.0625 = 0.1875; then U = {0,1}: M = (0.25, 0) -> pick 1, margin 0.25."""
+    S = np.zeros((3, 3))
+    for (i, j), v in {(0, 1): -0.5, (0, 2): 0.25, (1, 2): -0.75}.items():
+        S[i, j], S[j, i] = v, -v
+    order, margin = O.approx_order(S)
+    assert list(order) == [2, 1, 0]
+    assert list(margin) == [0.1875, 0.25, np.inf]

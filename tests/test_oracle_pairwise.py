@@ -140,3 +140,18 @@ def test_synth_instance_is_float32_roundtrip():
     inst = synth.make_instance(synth.SMALL, 0)
     assert inst.X32.dtype == np.float32 and inst.X32.shape == (1000, 10)
     assert np.array_equal(inst.X_parity, inst.X32.astype(np.float64))
+
+
+def test_rows_computed_elsewhere_give_the_same_bits():
+    """pairwise_stats with rows handed in (as worker processes compute them) equals the
+    serial precompute bit for bit, and a short row list is refused."""
+    rng = np.random.default_rng(9)
+    E = rng.laplace(size=(700, 6)) @ (np.eye(6) + 0.3 * rng.normal(size=(6, 6)))
+    ref = O.pairwise_stats(E)
+    X = O.standardize_columns(E)
+    rows = [O.pair_row(X, i) for i in reversed(range(6))][::-1]
+    out = O.pairwise_stats(E, rows=rows)
+    for a, b in zip(ref, out):
+        assert np.array_equal(a, b)
+    with pytest.raises(ValueError):
+        O.pairwise_stats(E, rows=rows[:5])

@@ -110,3 +110,23 @@ def test_b0_recovers_truth_given_true_order_long_series():
     B0, Bl = O.estimate_B(E, inst.perm, M)
     np.testing.assert_allclose(B0, inst.B0, atol=0.03)
     np.testing.assert_allclose(Bl[0], inst.B_lags[0], atol=0.03)
+
+
+def test_covariance_route_of_b_equals_least_squares():
+    """estimate_B_cov (normal equations on the population covariance) against estimate_B (one
+    least-squares fit with intercept per variable) on two workloads and a random order."""
+    for inst, p in ((synth.make_instance(synth.SMALL, 1), 1),
+                    (synth.make_custom(30, 2000, 2, "laplace", 4, edge_prob=0.1), 2)):
+        M, _, E = O.fit_var(inst.X_parity, p)
+        m = E.shape[1]
+        for order in (np.arange(m), np.random.default_rng(m).permutation(m)):
+            B0, Bl = O.estimate_B(E, order, M)
+            C0, Cl = O.estimate_B_cov(O.population_cov(E), order, M)
+            np.testing.assert_allclose(C0, B0, rtol=0, atol=1e-10)
+            np.testing.assert_allclose(Cl, Bl, rtol=0, atol=1e-10)
+
+
+def test_population_cov_divisor():
+    rng = np.random.default_rng(0)
+    E = rng.normal(size=(500, 4))
+    np.testing.assert_allclose(O.population_cov(E), np.cov(E.T, bias=True), atol=1e-14)
