@@ -14,8 +14,8 @@
 namespace vl {
 
 // M0[i] = sum_{j != i} min(0, S[i][j])^2, one wave per row, fixed summation order.
-// A non-finite S entry raises VL_ERR_NONFINITE; its row's M becomes +inf so that every
-// selection step still picks a valid index.
+// A non-finite S entry raises VL_ERR_NONFINITE and its row's M becomes +inf; the selection
+// keeps an explicit live mask, so every step still picks a variable not yet ordered.
 __global__ __launch_bounds__(256) void order_init_kernel(const double* __restrict__ S, int64_t m,
                                                          double* __restrict__ M0, int32_t* st) {
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);

@@ -106,14 +106,19 @@ __device__ inline void order_wave_block(const double* __restrict__ S, int64_t m,
   if (bad) raise_status(st, VL_ERR_NONFINITE);
   __syncthreads();
   if (wave == 0) {
-  // Removed and padding entries hold +inf: no per-entry flags in the loop.  Each step: m1 =
-  // wave min; i1 = lowest index holding m1; the loads of row i1 are issued at once and the
-  // second minimum (the margin) is reduced while they are in flight.
+  // Removed and padding entries hold +inf, so they never win a minimum over a finite M.  A
+  // live candidate can hold +inf too (its row of S had a non-finite entry, which raised
+  // VL_ERR_NONFINITE), so the index search runs over the live entries only: every step picks
+  // a variable not yet ordered.  Each step: m1 = wave min; i1 = lowest live index holding m1;
+  // the loads of row i1 are issued at once and the second minimum (the margin) is reduced
+  // while they are in flight.
   const double inf = INFINITY;
   double Mv[R];
+  bool live[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int i = lane + 64 * r;
+    live[r] = i < m;
     Mv[r] = i < m ? M0s[i] : inf;
   }
   const int64_t last = m - 1;
@@ -125,7 +130,7 @@ __device__ inline void order_wave_block(const double* __restrict__ S, int64_t m,
     int li = 0x7fffffff;
 #pragma unroll
     for (int r = R - 1; r >= 0; --r)
-      if (Mv[r] == m1) li = lane + 64 * r;
+      if (live[r] && Mv[r] == m1) li = lane + 64 * r;
     const int i1 = wave_min_i32(li);
     // row i1 of S (indices clamped into the matrix; padding entries stay +inf)
     const double* rowp = S + (int64_t)(i1 < m ? i1 : last) * m;
@@ -138,7 +143,10 @@ __device__ inline void order_wave_block(const double* __restrict__ S, int64_t m,
     // remove the winner, then the margin from the remaining minimum
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if (lane + 64 * r == i1) Mv[r] = inf;
+      if (lane + 64 * r == i1) {
+        Mv[r] = inf;
+        live[r] = false;
+      }
     double l2 = Mv[0];
 #pragma unroll
     for (int r = 1; r < R; ++r) l2 = fmin(l2, Mv[r]);

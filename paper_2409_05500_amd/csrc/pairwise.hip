@@ -10,7 +10,9 @@
 //      u_{i<-j} = (x_i - rho x_j) / sqrt(1 - rho^2); the kernel receives the two scaled
 //      coefficients a = c / sqrt(1-rho^2), b = c rho / sqrt(1-rho^2) and forms w = c u;
 //   4. the hot kernel: for every pair and sample, both directions w_{i<-j}, w_{j<-i} and their
-//      entropy moments (Eq. 2): sum log cosh u and sum u exp(-u^2/2);
+//      entropy moments (Eq. 2): sum log cosh u and sum u exp(-u^2/2); micro-tiles holding a
+//      near-collinear pair (sqrt(1 - rho^2) < 0.25) are left to a second kernel that forms
+//      their residuals in FP64 from E;
 //   5. FP64 combine: Hr = H(nu) - k1 (A - gamma)^2 - k2 B^2 and
 //      S[i,j] = (Hx[j] + Hr[i,j]) - (Hx[i] + Hr[j,i]).
 #include <algorithm>
@@ -46,8 +48,10 @@ __global__ __launch_bounds__(kHxThreads) void hx_kernel(const float* __restrict_
 }
 
 __global__ void pair_coef_kernel(const double* __restrict__ cov, int64_t m, int64_t m_pad,
-                                 float2* __restrict__ coef, int32_t* st) {
-  pair_coef_elem(cov, m, m_pad, coef, st, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+                                 float2* __restrict__ coef, int nt, int64_t tiles,
+                                 int32_t* __restrict__ tflag, int32_t* st) {
+  pair_coef_elem(cov, m, m_pad, coef, nt, tiles, tflag, st,
+                 (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // Blocks are remapped so that XCD x (block id mod 8) processes a contiguous range of items in
@@ -55,14 +59,28 @@ __global__ void pair_coef_kernel(const double* __restrict__ cov, int64_t m, int6
 __global__ __launch_bounds__(256) void pairwise_moments_kernel(
     const float* __restrict__ Xs, int64_t n_pad, const float2* __restrict__ coef, int64_t m_pad,
     int64_t m, int nt, int64_t tiles, int chunk_len, int64_t items,
-    float* __restrict__ partU, float* __restrict__ partB) {
+    const int32_t* __restrict__ tflag, float* __restrict__ partU, float* __restrict__ partB) {
   const int64_t nb = gridDim.x;                     // a multiple of 8
   const int64_t b = blockIdx.x;
   const int64_t lb = (b & 7) * (nb >> 3) + (b >> 3);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t item = lb * 4 + wave;
   if (item >= items) return;
-  pairwise_moments_item(Xs, n_pad, coef, m_pad, m, nt, tiles, chunk_len, item, partU, partB);
+  pairwise_moments_item(Xs, n_pad, coef, m_pad, m, nt, tiles, chunk_len, item, tflag, partU,
+                        partB);
+}
+
+// The items of micro-tiles with a near-collinear pair (every other wave returns at once).
+__global__ __launch_bounds__(256) void pairwise_collinear_kernel(
+    const float* __restrict__ E, int64_t lde, int64_t n_eff, const double* __restrict__ mu,
+    const double* __restrict__ cov, int64_t m, int nt, int64_t tiles, int chunk_len,
+    int64_t items, const int32_t* __restrict__ tflag, float* __restrict__ partU,
+    float* __restrict__ partB) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t item = (int64_t)blockIdx.x * 4 + wave;
+  if (item >= items) return;
+  pairwise_collinear_item(E, lde, n_eff, mu, cov, m, nt, tiles, chunk_len, item, tflag, partU,
+                          partB);
 }
 
 __global__ void combine_hr_kernel(const float* __restrict__ partU, const float* __restrict__ partB,
@@ -101,19 +119,25 @@ PairwisePlan plan_pairwise(int64_t n_eff, int64_t m) {
   return p;
 }
 
+// The split partials of the column means and the covariance are dead once the covariance is
+// formed, before anything of stages 2-5 is written: the two share one region.
 size_t pairwise_ws_bytes(const PairwisePlan& p, void* base, PairwiseWs* out) {
   Carver c(base);
   PairwiseWs w;
   w.mu = c.take<double>(p.m);
   w.cov = c.take<double>(p.m * p.m);
-  w.scratch = c.take<double>(scratch_doubles(p));
-  w.Xs = c.take<float>(p.m_pad * p.n_pad);
-  w.coef = c.take<float2>(p.m_pad * p.m_pad);
-  w.partU = c.take<float>((size_t)p.nc * p.m * p.m);
-  w.partB = c.take<float>((size_t)p.nc * p.m * p.m);
   w.momx = c.take<double>(2 * p.m);
+  char* region = base ? static_cast<char*>(base) + c.used : nullptr;
+  Carver a(region);                              // stage 1
+  w.scratch = a.take<double>(scratch_doubles(p));
+  Carver b(region);                              // stages 2-5
+  w.Xs = b.take<float>(p.m_pad * p.n_pad);
+  w.coef = b.take<float2>(p.m_pad * p.m_pad);
+  w.partU = b.take<float>((size_t)p.nc * p.m * p.m);
+  w.partB = b.take<float>((size_t)p.nc * p.m * p.m);
+  w.tflag = b.take<int32_t>(p.tiles);
   if (out) *out = w;
-  return c.used;
+  return c.used + std::max(a.used, b.used);
 }
 
 size_t scratch_doubles(const PairwisePlan& p) {
@@ -154,13 +178,20 @@ int run_pairwise(const PairwisePlan& p, const PairwiseWs& w, const float* E, int
     hx_kernel<<<(unsigned)m, kHxThreads, 0, stream>>>(w.Xs, p.n_pad, n_eff, Hx, w.momx);
     VL_LAUNCH_CHECK();
     pair_coef_kernel<<<(unsigned)ceil_div(p.m_pad * p.m_pad, 256), 256, 0, stream>>>(
-        cov, m, p.m_pad, w.coef, st);
+        cov, m, p.m_pad, w.coef, p.nt, p.tiles, w.tflag, st);
     VL_LAUNCH_CHECK();
   }
   {
     ProfileScope ps("pairwise_moments", stream);
     pairwise_moments_kernel<<<(unsigned)p.blocks, 256, 0, stream>>>(
-        w.Xs, p.n_pad, w.coef, p.m_pad, m, p.nt, p.tiles, p.chunk_len, p.items, w.partU,
+        w.Xs, p.n_pad, w.coef, p.m_pad, m, p.nt, p.tiles, p.chunk_len, p.items, w.tflag,
+        w.partU, w.partB);
+    VL_LAUNCH_CHECK();
+  }
+  {
+    ProfileScope ps("pairwise_collinear", stream);
+    pairwise_collinear_kernel<<<(unsigned)ceil_div(p.items, 4), 256, 0, stream>>>(
+        E, lde, n_eff, w.mu, cov, m, p.nt, p.tiles, p.chunk_len, p.items, w.tflag, w.partU,
         w.partB);
     VL_LAUNCH_CHECK();
   }

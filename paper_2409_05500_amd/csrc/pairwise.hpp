@@ -25,6 +25,7 @@ struct PairwiseWs {
   float* partU = nullptr;     // nc x m x m
   float* partB = nullptr;     // nc x m x m
   double* momx = nullptr;     // 2 m: E[log cosh x_i], E[x_i exp(-x_i^2/2)]
+  int32_t* tflag = nullptr;   // tiles: 1 where the micro-tile holds a near-collinear pair
 };
 
 PairwisePlan plan_pairwise(int64_t n_eff, int64_t m);

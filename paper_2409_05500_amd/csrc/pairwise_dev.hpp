@@ -85,10 +85,53 @@ __device__ inline void hx_block(const float* __restrict__ Xs, int64_t n_pad, int
 }
 
 // ------------------------------------------------------------------------------------------
+// Micro-tiles: kT x kT variable blocks {I, J} with bi <= bj, numbered row by row.
+// ------------------------------------------------------------------------------------------
+constexpr int kT = 4;
+
+__device__ inline void tile_coords(int64_t k, int nt, int& bi, int& bj) {
+  // upper-triangular tiles in row-major order: row r starts at r*nt - r*(r-1)/2
+  const double T = (double)nt;
+  const double disc = (2.0 * T + 1.0) * (2.0 * T + 1.0) - 8.0 * (double)k;
+  int r = (int)(((2.0 * T + 1.0) - sqrt(disc > 0.0 ? disc : 0.0)) * 0.5);
+  if (r < 0) r = 0;
+  if (r > nt - 1) r = nt - 1;
+  auto start = [nt](int q) { return (int64_t)q * nt - (int64_t)q * (q - 1) / 2; };
+  while (r > 0 && start(r) > k) --r;
+  while (r < nt - 1 && start(r + 1) <= k) ++r;
+  bi = r;
+  bj = r + (int)(k - start(r));
+}
+
+// A pair with sqrt(1 - rho^2) below kCollinearS is near-collinear: its Eq. 1 residual
+// x_i - rho x_j cancels to a small fraction of the data, and forming it from the FP32 rounded
+// standardised columns would amplify their rounding by 1 / sqrt(1 - rho^2).  Micro-tiles that
+// hold such a pair are skipped by the FP32 moment kernel and run by the collinear kernel,
+// which standardises and forms the residual in FP64 from E itself.
+constexpr double kCollinearS = 0.25;
+
+__device__ inline int32_t tile_collinear_flag(const double* __restrict__ cov, int64_t m, int nt,
+                                              int64_t tile) {
+  int bi, bj;
+  tile_coords(tile, nt, bi, bj);
+  for (int ii = 0; ii < kT; ++ii)
+    for (int jj = 0; jj < kT; ++jj) {
+      const int64_t i = (int64_t)bi * kT + ii, j = (int64_t)bj * kT + jj;
+      if (i >= m || j >= m || i == j) continue;
+      const double rho = cov[i * m + j] / sqrt(cov[i * m + i] * cov[j * m + j]);
+      if (!(1.0 - rho * rho >= kCollinearS * kCollinearS)) return 1;
+    }
+  return 0;
+}
+
+// ------------------------------------------------------------------------------------------
 // Stage 3: scaled pair coefficients (a, b) for i, j < m_pad; zero on the diagonal / padding.
+// Thread e < tiles also writes the collinear flag of micro-tile e.
 // ------------------------------------------------------------------------------------------
 __device__ inline void pair_coef_elem(const double* __restrict__ cov, int64_t m, int64_t m_pad,
-                                      float2* __restrict__ coef, int32_t* st, int64_t e) {
+                                      float2* __restrict__ coef, int nt, int64_t tiles,
+                                      int32_t* __restrict__ tflag, int32_t* st, int64_t e) {
+  if (e < tiles) tflag[e] = tile_collinear_flag(cov, m, nt, e);
   if (e >= m_pad * m_pad) return;
   const int64_t i = e / m_pad, j = e % m_pad;
   float2 c = make_float2(0.f, 0.f);
@@ -127,22 +170,7 @@ __device__ inline void pair_coef_elem(const double* __restrict__ cov, int64_t m,
 // At the end the 2 x 2 x kT x kT wave sums are formed by a reduce-scatter (lane l ends with
 // value l) and written to per-chunk FP32 partials part{U,B}[chunk][row][col].
 // ------------------------------------------------------------------------------------------
-constexpr int kT = 4;
 static_assert(2 * 2 * kT * kT == 64, "reduce-scatter expects 64 values per lane");
-
-__device__ inline void tile_coords(int64_t k, int nt, int& bi, int& bj) {
-  // upper-triangular tiles in row-major order: row r starts at r*nt - r*(r-1)/2
-  const double T = (double)nt;
-  const double disc = (2.0 * T + 1.0) * (2.0 * T + 1.0) - 8.0 * (double)k;
-  int r = (int)(((2.0 * T + 1.0) - sqrt(disc > 0.0 ? disc : 0.0)) * 0.5);
-  if (r < 0) r = 0;
-  if (r > nt - 1) r = nt - 1;
-  auto start = [nt](int q) { return (int64_t)q * nt - (int64_t)q * (q - 1) / 2; };
-  while (r > 0 && start(r) > k) --r;
-  while (r < nt - 1 && start(r + 1) <= k) ++r;
-  bi = r;
-  bj = r + (int)(k - start(r));
-}
 
 __device__ __forceinline__ void moment_step(float w, float& U, float& P, float& B) {
   const float q = w * w;
@@ -154,15 +182,47 @@ __device__ __forceinline__ void moment_step(float w, float& U, float& P, float& 
   U += aw;
 }
 
+// Writes the 2 x 2 x kT x kT wave sums of one item: a reduce-scatter (lane l ends with value
+// l), then the chunk partials part{U,B}[chunk][row][col] of the valid ordered pairs.
+__device__ __forceinline__ void write_moment_partials(
+    float (&U)[2][kT][kT], float (&B)[2][kT][kT], int64_t i0, int64_t j0, int64_t m,
+    int64_t chunk, float* __restrict__ partU, float* __restrict__ partB) {
+  const int lane = threadIdx.x & 63;
+  // value index v = kind*32 + d*16 + ii*4 + jj (kind 0: U, 1: B)
+  float v[64];
+#pragma unroll
+  for (int d = 0; d < 2; ++d)
+#pragma unroll
+    for (int ii = 0; ii < kT; ++ii)
+#pragma unroll
+      for (int jj = 0; jj < kT; ++jj) {
+        v[d * 16 + ii * 4 + jj] = U[d][ii][jj];
+        v[32 + d * 16 + ii * 4 + jj] = B[d][ii][jj];
+      }
+  const float sum = wave_reduce_scatter64(v);
+  const int kind = lane >> 5, d = (lane >> 4) & 1, ii = (lane >> 2) & 3, jj = lane & 3;
+  const int64_t i = i0 + ii, j = j0 + jj;
+  if (i < m && j < m && i != j) {
+    const int64_t row = d ? j : i, col = d ? i : j;
+    float* dst = kind ? partB : partU;
+    dst[chunk * m * m + row * m + col] = sum;
+  }
+}
+
 // One wave's work item (tile, chunk); item < items is the caller's check.  Always inlined:
 // as a call its register use rises from 168 to 248 and the occupancy falls to 2 waves/SIMD.
+// tflag[tile] != 0 marks a micro-tile with a near-collinear pair: left to the collinear item.
 __device__ __attribute__((always_inline)) inline void pairwise_moments_item(
     const float* __restrict__ Xs, int64_t n_pad, const float2* __restrict__ coef, int64_t m_pad,
     int64_t m, int nt, int64_t tiles, int chunk_len, int64_t item,
-    float* __restrict__ partU, float* __restrict__ partB) {
+    const int32_t* __restrict__ tflag, float* __restrict__ partU, float* __restrict__ partB) {
   const int lane = threadIdx.x & 63;
   const int64_t chunk = item / tiles;
   const int64_t tile = item - chunk * tiles;
+  {
+    typedef const __attribute__((address_space(4))) int32_t* const_i32p;
+    if (((const_i32p)(uintptr_t)tflag)[tile]) return;
+  }
   int bi, bj;
   tile_coords(tile, nt, bi, bj);
   const int64_t i0 = (int64_t)bi * kT, j0 = (int64_t)bj * kT;
@@ -246,25 +306,104 @@ __device__ __attribute__((always_inline)) inline void pairwise_moments_item(
     }
   }
 
-  // value index v = kind*32 + d*16 + ii*4 + jj (kind 0: U, 1: B)
-  float v[64];
+  write_moment_partials(U, B, i0, j0, m, chunk, partU, partB);
+}
+
+// The same item for a micro-tile with a near-collinear pair (tflag[tile] != 0; others return
+// at once).  Lanes run over samples, one per step.  Each sample of the tile's 2 kT variables
+// is standardised in FP64 from E (x = (e - mu) / sd, population moments), the residuals of
+// both directions are formed in FP64, d = x_i - rho x_j, and only the scaled residual
+// w = d c / sqrt(1 - rho^2) is rounded to FP32: its relative error is then that of one
+// rounding, as for a well-conditioned pair.  The moment terms are the fast item's.
+__device__ inline void pairwise_collinear_item(
+    const float* __restrict__ E, int64_t lde, int64_t n_eff, const double* __restrict__ mu,
+    const double* __restrict__ cov, int64_t m, int nt, int64_t tiles, int chunk_len,
+    int64_t item, const int32_t* __restrict__ tflag, float* __restrict__ partU,
+    float* __restrict__ partB) {
+  const int lane = threadIdx.x & 63;
+  const int64_t chunk = item / tiles;
+  const int64_t tile = item - chunk * tiles;
+  if (!tflag[tile]) return;
+  int bi, bj;
+  tile_coords(tile, nt, bi, bj);
+  const int64_t i0 = (int64_t)bi * kT, j0 = (int64_t)bj * kT;
+  double mi[kT], si[kT], mj[kT], sj[kT];
+  int64_t ci[kT], cj[kT];
+#pragma unroll
+  for (int k = 0; k < kT; ++k) {
+    const bool oi = i0 + k < m, oj = j0 + k < m;
+    ci[k] = oi ? i0 + k : m - 1;
+    cj[k] = oj ? j0 + k : m - 1;
+    mi[k] = mu[ci[k]];
+    mj[k] = mu[cj[k]];
+    si[k] = oi ? 1.0 / sqrt(cov[ci[k] * m + ci[k]]) : 0.0;   // padding variables: x = 0
+    sj[k] = oj ? 1.0 / sqrt(cov[cj[k] * m + cj[k]]) : 0.0;
+  }
+  double rho[kT][kT], kc[kT][kT];
+#pragma unroll
+  for (int ii = 0; ii < kT; ++ii)
+#pragma unroll
+    for (int jj = 0; jj < kT; ++jj) {
+      const int64_t i = i0 + ii, j = j0 + jj;
+      rho[ii][jj] = 0.0;
+      kc[ii][jj] = 0.0;
+      if (i < m && j < m && i != j) {
+        const double r = cov[i * m + j] / sqrt(cov[i * m + i] * cov[j * m + j]);
+        const double omr = 1.0 - r * r;
+        rho[ii][jj] = r;
+        kc[ii][jj] = omr >= kMinOneMinusRho2 ? kWScale / sqrt(omr) : 0.0;  // else: raised
+      }
+    }
+
+  float U[2][kT][kT], P[2][kT][kT], B[2][kT][kT];
 #pragma unroll
   for (int d = 0; d < 2; ++d)
 #pragma unroll
     for (int ii = 0; ii < kT; ++ii)
 #pragma unroll
       for (int jj = 0; jj < kT; ++jj) {
-        v[d * 16 + ii * 4 + jj] = U[d][ii][jj];
-        v[32 + d * 16 + ii * 4 + jj] = B[d][ii][jj];
+        U[d][ii][jj] = 0.f;
+        P[d][ii][jj] = 1.f;
+        B[d][ii][jj] = 0.f;
       }
-  const float sum = wave_reduce_scatter64(v);
-  const int kind = lane >> 5, d = (lane >> 4) & 1, ii = (lane >> 2) & 3, jj = lane & 3;
-  const int64_t i = i0 + ii, j = j0 + jj;
-  if (i < m && j < m && i != j) {
-    const int64_t row = d ? j : i, col = d ? i : j;
-    float* dst = kind ? partB : partU;
-    dst[chunk * m * m + row * m + col] = sum;
+  const float cln2 = (float)(kWScale * kLn2);
+  const int steps = chunk_len / 64;
+  int since_flush = 0;
+  for (int s = 0; s < steps; ++s) {
+    const int64_t t = chunk * chunk_len + (int64_t)s * 64 + lane;
+    const bool ot = t < n_eff;
+    const int64_t tc = ot ? t : n_eff - 1;           // clamped row; padding samples give 0
+    double xi[kT], xj[kT];
+#pragma unroll
+    for (int k = 0; k < kT; ++k) {
+      xi[k] = mask_f64(((double)E[tc * lde + ci[k]] - mi[k]) * si[k], ot);
+      xj[k] = mask_f64(((double)E[tc * lde + cj[k]] - mj[k]) * sj[k], ot);
+    }
+#pragma unroll
+    for (int ii = 0; ii < kT; ++ii)
+#pragma unroll
+      for (int jj = 0; jj < kT; ++jj) {
+        const float w0 = (float)(fma(-rho[ii][jj], xj[jj], xi[ii]) * kc[ii][jj]);
+        const float w1 = (float)(fma(-rho[ii][jj], xi[ii], xj[jj]) * kc[ii][jj]);
+        moment_step(w0, U[0][ii][jj], P[0][ii][jj], B[0][ii][jj]);
+        moment_step(w1, U[1][ii][jj], P[1][ii][jj], B[1][ii][jj]);
+      }
+    since_flush += 1;
+    if (since_flush == 64 || s == steps - 1) {
+      const float cnt = (float)since_flush;
+#pragma unroll
+      for (int d = 0; d < 2; ++d)
+#pragma unroll
+        for (int ii = 0; ii < kT; ++ii)
+#pragma unroll
+          for (int jj = 0; jj < kT; ++jj) {
+            U[d][ii][jj] = fmaf(__builtin_amdgcn_logf(P[d][ii][jj]) - cnt, cln2, U[d][ii][jj]);
+            P[d][ii][jj] = 1.f;
+          }
+      since_flush = 0;
+    }
   }
+  write_moment_partials(U, B, i0, j0, m, chunk, partU, partB);
 }
 
 // ------------------------------------------------------------------------------------------

@@ -184,3 +184,22 @@ def make_batch(seed: int = 0, count: int = BATCH_COUNT) -> list[Instance]:
         X, lags, rescaled = _simulate(rng, w, m, n, B0, lags)
         out.append(Instance(w, seed, X, B0, lags, perm, rescaled, {"index": b}))
     return out
+
+
+def near_collinear(n: int, seed: int, rhos) -> np.ndarray:
+    """n x (2 len(rhos) + 2) float32 series of i.i.d. rows: for each rho a pair of columns
+    (z0, rho z0 + sqrt(1 - rho^2) z1) with Laplace, uniform and centred exponential noise in
+    turn, then one Laplace and one uniform column unrelated to the rest.  Pairs near |rho| = 1
+    are the near-collinear edge case of the pairwise residual."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed))
+    cols = []
+    for k, r in enumerate(rhos):
+        if k % 3 == 0:
+            z0, z1 = rng.laplace(size=n), rng.laplace(size=n)
+        elif k % 3 == 1:
+            z0, z1 = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n)
+        else:
+            z0, z1 = rng.exponential(size=n) - 1.0, rng.exponential(size=n) - 1.0
+        cols += [z0, r * z0 + math.sqrt(1.0 - r * r) * z1]
+    cols += [rng.laplace(size=n), rng.uniform(-1, 1, n)]
+    return np.ascontiguousarray(np.column_stack(cols).astype(np.float32))

@@ -94,6 +94,24 @@ def test_batch_matches_single_problem_path(api):
         np.testing.assert_allclose(r.E.cpu().numpy(), g.E.cpu().numpy(), rtol=0, atol=1e-5)
 
 
+def test_batch_near_collinear_pairs(api):
+    """Problems whose residuals hold pairs at rho = 0.99 ... 0.999999 (the collinear path of
+    the batched moment stage) next to an ordinary one: S of each against the oracle's."""
+    Xs = [synth.near_collinear(n, 50 + n, [0.99, 0.9999, 0.999999, 0.999])
+          for n in (600, 3000)]
+    plain = _instances([(12, 900, 1, "laplace")], seed0=3)[0]
+    results, status = api.fit_batched(Xs + [plain.X32], 1, "mixed")
+    assert status == [0, 0, 0]
+    for X, r in zip(Xs + [plain.X32], results):
+        ref = O.fit(X.astype(np.float64), 1, b_from_cov=True)
+        S = r.S.cpu().numpy()
+        assert np.array_equal(S, -S.T)
+        ds = float(np.max(np.abs(S - ref["S"])))
+        print(f"  near-collinear batch m={X.shape[1]} n={X.shape[0]}: max|dS| {ds:.2e}",
+              flush=True)
+        assert ds <= TOL_S
+
+
 def test_batch_error_isolation(api):
     spec = [(10, 600, 1, "uniform"), (12, 800, 1, "laplace"), (9, 500, 1, "uniform")]
     insts = _instances(spec, seed0=7)

@@ -193,6 +193,23 @@ def test_order_nonfinite_raises(api, dev):
     assert ei.value.code == VL_ERR_NONFINITE
 
 
+@pytest.mark.parametrize("m", [30, 100])
+def test_order_nonfinite_rows_still_give_a_permutation(api, dev, m):
+    """Rows 10..19 of S hold -inf, so their M is +inf like the removed entries: the status is
+    VL_ERR_NONFINITE, and the order must still be a permutation (no removed variable picked
+    again once only the +inf candidates are left)."""
+    from paper_2409_05500_amd._lib import VL_ERR_NONFINITE
+    A = np.random.default_rng(2).normal(size=(m, m))
+    S = A - A.T
+    S[10:20, 25] = -np.inf
+    S[25, 10:20] = np.inf
+    st = api.DeviceStatus(dev)
+    order, _ = api.approx_order(_dev(S, dev), status=st)
+    torch.cuda.synchronize()
+    assert int(st.t.item()) == VL_ERR_NONFINITE
+    assert sorted(order.cpu().numpy().tolist()) == list(range(m))
+
+
 def test_order_ties_lowest_index(api, dev):
     order, margin = api.approx_order(_dev(np.zeros((5, 5)), dev))
     assert order.cpu().numpy().tolist() == [0, 1, 2, 3, 4]
@@ -436,3 +453,13 @@ def test_var_fit_largest_design(api, dev):
     print(f"  max |z^T e| / (|z| |e|) over all regressors: {err:.1e}", flush=True)
     assert err <= 1e-5
     assert np.abs(E.mean(0)).max() <= 1e-5 * np.abs(E).max()      # the intercept
+
+
+@pytest.mark.parametrize("n", [600, 10000])
+def test_pairwise_near_collinear_pairs(api, dev, n):
+    """Pairs at rho = 0.99 ... 0.999999: the Eq. 1 residual x_i - rho x_j cancels almost
+    completely, so it must not be formed from rounded standardised data.  Element-wise Hx,
+    Hr, S against the oracle at the bounds of the well-conditioned tests."""
+    print(f"pairwise near-collinear n={n}", flush=True)
+    E32 = synth.near_collinear(n, 17 + n, [0.99, 0.999, 0.9999, 0.99999, 0.999999])
+    _check_pairwise(api, dev, E32)
