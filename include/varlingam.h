@@ -126,6 +126,23 @@ int pairwise_stats(const float* E, int64_t n_eff, int64_t m, int64_t lde, int pr
                    int32_t* dev_status, void* stream);
 
 /* ------------------------------------------------------------------------------------- */
+/* pairwise_stats without a workspace argument, for callers that cannot allocate device    */
+/* memory (code under HIP graph capture, tight serving loops, harnesses that forbid        */
+/* hipMalloc).  Arguments, outputs and errors as pairwise_stats.                          */
+/* Its scratch is a library-owned static device array of pairwise_stats_noalloc_max_bytes() */
+/* bytes (64 MiB) per GPU, held from the first call on that GPU until the process ends:    */
+/* n_eff and m whose pairwise_stats_workspace_bytes() exceed it return VL_ERR_WORKSPACE     */
+/* (m = 400 with n_eff = 10^4 needs about 39 MB).  Nothing is allocated, freed or cleared   */
+/* by the call: every scratch word the kernels read is written earlier in the same call.   */
+/* All calls on one GPU share that array, so calls that overlap on one GPU (other streams,  */
+/* other threads) race: serialise them.                                                    */
+/* ------------------------------------------------------------------------------------- */
+size_t pairwise_stats_noalloc_max_bytes(void);
+int pairwise_stats_noalloc(const float* E, int64_t n_eff, int64_t m, int64_t lde, int prec,
+                           double* Hx, double* Hr, double* S, double* Cov, int32_t* dev_status,
+                           void* stream);
+
+/* ------------------------------------------------------------------------------------- */
 /* Gradient of the pairwise score (the precompute of Sec. 4.2 steps 1-2 with Eq. 1-2 made  */
 /* differentiable): dE = d<G, S(E)>/dE for an m x m cotangent G.                           */
 /*                                                                                        */

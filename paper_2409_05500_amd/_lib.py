@@ -44,6 +44,8 @@ SIGNATURES = {
                                     _p]),
     "pairwise_stats_workspace_bytes": (_sz, [_i64, _i64, _i32]),
     "pairwise_stats": (_i32, [_p, _i64, _i64, _i64, _i32, _p, _p, _p, _p, _p, _sz, _p, _p]),
+    "pairwise_stats_noalloc_max_bytes": (_sz, []),
+    "pairwise_stats_noalloc": (_i32, [_p, _i64, _i64, _i64, _i32, _p, _p, _p, _p, _p, _p]),
     "pairwise_stats_backward_workspace_bytes": (_sz, [_i64, _i64, _i32]),
     "pairwise_stats_saved_doubles": (_sz, [_i64]),
     "pairwise_stats_save": (_i32, [_p, _i64, _i64, _i64, _i32, _p, _p, _p, _p, _p, _p, _sz, _p,

@@ -115,6 +115,33 @@ def pairwise_stats(E: torch.Tensor, prec="mixed", status: "DeviceStatus | None" 
     return Hx, Hr, S, Cov
 
 
+def pairwise_stats_noalloc(E: torch.Tensor, prec="mixed", status: "DeviceStatus | None" = None,
+                           out=None):
+    """pairwise_stats through the entry point that takes no workspace (the library's static
+    per-GPU scratch).  `out` may hold preallocated (Hx, Hr, S, Cov) f64 device tensors, so that
+    the call itself allocates nothing."""
+    _require(E, torch.float32, "E")
+    n_eff, m = E.shape
+    dev = E.device
+    if out is None:
+        out = (torch.empty(m, dtype=torch.float64, device=dev),
+               torch.empty((m, m), dtype=torch.float64, device=dev),
+               torch.empty((m, m), dtype=torch.float64, device=dev),
+               torch.empty((m, m), dtype=torch.float64, device=dev))
+    Hx, Hr, S, Cov = out
+    for t, shape in zip(out, ((m,), (m, m), (m, m), (m, m))):
+        if t.dtype != torch.float64 or not t.is_cuda or tuple(t.shape) != shape or \
+                not t.is_contiguous():
+            raise ValueError("out must be contiguous f64 device tensors (m), (m, m) x 3")
+    st = status if status is not None else DeviceStatus(dev)
+    check(lib.pairwise_stats_noalloc(E.data_ptr(), n_eff, m, E.stride(0), _prec(prec),
+                                     Hx.data_ptr(), Hr.data_ptr(), S.data_ptr(), Cov.data_ptr(),
+                                     st.ptr, _stream_ptr(dev)), "pairwise_stats_noalloc")
+    if status is None:
+        st.read("pairwise_stats_noalloc")
+    return Hx, Hr, S, Cov
+
+
 def pairwise_stats_save(E: torch.Tensor, prec="mixed", status: "DeviceStatus | None" = None):
     """pairwise_stats plus the block of forward statistics the backward can reuse:
     (Hx, Hr, S, Cov, saved) with saved [3 m^2 + 3 m] f64."""

@@ -1,4 +1,7 @@
 // extern "C" entry points: argument validation, workspace carving, status handling.
+#include <map>
+#include <mutex>
+
 #include "backward.hpp"
 #include "ensemble.hpp"
 #include "estimate_b.hpp"
@@ -23,6 +26,29 @@ inline bool aligned256(const void* p) { return (reinterpret_cast<uintptr_t>(p) &
 int begin(int32_t* dev_status, hipStream_t stream) {
   reset_status_kernel<<<1, 64, 0, stream>>>(dev_status);
   return hipGetLastError() == hipSuccess ? VL_OK : VL_ERR_HIP;
+}
+
+// Library-owned scratch of pairwise_stats_noalloc: one copy per GPU, held until the process
+// ends.  Host code never passes `scratch` itself (on the host it only names the symbol): the
+// device address comes from hipGetSymbolAddress, taken once per device with that device
+// current, and is kept in g_scratch.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch;
+
+int scratch_address(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return VL_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch.find(dev);
+  if (it == g_scratch.end()) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return VL_ERR_HIP;
+    it = g_scratch.emplace(dev, p).first;
+  }
+  *out = it->second;
+  return VL_OK;
 }
 
 }  // namespace
@@ -110,6 +136,27 @@ int pairwise_stats(const float* E, int64_t n_eff, int64_t m, int64_t lde, int pr
   pairwise_ws_bytes(p, ws, &w);
   hipStream_t s = as_stream(stream);
   int rc = begin(dev_status, s);
+  if (rc) return rc;
+  return run_pairwise(p, w, E, lde, prec, Hx, Hr, S, Cov, nullptr, dev_status, s);
+}
+
+size_t pairwise_stats_noalloc_max_bytes(void) { return kNoAllocScratchBytes; }
+
+int pairwise_stats_noalloc(const float* E, int64_t n_eff, int64_t m, int64_t lde, int prec,
+                           double* Hx, double* Hr, double* S, double* Cov, int32_t* dev_status,
+                           void* stream) {
+  if (!E || !Hx || !Hr || !S || !dev_status || !valid_prec(prec)) return VL_ERR_INVALID_ARG;
+  if (m < 2 || n_eff < 2 || m > 65536) return VL_ERR_SHAPE;
+  if (lde < m) return VL_ERR_INVALID_ARG;
+  const PairwisePlan p = plan_pairwise(n_eff, m);
+  if (pairwise_ws_bytes(p, nullptr, nullptr) > kNoAllocScratchBytes) return VL_ERR_WORKSPACE;
+  void* ws = nullptr;
+  int rc = scratch_address(&ws);
+  if (rc) return rc;
+  PairwiseWs w;
+  pairwise_ws_bytes(p, ws, &w);
+  hipStream_t s = as_stream(stream);
+  rc = begin(dev_status, s);
   if (rc) return rc;
   return run_pairwise(p, w, E, lde, prec, Hx, Hr, S, Cov, nullptr, dev_status, s);
 }
