@@ -58,7 +58,7 @@ struct BInst {
   float* Xs;
   float2* coef;
   float *partU, *partB;
-  int32_t* tflag;
+  int32_t* clist;   // near-collinear tile flags, count, list (2 tiles + 1)
   double *P, *Linv, *bchol;
 };
 
@@ -283,7 +283,8 @@ __global__ __launch_bounds__(256) void bat_standardize_kernel(BTables T, int32_t
   const BInst& d = T.inst[b];
   const int64_t gx = ceil_div(d.n_pad, 64);
   standardize_tile(d.E, d.lde, d.n_eff, d.m, d.emu, d.cov, d.Xs, d.n_pad, d.m_pad, st0 + b,
-                   (lb % gx) * 64, (lb / gx) * 64);
+                   (lb % gx) * 64, (lb / gx) * 64, d.clist, d.tiles + 1, lb,
+                   gx * ceil_div(d.m_pad, 64));
 }
 
 // Blocks [0, m): Hx of variable lb; then the pair coefficients, 256 entries per block.
@@ -294,7 +295,7 @@ __global__ __launch_bounds__(256) void bat_prep_kernel(BTables T, int32_t* st0) 
   if (lb < d.m)
     hx_block<256>(d.Xs, d.n_pad, d.n_eff, d.Hx, d.momx, lb);
   else
-    pair_coef_elem(d.cov, d.m, d.m_pad, d.coef, d.nt, d.tiles, d.tflag, st0 + b,
+    pair_coef_elem(d.cov, d.m, d.m_pad, d.coef, d.nt, d.tiles, d.clist, st0 + b,
                    (lb - d.m) * 256 + threadIdx.x);
 }
 
@@ -311,21 +312,20 @@ __global__ __launch_bounds__(256) void bat_moments_kernel(BTables T, int64_t tot
   if (item >= uni(d.items)) return;
   pairwise_moments_item(uni(d.Xs), uni(d.n_pad), uni(d.coef), uni(d.m_pad), uni(d.m),
                         (int)uni(d.nt), uni(d.tiles), (int)uni(d.chunk_len), item,
-                        uni(d.tflag), uni(d.partU), uni(d.partB));
+                        uni(d.partU), uni(d.partB));
 }
 
-// The items of micro-tiles with a near-collinear pair, in the same block layout.
-__global__ __launch_bounds__(256) void bat_collinear_kernel(BTables T, int64_t total) {
-  const int64_t g = blockIdx.x;
-  if (g >= total) return;
-  int64_t lb;
-  const int b = bat_locate(T, kMapMom, g, lb);
-  const BInst& d = T.inst[b];
+// The listed near-collinear tiles of problem blockIdx.x, recomputed after the moment kernel
+// (one workgroup per problem, grid-stride over its list).
+__global__ __launch_bounds__(256) void bat_collinear_kernel(const BInst* __restrict__ I) {
+  const BInst& d = I[blockIdx.x];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t item = uni(lb) * 4 + wave;
-  if (item >= uni(d.items)) return;
-  pairwise_collinear_item(d.E, d.lde, d.n_eff, d.emu, d.cov, d.m, d.nt, d.tiles, d.chunk_len,
-                          item, d.tflag, d.partU, d.partB);
+  const int64_t total = (int64_t)d.clist[d.tiles] * d.nchunk;
+  for (int64_t w = wave; w < total; w += 4) {
+    const int64_t tile = d.clist[d.tiles + 1 + w / d.nchunk], chunk = w % d.nchunk;
+    pairwise_collinear_item(d.E, d.lde, d.n_eff, d.emu, d.cov, d.m, d.nt, d.chunk_len, tile,
+                            chunk, d.partU, d.partB);
+  }
 }
 
 // Per unordered pair (one thread at i <= j): Hr of both orders, then S[i][j] and S[j][i] with
@@ -447,7 +447,7 @@ size_t carve_inst(const vl_instance& in, const InstLayout& L, char* base, BInst*
   t.coef = c.take<float2>(L.m_pad * L.m_pad);
   t.partU = c.take<float>((size_t)L.nchunk * m * m);
   t.partB = c.take<float>((size_t)L.nchunk * m * m);
-  t.tflag = c.take<int32_t>(L.tiles);
+  t.clist = c.take<int32_t>(2 * L.tiles + 1);
   t.P = c.take<double>(m * m);
   t.Linv = c.take<double>(m * m);
   t.bchol = c.take<double>(chol_ws_doubles_dev(m));
@@ -670,7 +670,7 @@ int launch_fit(const vl_batch* B, void* ws, int32_t* st, hipStream_t s) {
     const int64_t tot = B->total[kMapMom];
     bat_moments_kernel<<<(unsigned)round_up(tot, 8), 256, 0, s>>>(T, tot);
     VL_LAUNCH_CHECK();
-    bat_collinear_kernel<<<(unsigned)tot, 256, 0, s>>>(T, tot);
+    bat_collinear_kernel<<<(unsigned)n, 256, 0, s>>>(I);
     VL_LAUNCH_CHECK();
   }
   {

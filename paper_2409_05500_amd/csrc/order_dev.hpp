@@ -106,20 +106,17 @@ __device__ inline void order_wave_block(const double* __restrict__ S, int64_t m,
   if (bad) raise_status(st, VL_ERR_NONFINITE);
   __syncthreads();
   if (wave == 0) {
-  // Removed and padding entries hold +inf, so they never win a minimum over a finite M.  A
-  // live candidate can hold +inf too (its row of S had a non-finite entry, which raised
-  // VL_ERR_NONFINITE), so the index search runs over the live entries only: every step picks
-  // a variable not yet ordered.  Each step: m1 = wave min; i1 = lowest live index holding m1;
-  // the loads of row i1 are issued at once and the second minimum (the margin) is reduced
-  // while they are in flight.
-  const double inf = INFINITY;
+  // Removed and padding entries hold NaN: fmin passes over NaN, and NaN equals nothing, so
+  // they never win a minimum nor the index search even when every live M is +inf (a row of S
+  // with a non-finite entry, which raised VL_ERR_NONFINITE).  Each step: m1 = wave min over
+  // the live entries; i1 = lowest index holding m1; the loads of row i1 are issued at once
+  // and the second minimum (the margin) is reduced while they are in flight.
+  const double inf = INFINITY, gone = __builtin_nan("");
   double Mv[R];
-  bool live[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int i = lane + 64 * r;
-    live[r] = i < m;
-    Mv[r] = i < m ? M0s[i] : inf;
+    Mv[r] = i < m ? M0s[i] : gone;
   }
   const int64_t last = m - 1;
   for (int64_t k = 0; k < m; ++k) {
@@ -130,9 +127,9 @@ __device__ inline void order_wave_block(const double* __restrict__ S, int64_t m,
     int li = 0x7fffffff;
 #pragma unroll
     for (int r = R - 1; r >= 0; --r)
-      if (live[r] && Mv[r] == m1) li = lane + 64 * r;
+      if (Mv[r] == m1) li = lane + 64 * r;
     const int i1 = wave_min_i32(li);
-    // row i1 of S (indices clamped into the matrix; padding entries stay +inf)
+    // row i1 of S (indices clamped into the matrix; padding entries stay NaN)
     const double* rowp = S + (int64_t)(i1 < m ? i1 : last) * m;
     double v[R];
 #pragma unroll
@@ -143,22 +140,19 @@ __device__ inline void order_wave_block(const double* __restrict__ S, int64_t m,
     // remove the winner, then the margin from the remaining minimum
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if (lane + 64 * r == i1) {
-        Mv[r] = inf;
-        live[r] = false;
-      }
+      if (lane + 64 * r == i1) Mv[r] = gone;
     double l2 = Mv[0];
 #pragma unroll
     for (int r = 1; r < R; ++r) l2 = fmin(l2, Mv[r]);
-    const double m2 = wave_min_f64(l2);
+    const double m2 = wave_min_f64(l2);    // NaN when no live entry is left
     if (lane == 0) {
       order[k] = i1;
-      margin[k] = (m2 == inf) ? inf : m2 - m1;
+      margin[k] = (m2 == inf || m2 != m2) ? inf : m2 - m1;
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const double pos = v[r] > 0.0 && v[r] < inf ? v[r] : 0.0;
-      Mv[r] -= pos * pos;            // +inf stays +inf
+      Mv[r] -= pos * pos;            // +inf stays +inf, NaN stays NaN
     }
   }
   }

@@ -10,9 +10,9 @@
 //      u_{i<-j} = (x_i - rho x_j) / sqrt(1 - rho^2); the kernel receives the two scaled
 //      coefficients a = c / sqrt(1-rho^2), b = c rho / sqrt(1-rho^2) and forms w = c u;
 //   4. the hot kernel: for every pair and sample, both directions w_{i<-j}, w_{j<-i} and their
-//      entropy moments (Eq. 2): sum log cosh u and sum u exp(-u^2/2); micro-tiles holding a
-//      near-collinear pair (sqrt(1 - rho^2) < 0.25) are left to a second kernel that forms
-//      their residuals in FP64 from E;
+//      entropy moments (Eq. 2): sum log cosh u and sum u exp(-u^2/2); the micro-tiles holding
+//      a near-collinear pair (sqrt(1 - rho^2) < 0.25) are then recomputed by a second kernel
+//      that forms their residuals in FP64 from E;
 //   5. FP64 combine: Hr = H(nu) - k1 (A - gamma)^2 - k2 B^2 and
 //      S[i,j] = (Hx[j] + Hr[i,j]) - (Hx[i] + Hr[j,i]).
 #include <algorithm>
@@ -30,9 +30,10 @@ namespace vl {
 __global__ __launch_bounds__(256) void standardize_transpose_kernel(
     const float* __restrict__ E, int64_t lde, int64_t n_eff, int64_t m,
     const double* __restrict__ mu, const double* __restrict__ cov, float* __restrict__ Xs,
-    int64_t n_pad, int64_t m_pad, int32_t* st) {
+    int64_t n_pad, int64_t m_pad, int32_t* st, int32_t* __restrict__ zero, int64_t nzero) {
   standardize_tile(E, lde, n_eff, m, mu, cov, Xs, n_pad, m_pad, st, (int64_t)blockIdx.x * 64,
-                   (int64_t)blockIdx.y * 64);
+                   (int64_t)blockIdx.y * 64, zero, nzero,
+                   (int64_t)blockIdx.y * gridDim.x + blockIdx.x, (int64_t)gridDim.x * gridDim.y);
 }
 
 // 1024 threads per variable: one workgroup per variable is all the parallelism there is (a few
@@ -49,8 +50,8 @@ __global__ __launch_bounds__(kHxThreads) void hx_kernel(const float* __restrict_
 
 __global__ void pair_coef_kernel(const double* __restrict__ cov, int64_t m, int64_t m_pad,
                                  float2* __restrict__ coef, int nt, int64_t tiles,
-                                 int32_t* __restrict__ tflag, int32_t* st) {
-  pair_coef_elem(cov, m, m_pad, coef, nt, tiles, tflag, st,
+                                 int32_t* __restrict__ clist, int32_t* st) {
+  pair_coef_elem(cov, m, m_pad, coef, nt, tiles, clist, st,
                  (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
@@ -59,28 +60,30 @@ __global__ void pair_coef_kernel(const double* __restrict__ cov, int64_t m, int6
 __global__ __launch_bounds__(256) void pairwise_moments_kernel(
     const float* __restrict__ Xs, int64_t n_pad, const float2* __restrict__ coef, int64_t m_pad,
     int64_t m, int nt, int64_t tiles, int chunk_len, int64_t items,
-    const int32_t* __restrict__ tflag, float* __restrict__ partU, float* __restrict__ partB) {
+    float* __restrict__ partU, float* __restrict__ partB) {
   const int64_t nb = gridDim.x;                     // a multiple of 8
   const int64_t b = blockIdx.x;
   const int64_t lb = (b & 7) * (nb >> 3) + (b >> 3);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t item = lb * 4 + wave;
   if (item >= items) return;
-  pairwise_moments_item(Xs, n_pad, coef, m_pad, m, nt, tiles, chunk_len, item, tflag, partU,
-                        partB);
+  pairwise_moments_item(Xs, n_pad, coef, m_pad, m, nt, tiles, chunk_len, item, partU, partB);
 }
 
-// The items of micro-tiles with a near-collinear pair (every other wave returns at once).
+// The (listed tile, chunk) items of the near-collinear micro-tiles, grid-stride over the list
+// the coefficient stage built (count = clist[tiles]); with no listed tile every wave returns
+// at once.
 __global__ __launch_bounds__(256) void pairwise_collinear_kernel(
     const float* __restrict__ E, int64_t lde, int64_t n_eff, const double* __restrict__ mu,
-    const double* __restrict__ cov, int64_t m, int nt, int64_t tiles, int chunk_len,
-    int64_t items, const int32_t* __restrict__ tflag, float* __restrict__ partU,
-    float* __restrict__ partB) {
+    const double* __restrict__ cov, int64_t m, int nt, int64_t tiles, int nc, int chunk_len,
+    const int32_t* __restrict__ clist, float* __restrict__ partU, float* __restrict__ partB) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t item = (int64_t)blockIdx.x * 4 + wave;
-  if (item >= items) return;
-  pairwise_collinear_item(E, lde, n_eff, mu, cov, m, nt, tiles, chunk_len, item, tflag, partU,
-                          partB);
+  const int64_t total = (int64_t)clist[tiles] * nc;
+  for (int64_t w = (int64_t)blockIdx.x * 4 + wave; w < total; w += (int64_t)gridDim.x * 4) {
+    const int64_t tile = clist[tiles + 1 + w / nc], chunk = w % nc;
+    pairwise_collinear_item(E, lde, n_eff, mu, cov, m, nt, chunk_len, tile, chunk, partU,
+                            partB);
+  }
 }
 
 __global__ void combine_hr_kernel(const float* __restrict__ partU, const float* __restrict__ partB,
@@ -135,7 +138,7 @@ size_t pairwise_ws_bytes(const PairwisePlan& p, void* base, PairwiseWs* out) {
   w.coef = b.take<float2>(p.m_pad * p.m_pad);
   w.partU = b.take<float>((size_t)p.nc * p.m * p.m);
   w.partB = b.take<float>((size_t)p.nc * p.m * p.m);
-  w.tflag = b.take<int32_t>(p.tiles);
+  w.clist = b.take<int32_t>(2 * p.tiles + 1);
   if (out) *out = w;
   return c.used + std::max(a.used, b.used);
 }
@@ -148,10 +151,10 @@ size_t scratch_doubles(const PairwisePlan& p) {
 
 int standardize_to(const float* E, int64_t lde, int64_t n_eff, int64_t m, const double* mu,
                    const double* cov, float* Xs, int64_t n_pad, int64_t m_pad, int32_t* st,
-                   hipStream_t stream) {
+                   hipStream_t stream, int32_t* zero, int64_t nzero) {
   dim3 g((unsigned)ceil_div(n_pad, 64), (unsigned)ceil_div(m_pad, 64));
   standardize_transpose_kernel<<<g, 256, 0, stream>>>(E, lde, n_eff, m, mu, cov, Xs, n_pad,
-                                                       m_pad, st);
+                                                       m_pad, st, zero, nzero);
   VL_LAUNCH_CHECK();
   return VL_OK;
 }
@@ -173,25 +176,27 @@ int run_pairwise(const PairwisePlan& p, const PairwiseWs& w, const float* E, int
   }
   {
     ProfileScope ps("pairwise_prep", stream);
-    int rc = standardize_to(E, lde, n_eff, m, w.mu, cov, w.Xs, p.n_pad, p.m_pad, st, stream);
+    int rc = standardize_to(E, lde, n_eff, m, w.mu, cov, w.Xs, p.n_pad, p.m_pad, st, stream,
+                            w.clist, p.tiles + 1);
     if (rc) return rc;
     hx_kernel<<<(unsigned)m, kHxThreads, 0, stream>>>(w.Xs, p.n_pad, n_eff, Hx, w.momx);
     VL_LAUNCH_CHECK();
     pair_coef_kernel<<<(unsigned)ceil_div(p.m_pad * p.m_pad, 256), 256, 0, stream>>>(
-        cov, m, p.m_pad, w.coef, p.nt, p.tiles, w.tflag, st);
+        cov, m, p.m_pad, w.coef, p.nt, p.tiles, w.clist, st);
     VL_LAUNCH_CHECK();
   }
   {
     ProfileScope ps("pairwise_moments", stream);
     pairwise_moments_kernel<<<(unsigned)p.blocks, 256, 0, stream>>>(
-        w.Xs, p.n_pad, w.coef, p.m_pad, m, p.nt, p.tiles, p.chunk_len, p.items, w.tflag,
-        w.partU, w.partB);
+        w.Xs, p.n_pad, w.coef, p.m_pad, m, p.nt, p.tiles, p.chunk_len, p.items, w.partU,
+        w.partB);
     VL_LAUNCH_CHECK();
   }
   {
     ProfileScope ps("pairwise_collinear", stream);
-    pairwise_collinear_kernel<<<(unsigned)ceil_div(p.items, 4), 256, 0, stream>>>(
-        E, lde, n_eff, w.mu, cov, m, p.nt, p.tiles, p.chunk_len, p.items, w.tflag, w.partU,
+    const int64_t blocks = std::min<int64_t>(ceil_div(p.items, 4), 256);
+    pairwise_collinear_kernel<<<(unsigned)blocks, 256, 0, stream>>>(
+        E, lde, n_eff, w.mu, cov, m, p.nt, p.tiles, p.nc, p.chunk_len, w.clist, w.partU,
         w.partB);
     VL_LAUNCH_CHECK();
   }

@@ -25,7 +25,7 @@ struct PairwiseWs {
   float* partU = nullptr;     // nc x m x m
   float* partB = nullptr;     // nc x m x m
   double* momx = nullptr;     // 2 m: E[log cosh x_i], E[x_i exp(-x_i^2/2)]
-  int32_t* tflag = nullptr;   // tiles: 1 where the micro-tile holds a near-collinear pair
+  int32_t* clist = nullptr;   // 2 tiles + 1: near-collinear tile flags, count, list
 };
 
 PairwisePlan plan_pairwise(int64_t n_eff, int64_t m);
@@ -34,9 +34,10 @@ size_t scratch_doubles(const PairwisePlan& p);
 size_t pairwise_ws_bytes(const PairwisePlan& p, void* base, PairwiseWs* out);
 // Standardise E with the given means and covariance diagonal into the variable-major Xs
 // (m_pad x n_pad, zero padded).  n_pad >= n_eff, m_pad >= m.
+// The launch also clears zero[0 .. nzero) (nullptr: nothing).
 int standardize_to(const float* E, int64_t lde, int64_t n_eff, int64_t m, const double* mu,
                    const double* cov, float* Xs, int64_t n_pad, int64_t m_pad, int32_t* st,
-                   hipStream_t stream);
+                   hipStream_t stream, int32_t* zero = nullptr, int64_t nzero = 0);
 // mom (nullable): 2 m^2 doubles, (A, B) per ordered pair, for tests and the backward pass.
 int run_pairwise(const PairwisePlan& p, const PairwiseWs& w, const float* E, int64_t lde,
                  int prec, double* Hx, double* Hr, double* S, double* Cov, double* mom,

@@ -8,12 +8,17 @@ namespace vl {
 // ------------------------------------------------------------------------------------------
 // Stage 2a: standardise + transpose.  Block = 64 x 64 tile of E (t x i), staged through LDS.
 // ------------------------------------------------------------------------------------------
+// The blocks also clear zero[0 .. nzero) (the collinear-tile flags and list count of the
+// pairwise precompute; nullptr for none), block `blk` of `nblk` taking a grid-stride share.
 __device__ inline void standardize_tile(
     const float* __restrict__ E, int64_t lde, int64_t n_eff, int64_t m,
     const double* __restrict__ mu, const double* __restrict__ cov, float* __restrict__ Xs,
-    int64_t n_pad, int64_t m_pad, int32_t* st, int64_t t0, int64_t i0) {
+    int64_t n_pad, int64_t m_pad, int32_t* st, int64_t t0, int64_t i0,
+    int32_t* __restrict__ zero = nullptr, int64_t nzero = 0, int64_t blk = 0, int64_t nblk = 1) {
   __shared__ float tile[64][65];
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  if (zero)
+    for (int64_t e = blk * blockDim.x + threadIdx.x; e < nzero; e += nblk * blockDim.x) zero[e] = 0;
   const int64_t i = i0 + tx;
   double mui = 0.0, inv = 0.0;
   if (i < m) {
@@ -105,33 +110,31 @@ __device__ inline void tile_coords(int64_t k, int nt, int& bi, int& bj) {
 
 // A pair with sqrt(1 - rho^2) below kCollinearS is near-collinear: its Eq. 1 residual
 // x_i - rho x_j cancels to a small fraction of the data, and forming it from the FP32 rounded
-// standardised columns would amplify their rounding by 1 / sqrt(1 - rho^2).  Micro-tiles that
-// hold such a pair are skipped by the FP32 moment kernel and run by the collinear kernel,
-// which standardises and forms the residual in FP64 from E itself.
+// standardised columns would amplify their rounding by 1 / sqrt(1 - rho^2).  The coefficient
+// stage lists the micro-tiles that hold such a pair; after the FP32 moment kernel (which runs
+// every tile) the collinear kernel recomputes their items, standardising and forming the
+// residual in FP64 from E itself, and overwrites their partials.
+// List layout (int32): flag[tiles] (1 = listed), then count, then the listed tile indices; the
+// flags and the count are cleared by the standardisation stage.
 constexpr double kCollinearS = 0.25;
 
-__device__ inline int32_t tile_collinear_flag(const double* __restrict__ cov, int64_t m, int nt,
-                                              int64_t tile) {
-  int bi, bj;
-  tile_coords(tile, nt, bi, bj);
-  for (int ii = 0; ii < kT; ++ii)
-    for (int jj = 0; jj < kT; ++jj) {
-      const int64_t i = (int64_t)bi * kT + ii, j = (int64_t)bj * kT + jj;
-      if (i >= m || j >= m || i == j) continue;
-      const double rho = cov[i * m + j] / sqrt(cov[i * m + i] * cov[j * m + j]);
-      if (!(1.0 - rho * rho >= kCollinearS * kCollinearS)) return 1;
-    }
-  return 0;
+__device__ inline void list_collinear_tile(int32_t* __restrict__ clist, int nt, int64_t tiles,
+                                           int64_t i, int64_t j) {
+  const int64_t a = (i < j ? i : j) / kT, b = (i < j ? j : i) / kT;
+  const int64_t tile = a * nt - a * (a - 1) / 2 + (b - a);
+  if (atomicExch(&clist[tile], 1) == 0) {
+    const int k = atomicAdd(&clist[tiles], 1);
+    clist[tiles + 1 + k] = (int32_t)tile;
+  }
 }
 
 // ------------------------------------------------------------------------------------------
 // Stage 3: scaled pair coefficients (a, b) for i, j < m_pad; zero on the diagonal / padding.
-// Thread e < tiles also writes the collinear flag of micro-tile e.
+// A near-collinear pair lists its micro-tile in clist.
 // ------------------------------------------------------------------------------------------
 __device__ inline void pair_coef_elem(const double* __restrict__ cov, int64_t m, int64_t m_pad,
                                       float2* __restrict__ coef, int nt, int64_t tiles,
-                                      int32_t* __restrict__ tflag, int32_t* st, int64_t e) {
-  if (e < tiles) tflag[e] = tile_collinear_flag(cov, m, nt, e);
+                                      int32_t* __restrict__ clist, int32_t* st, int64_t e) {
   if (e >= m_pad * m_pad) return;
   const int64_t i = e / m_pad, j = e % m_pad;
   float2 c = make_float2(0.f, 0.f);
@@ -139,6 +142,7 @@ __device__ inline void pair_coef_elem(const double* __restrict__ cov, int64_t m,
     const double vi = cov[i * m + i], vj = cov[j * m + j];
     const double rho = cov[i * m + j] / sqrt(vi * vj);
     const double omr = 1.0 - rho * rho;
+    if (!(omr >= kCollinearS * kCollinearS)) list_collinear_tile(clist, nt, tiles, i, j);
     if (!(omr >= kMinOneMinusRho2)) {
       raise_status(st, VL_ERR_DEGENERATE);
     } else {
@@ -211,18 +215,13 @@ __device__ __forceinline__ void write_moment_partials(
 
 // One wave's work item (tile, chunk); item < items is the caller's check.  Always inlined:
 // as a call its register use rises from 168 to 248 and the occupancy falls to 2 waves/SIMD.
-// tflag[tile] != 0 marks a micro-tile with a near-collinear pair: left to the collinear item.
 __device__ __attribute__((always_inline)) inline void pairwise_moments_item(
     const float* __restrict__ Xs, int64_t n_pad, const float2* __restrict__ coef, int64_t m_pad,
     int64_t m, int nt, int64_t tiles, int chunk_len, int64_t item,
-    const int32_t* __restrict__ tflag, float* __restrict__ partU, float* __restrict__ partB) {
+    float* __restrict__ partU, float* __restrict__ partB) {
   const int lane = threadIdx.x & 63;
   const int64_t chunk = item / tiles;
   const int64_t tile = item - chunk * tiles;
-  {
-    typedef const __attribute__((address_space(4))) int32_t* const_i32p;
-    if (((const_i32p)(uintptr_t)tflag)[tile]) return;
-  }
   int bi, bj;
   tile_coords(tile, nt, bi, bj);
   const int64_t i0 = (int64_t)bi * kT, j0 = (int64_t)bj * kT;
@@ -306,24 +305,37 @@ __device__ __attribute__((always_inline)) inline void pairwise_moments_item(
     }
   }
 
-  write_moment_partials(U, B, i0, j0, m, chunk, partU, partB);
+  // value index v = kind*32 + d*16 + ii*4 + jj (kind 0: U, 1: B)
+  float v[64];
+#pragma unroll
+  for (int d = 0; d < 2; ++d)
+#pragma unroll
+    for (int ii = 0; ii < kT; ++ii)
+#pragma unroll
+      for (int jj = 0; jj < kT; ++jj) {
+        v[d * 16 + ii * 4 + jj] = U[d][ii][jj];
+        v[32 + d * 16 + ii * 4 + jj] = B[d][ii][jj];
+      }
+  const float sum = wave_reduce_scatter64(v);
+  const int kind = lane >> 5, d = (lane >> 4) & 1, ii = (lane >> 2) & 3, jj = lane & 3;
+  const int64_t i = i0 + ii, j = j0 + jj;
+  if (i < m && j < m && i != j) {
+    const int64_t row = d ? j : i, col = d ? i : j;
+    float* dst = kind ? partB : partU;
+    dst[chunk * m * m + row * m + col] = sum;
+  }
 }
 
-// The same item for a micro-tile with a near-collinear pair (tflag[tile] != 0; others return
-// at once).  Lanes run over samples, one per step.  Each sample of the tile's 2 kT variables
+// The same item, (tile, chunk), for a listed micro-tile.  Lanes run over samples, one per step.  Each sample of the tile's 2 kT variables
 // is standardised in FP64 from E (x = (e - mu) / sd, population moments), the residuals of
 // both directions are formed in FP64, d = x_i - rho x_j, and only the scaled residual
 // w = d c / sqrt(1 - rho^2) is rounded to FP32: its relative error is then that of one
 // rounding, as for a well-conditioned pair.  The moment terms are the fast item's.
 __device__ inline void pairwise_collinear_item(
     const float* __restrict__ E, int64_t lde, int64_t n_eff, const double* __restrict__ mu,
-    const double* __restrict__ cov, int64_t m, int nt, int64_t tiles, int chunk_len,
-    int64_t item, const int32_t* __restrict__ tflag, float* __restrict__ partU,
-    float* __restrict__ partB) {
+    const double* __restrict__ cov, int64_t m, int nt, int chunk_len, int64_t tile,
+    int64_t chunk, float* __restrict__ partU, float* __restrict__ partB) {
   const int lane = threadIdx.x & 63;
-  const int64_t chunk = item / tiles;
-  const int64_t tile = item - chunk * tiles;
-  if (!tflag[tile]) return;
   int bi, bj;
   tile_coords(tile, nt, bi, bj);
   const int64_t i0 = (int64_t)bi * kT, j0 = (int64_t)bj * kT;
