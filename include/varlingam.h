@@ -56,9 +56,18 @@ typedef enum {
  *                  its correlation with the lags formed in FP64); residual GEMM and covariance
  *                  as MIXED.  Meant for well-conditioned lag designs: when the last
  *                  refinement step still changes the coefficients by more than 1e-6 of their
- *                  largest magnitude, the fit raises VL_ERR_SINGULAR.  The batched fit takes
- *                  FP32 and MIXED only. */
-typedef enum { VL_PREC_FP32 = 0, VL_PREC_MIXED = 1, VL_PREC_BF16 = 2 } vl_precision;
+ *                  largest magnitude, the fit raises VL_ERR_SINGULAR.
+ *   VL_PREC_FP32_REFINED: the FP32 Gram matrices of VL_PREC_FP32, FP64 Cholesky, one FP64
+ *                  refinement step as in VL_PREC_BF16 (same convergence check), residual GEMM
+ *                  and covariance as MIXED.  The cheapest form on the FP32 Gram that meets
+ *                  the FP64 solution's accuracy.
+ * The batched fit takes FP32 and MIXED only. */
+typedef enum {
+  VL_PREC_FP32 = 0,
+  VL_PREC_MIXED = 1,
+  VL_PREC_BF16 = 2,
+  VL_PREC_FP32_REFINED = 3
+} vl_precision;
 
 /* Human-readable name of a status code (static string, never NULL). */
 const char* varlingam_status_string(int status);
@@ -185,6 +194,35 @@ int pairwise_stats_backward(const float* E, int64_t n_eff, int64_t m, int64_t ld
 size_t approx_order_workspace_bytes(int64_t m);
 int approx_order(const double* S, int64_t m, int32_t* order, double* margin, void* ws,
                  size_t ws_bytes, int32_t* dev_status, void* stream);
+
+/* ------------------------------------------------------------------------------------- */
+/* Certified ordering: Alg. 1 as approx_order, where every step that the scores' error     */
+/* bound cannot decide is re-decided on scores recomputed in FP64 (Eq. 1-3 in FP64 from E).  */
+/* With |S_ij - S*_ij| <= eps_S for the scores passed in (S* the exact ones), M_i of Eq. 3   */
+/* is within EM_i = sum_{j in U, S_ij < eps} eps (2 |min(0, S_ij)| + eps) of its exact      */
+/* value; a step is settled when M_c + EM_c - (M_i - EM_i) <= 1e-9 for every other i (the  */
+/* pick is then within 1e-9 of the exact minimum).  Otherwise the pick and every i that     */
+/* breaks it have their rows and columns of S recomputed in FP64 (population-moment        */
+/* standardisation, rho = mean(x_i x_j), both residuals, the Eq. 2 moments and H, FP64      */
+/* throughout; those entries then count as exact), and the ordering runs again, until no    */
+/* step is in doubt (at most m rounds; each refines at least one new row).                  */
+/* E        in, n_eff x m float32 (leading dimension lde >= m): the data S was computed from. */
+/* S        in/out, m x m float64 (from pairwise_stats): the refined rows are written back.  */
+/* eps_S    in, the error bound of S's entries (>= 0; the FP32-moment scores of            */
+/*          pairwise_stats stay within 6.1e-7 of the FP64 oracle on every workload tested).  */
+/* order, margin  out as approx_order (margins of the final round).                           */
+/* refined  out, nullable, m int32: 1 for a row recomputed in FP64.                           */
+/* n_refined out, nullable, HOST pointer: number of rows recomputed.                          */
+/* Unlike the other calls this one synchronises `stream` (once per round) to size the FP64  */
+/* recomputation.  Host errors: m < 1, m > 4096, n_eff < 2 -> VL_ERR_SHAPE; eps_S < 0 or a  */
+/* null pointer -> VL_ERR_INVALID_ARG.  Status: VL_ERR_DEGENERATE (a constant column or a    */
+/* pair with 1 - rho^2 < 1e-12 among the recomputed ones).                                   */
+/* ------------------------------------------------------------------------------------- */
+size_t approx_order_certified_workspace_bytes(int64_t n_eff, int64_t m);
+int approx_order_certified(const float* E, int64_t n_eff, int64_t m, int64_t lde, double* S,
+                           double eps_S, int32_t* order, double* margin, int32_t* refined,
+                           int64_t* n_refined, void* ws, size_t ws_bytes, int32_t* dev_status,
+                           void* stream);
 
 /* ------------------------------------------------------------------------------------- */
 /* The original iterative DirectLiNGAM ordering (Sec. 3 steps 1-5), the search the       */
@@ -368,6 +406,7 @@ void varlingam_batch_destroy(vl_batch* batch);
 /*   var_gram, var_solve, var_residual, var_refine, pairwise_cov, pairwise_prep,            */
 /*   pairwise_moments, pairwise_combine, backward_prep, backward_owner, backward_tail,       */
 /*   order, estimate_b, batch_var, batch_pairwise, batch_moments, batch_order_b, iterative, */
+/*   certify,                                                                              */
 /*   lag_scores, prune, simulate.                                                           */
 /* varlingam_profile_read() waits for the recorded events of one stage and returns the      */
 /* accumulated milliseconds and the number of recorded launches.  Thread-safe.              */

@@ -17,7 +17,7 @@ VL_ERR_NONFINITE = -5
 VL_ERR_WORKSPACE = -6
 VL_ERR_HIP = -7
 
-PREC = {"fp32": 0, "mixed": 1, "bf16": 2}
+PREC = {"fp32": 0, "mixed": 1, "bf16": 2, "fp32_refined": 3}
 
 _p = C.c_void_p
 _i64 = C.c_int64
@@ -52,6 +52,9 @@ SIGNATURES = {
                                    _p]),
     "pairwise_stats_backward": (_i32, [_p, _i64, _i64, _i64, _i32, _p, _p, _p, _i64, _p, _sz,
                                        _p, _p]),
+    "approx_order_certified_workspace_bytes": (_sz, [_i64, _i64]),
+    "approx_order_certified": (_i32, [_p, _i64, _i64, _i64, _p, _f64, _p, _p, _p,
+                                      C.POINTER(_i64), _p, _sz, _p, _p]),
     "approx_order_workspace_bytes": (_sz, [_i64]),
     "approx_order": (_i32, [_p, _i64, _p, _p, _p, _sz, _p, _p]),
     "varlingam_order_iterative_workspace_bytes": (_sz, [_i64, _i64, _i32]),

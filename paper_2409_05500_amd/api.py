@@ -243,6 +243,39 @@ def approx_order(S: torch.Tensor, status: "DeviceStatus | None" = None):
     return order, margin
 
 
+# The largest |S - S_oracle| the FP32-moment scores of pairwise_stats showed on any workload
+# tested (6.1e-7), rounded up: the default error bound of the certified ordering.
+CERT_EPS_S = 1e-6
+
+
+def approx_order_certified(E: torch.Tensor, S: torch.Tensor, eps_S: float = CERT_EPS_S,
+                           status: "DeviceStatus | None" = None):
+    """Alg. 1 on S with every step the bound eps_S cannot settle re-decided on FP64 scores
+    recomputed from E (n_eff x m f32, the data S came from).  S (m x m f64) is updated in
+    place.  Returns (order [m] int32, margin [m] f64, refined [m] int32 flags, rows refined).
+    Synchronises the stream."""
+    _require(E, torch.float32, "E")
+    _require(S, torch.float64, "S")
+    n_eff, m = E.shape
+    dev = E.device
+    if not S.is_contiguous() or tuple(S.shape) != (m, m):
+        raise ValueError("S must be a contiguous m x m f64 device tensor")
+    order = torch.empty(m, dtype=torch.int32, device=dev)
+    margin = torch.empty(m, dtype=torch.float64, device=dev)
+    refined = torch.empty(m, dtype=torch.int32, device=dev)
+    ws = _workspace(lib.approx_order_certified_workspace_bytes(n_eff, m), dev)
+    st = status if status is not None else DeviceStatus(dev)
+    nref = C.c_int64(0)
+    check(lib.approx_order_certified(E.data_ptr(), n_eff, m, E.stride(0), S.data_ptr(),
+                                     float(eps_S), order.data_ptr(), margin.data_ptr(),
+                                     refined.data_ptr(), C.byref(nref), ws.data_ptr(),
+                                     ws.numel(), st.ptr, _stream_ptr(dev)),
+          "approx_order_certified")
+    if status is None:
+        st.read("approx_order_certified")
+    return order, margin, refined, int(nref.value)
+
+
 def order_iterative(E: torch.Tensor, prec="mixed", status: "DeviceStatus | None" = None):
     """(order [m] int32, margin [m] f64) of the original iterative DirectLiNGAM search on the
     n_eff x m residuals (the pairwise scores recomputed on the updated data at every step)."""

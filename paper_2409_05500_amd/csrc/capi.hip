@@ -3,6 +3,7 @@
 #include <mutex>
 
 #include "backward.hpp"
+#include "certify.hpp"
 #include "ensemble.hpp"
 #include "estimate_b.hpp"
 #include "iterative.hpp"
@@ -18,7 +19,8 @@ namespace {
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 inline bool valid_prec(int prec) {
-  return prec == VL_PREC_FP32 || prec == VL_PREC_MIXED || prec == VL_PREC_BF16;
+  return prec == VL_PREC_FP32 || prec == VL_PREC_MIXED || prec == VL_PREC_BF16 ||
+         prec == VL_PREC_FP32_REFINED;
 }
 
 inline bool aligned256(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
@@ -277,6 +279,31 @@ int approx_order(const double* S, int64_t m, int32_t* order, double* margin, voi
   int rc = begin(dev_status, s);
   if (rc) return rc;
   return run_order(S, m, order, margin, static_cast<double*>(ws), dev_status, s);
+}
+
+// ----------------------------------------------------------------------------------------
+size_t approx_order_certified_workspace_bytes(int64_t n_eff, int64_t m) {
+  if (m < 1 || m > 4096 || n_eff < 2) return 0;
+  return cert_ws_bytes(n_eff, m, nullptr, nullptr);
+}
+
+int approx_order_certified(const float* E, int64_t n_eff, int64_t m, int64_t lde, double* S,
+                           double eps_S, int32_t* order, double* margin, int32_t* refined,
+                           int64_t* n_refined, void* ws, size_t ws_bytes, int32_t* dev_status,
+                           void* stream) {
+  if (!E || !S || !order || !margin || !dev_status || !(eps_S >= 0.0)) return VL_ERR_INVALID_ARG;
+  if (m < 1 || m > 4096 || n_eff < 2) return VL_ERR_SHAPE;
+  if (lde < m) return VL_ERR_INVALID_ARG;
+  if (!ws || ws_bytes < cert_ws_bytes(n_eff, m, nullptr, nullptr) || !aligned256(ws))
+    return VL_ERR_WORKSPACE;
+  CertWs w;
+  cert_ws_bytes(n_eff, m, ws, &w);
+  hipStream_t s = as_stream(stream);
+  int rc = begin(dev_status, s);
+  if (rc) return rc;
+  int64_t rounds = 0;
+  return run_order_certified(E, n_eff, m, lde, S, eps_S, order, margin, refined, n_refined,
+                             &rounds, w, dev_status, s);
 }
 
 // ----------------------------------------------------------------------------------------

@@ -9,6 +9,9 @@
 //   MIXED: Gram matrices by FP64 MFMA on the widened FP32 data (exact products, FP64 sums), FP64
 //          Cholesky solve, residual GEMM by FP64 MFMA, E rounded to FP32 once.
 //   FP32:  Gram and residual GEMM by FP32 MFMA with FP32 sums; FP64 Cholesky; no refinement.
+//   FP32_REFINED: the FP32 Gram of plain FP32, then one refinement step as BF16 below, and
+//          the residual GEMM by FP64 MFMA: the cheapest form built on the FP32 Gram that
+//          reaches the FP64 solution's accuracy.
 //   BF16:  Gram matrices by BF16 MFMA (FP32 sums flushed to FP64), FP64 Cholesky of that Gram,
 //          then kBf16RefineSteps refinement steps Coef += G^{-1} Zc^T E64 with the residual
 //          E64 = Yc - Zc Coef and its correlation with Zc formed in FP64 (exact products of the
@@ -50,10 +53,14 @@ __global__ void add_f64_kernel(double* __restrict__ a, const double* __restrict_
   if (e < n) a[e] += d[e];
 }
 
-// Convergence of the BF16-mode refinement: the last correction d must be below
-// kRefineTol * max|c| (and finite), else the design is too ill-conditioned for a BF16 Gram and
-// VL_ERR_SINGULAR is raised.  Per-workgroup partials into the split scratch, then one workgroup.
-constexpr double kRefineTol = 1e-6;
+// Convergence of the refinement: the last correction d must be below tol * max|c| (and
+// finite), else the design is too ill-conditioned for the low-precision Gram and
+// VL_ERR_SINGULAR is raised.  BF16 (three steps): the last correction must have shrunk to
+// kRefineTolBf16.  FP32_REFINED (one step): the correction is the FP32 solve's error, and
+// below kRefineTolFp32 the step contracts it by cond(G) u_FP32 < 1e-3 at least.  Per-workgroup
+// partials into the split scratch, then one workgroup.
+constexpr double kRefineTolBf16 = 1e-6;
+constexpr double kRefineTolFp32 = 1e-3;
 
 constexpr int kCheckBlocks = 256;
 
@@ -88,10 +95,10 @@ __global__ __launch_bounds__(256) void refine_partial_kernel(const double* __res
   }
 }
 
-// One workgroup over the partials: the correction must be finite and below kRefineTol of the
+// One workgroup over the partials: the correction must be finite and below tol of the
 // solution.
 __global__ __launch_bounds__(256) void refine_check_kernel(const double* __restrict__ part,
-                                                           int nb, int32_t* st) {
+                                                           int nb, double tol, int32_t* st) {
   __shared__ double sd[256], sc[256], sb[256];
   double md = 0.0, mc = 0.0, bad = 0.0;
   for (int b = threadIdx.x; b < nb; b += 256) {
@@ -111,7 +118,7 @@ __global__ __launch_bounds__(256) void refine_check_kernel(const double* __restr
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0 && (sb[0] != 0.0 || !(sd[0] <= kRefineTol * sc[0])))
+  if (threadIdx.x == 0 && (sb[0] != 0.0 || !(sd[0] <= tol * sc[0])))
     raise_status(st, VL_ERR_SINGULAR);
 }
 
@@ -345,8 +352,11 @@ int run_var(const VarPlan& v, const VarWs& w, const float* X, int64_t ldx, int p
             double* intercept, float* E, int64_t lde, int32_t* st, hipStream_t stream) {
   const int64_t m = v.m, dz = v.dz, n_eff = v.n_eff;
   const bool plain = prec == VL_PREC_FP32;
-  const bool refine = prec == VL_PREC_BF16;
-  const GramMode gmode = plain ? GramMode::kFp32 : refine ? GramMode::kBf16 : GramMode::kFp64;
+  const bool refine = prec == VL_PREC_BF16 || prec == VL_PREC_FP32_REFINED;
+  const GramMode gmode = (plain || prec == VL_PREC_FP32_REFINED) ? GramMode::kFp32
+                         : prec == VL_PREC_BF16                 ? GramMode::kBf16
+                                                                : GramMode::kFp64;
+  const int steps = prec == VL_PREC_BF16 ? kBf16RefineSteps : 1;
   const int64_t* mapZ = w.colmap + m;
   const double* muZ = w.mu + m;
   int rc = var_normal_equations(v, w, X, ldx, gmode, st, stream);
@@ -362,7 +372,7 @@ int run_var(const VarPlan& v, const VarWs& w, const float* X, int64_t ldx, int p
   }
   if (refine) {
     ProfileScope ps("var_refine", stream);
-    for (int it = 0; it < kBf16RefineSteps; ++it) {
+    for (int it = 0; it < steps; ++it) {
       launch_residual_f64w<double>(X, ldx, w.colmap, w.mu, m, v.p, n_eff, w.Coef, w.E64, m,
                                    stream);
       VL_LAUNCH_CHECK();
@@ -382,7 +392,8 @@ int run_var(const VarPlan& v, const VarWs& w, const float* X, int64_t ldx, int p
     const int nb = (int)(nbl < kCheckBlocks ? nbl : kCheckBlocks);
     refine_partial_kernel<<<nb, 256, 0, stream>>>(w.Rres, w.Coef, dz * m, w.scratch);
     VL_LAUNCH_CHECK();
-    refine_check_kernel<<<1, 256, 0, stream>>>(w.scratch, nb, st);
+    refine_check_kernel<<<1, 256, 0, stream>>>(
+        w.scratch, nb, prec == VL_PREC_BF16 ? kRefineTolBf16 : kRefineTolFp32, st);
     VL_LAUNCH_CHECK();
   }
   {

@@ -244,3 +244,30 @@ def test_batch_plan_host_checks(L):
     assert lib.varlingam_batch_create(bad, 1, 1, ctypes.byref(h)) == L.VL_ERR_INVALID_ARG
     assert lib.varlingam_batch_create(ok, 4, 2, ctypes.byref(h)) == L.VL_ERR_INVALID_ARG
     assert lib.varlingam_batch_create(ok, 0, 1, ctypes.byref(h)) == L.VL_ERR_INVALID_ARG
+
+
+def test_certified_order_host_checks(L):
+    """Host-side refusals of approx_order_certified (nothing is enqueued)."""
+    lib = L.lib
+    big = 1 << 30
+    co = lib.approx_order_certified
+    assert lib.approx_order_certified_workspace_bytes(100, 0) == 0
+    assert lib.approx_order_certified_workspace_bytes(100, 4097) == 0
+    assert lib.approx_order_certified_workspace_bytes(1000, 400) >= 8 * 400 * 1000
+    assert co(None, 100, 4, 4, FAKE, 1e-6, FAKE, FAKE, None, None, FAKE, big, FAKE,
+              None) == L.VL_ERR_INVALID_ARG
+    assert co(FAKE, 100, 4, 4, FAKE, -1.0, FAKE, FAKE, None, None, FAKE, big, FAKE,
+              None) == L.VL_ERR_INVALID_ARG
+    assert co(FAKE, 1, 4, 4, FAKE, 1e-6, FAKE, FAKE, None, None, FAKE, big, FAKE,
+              None) == L.VL_ERR_SHAPE
+    assert co(FAKE, 100, 5000, 5000, FAKE, 1e-6, FAKE, FAKE, None, None, FAKE, big, FAKE,
+              None) == L.VL_ERR_SHAPE
+    assert co(FAKE, 100, 4, 3, FAKE, 1e-6, FAKE, FAKE, None, None, FAKE, big, FAKE,
+              None) == L.VL_ERR_INVALID_ARG
+    assert co(FAKE, 100, 4, 4, FAKE, 1e-6, FAKE, FAKE, None, None, FAKE, 64, FAKE,
+              None) == L.VL_ERR_WORKSPACE
+    # precision enum: the refined FP32 mode is accepted, an unknown one refused
+    assert lib.pairwise_stats(FAKE, 100, 4, 4, 3, FAKE, FAKE, FAKE, None, FAKE, 16, FAKE,
+                              None) == L.VL_ERR_WORKSPACE
+    assert lib.pairwise_stats(FAKE, 100, 4, 4, 4, FAKE, FAKE, FAKE, None, FAKE, big, FAKE,
+                              None) == L.VL_ERR_INVALID_ARG

@@ -232,16 +232,18 @@ def test_var_fit_parity(api, dev, wl, seed):
     assert np.max(np.abs(E - oE)) <= 2.0 ** -23 * np.abs(oE).max() + 1e-7
 
 
+@pytest.mark.parametrize("prec", ["bf16", "fp32_refined"])
 @pytest.mark.parametrize("wl,seed", [(synth.SMALL, 1), (synth.MEDIUM, 0), (synth.FINANCE, 0)])
-def test_var_fit_bf16_refined(api, dev, wl, seed):
-    """BF16 Gram matrices + FP64 refinement: after the refinement steps the coefficients are
-    those of the FP64 solve up to the step's contraction; bounded here by 1e-6 relative."""
+def test_var_fit_refined(api, dev, wl, seed, prec):
+    """BF16 or FP32 Gram matrices + FP64 refinement (three steps / one step): the coefficients
+    are those of the FP64 solve up to the last step's contraction; bounded here by 1e-6
+    relative, and E (formed in FP64) within half an ulp like the FP64 products'."""
     inst = synth.make_instance(wl, seed)
     oM, oc, oE = O.fit_var(inst.X_parity, wl.p)
-    M, c, E = [t.cpu().numpy() for t in api.fit_var(_dev(inst.X32, dev), wl.p, "bf16")]
+    M, c, E = [t.cpu().numpy() for t in api.fit_var(_dev(inst.X32, dev), wl.p, prec)]
     eM = np.max(np.abs(M - oM)) / max(1.0, np.abs(oM).max())
     eE = np.max(np.abs(E - oE)) / np.abs(oE).max()
-    print(f"bf16 var fit {wl.name}: M rel err {eM:.1e}, E rel err {eE:.1e}", flush=True)
+    print(f"{prec} var fit {wl.name}: M rel err {eM:.1e}, E rel err {eE:.1e}", flush=True)
     assert eM <= 1e-6
     assert eE <= 1e-6
 
@@ -287,7 +289,7 @@ def test_var_fit_lag_blocks_with_outlying_edge_rows(api, dev, m, p):
     X[-p:] = 30.0 * X[-p:] + rng.normal(0, 5.0, (p, m))
     X32 = X.astype(np.float32)
     oM, oc, oE = O.fit_var(X32.astype(np.float64), p)
-    for prec, tol in (("mixed", 1e-7), ("bf16", 1e-7), ("fp32", 2e-3)):
+    for prec, tol in (("mixed", 1e-7), ("bf16", 1e-7), ("fp32", 2e-3), ("fp32_refined", 1e-6)):
         try:
             M, c, E = [t.cpu().numpy() for t in api.fit_var(_dev(X32, dev), p, prec)]
         except VarLiNGAMError as err:
