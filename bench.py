@@ -56,18 +56,55 @@ def measured_traffic():
     return MEASURED_TRAFFIC.get(kernel_source_digest())
 
 
-def cpu_baseline(E64, cols: int):
-    """The oracle as it stands, on the first `cols` residual columns (all ordered pairs)."""
+def _oracle_rows(args):
+    """Worker of the all-core CPU baseline: rows i0 .. i1 - 1 of the oracle's precompute."""
     from oracle import varlingam as O
-    sub = E64[:, :cols]
+    X, i0, i1 = args
+    return i0, [O.pair_row(X, i) for i in range(i0, i1)]
+
+
+def cpu_baseline(seed: int, cols: int) -> dict:
+    """The oracle as it stands, on the host cores, before anything touches the GPU (the pool
+    is forked): its VAR fit of the workload series, the pairwise precompute of all 400
+    residual columns on every host core (processes over row blocks; bit-identical to the
+    serial oracle), the same precompute on one core for the first `cols` columns, its ordering
+    and its B (normal equations on the residual covariance).  value = all-core precompute
+    rate."""
+    import multiprocessing as mp
+    from oracle import varlingam as O
+    import synth
+    wl = synth.FINANCE
+    X = synth.make_instance(wl, seed).X_parity
     t0 = time.perf_counter()
-    O.pairwise_stats(sub)
-    dt = time.perf_counter() - t0
-    evals = cols * (cols - 1) * sub.shape[0]
-    return {"value": evals / dt, "unit": "sample-evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle pairwise_stats on the first {cols} of {E64.shape[1]} residual "
-                      f"columns ({cols * (cols - 1)} ordered pairs, n_eff={sub.shape[0]}), "
-                      f"{dt:.1f} s, numpy FP64 single thread"}
+    M, _, E = O.fit_var(X, wl.p)
+    t_var = time.perf_counter() - t0
+    Xs = O.standardize_columns(E)
+    n_eff, m = E.shape
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        blocks = pool.map(_oracle_rows, [(Xs, i, min(i + 10, m)) for i in range(0, m, 10)])
+    rows = [r for _, rs in sorted(blocks, key=lambda b: b[0]) for r in rs]
+    _, _, S = O.pairwise_stats(E, rows=rows)
+    t_pre = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.pairwise_stats(E[:, :cols])
+    t_one = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    order, _ = O.approx_order(S)
+    t_ord = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.estimate_B_cov(O.population_cov(E), order, M)
+    t_b = time.perf_counter() - t0
+    evals = m * (m - 1) * n_eff
+    return {"value": evals / t_pre, "unit": "sample-evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"oracle pairwise_stats over all {m} residual columns of the "
+                      f"{wl.name} series ({m * (m - 1)} ordered pairs, n_eff={n_eff}), rows "
+                      f"split over {cores} host processes, {t_pre:.1f} s wall",
+            "single_core": {"value": cols * (cols - 1) * n_eff / t_one, "cores": 1,
+                            "sample": f"the first {cols} columns on one core, {t_one:.1f} s"},
+            "stage_s": {"var_fit": round(t_var, 3), "precompute": round(t_pre, 3),
+                        "ordering": round(t_ord, 3), "estimate_b": round(t_b, 3)}}
 
 
 def time_steps(fitter, X, steps, torch):
@@ -103,6 +140,24 @@ def bench_batched(api, torch, steps: int, seed: int):
             bf.run()
         torch.cuda.synchronize()
         out[f"batched_ms_{prec}"] = (time.perf_counter() - t0) / steps * 1e3
+        # the same fit captured once in a HIP graph and replayed
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            bf.run()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            bf.run()
+        g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            g.replay()
+        torch.cuda.synchronize()
+        out[f"batched_graph_ms_{prec}"] = (time.perf_counter() - t0) / steps * 1e3
+        del g
         if prec == "mixed":
             from paper_2409_05500_amd import _lib
             _lib.profile_enable("*")
@@ -130,6 +185,22 @@ def bench_batched(api, torch, steps: int, seed: int):
     out["batched_sample_evals_per_s_mixed"] = evals / (out["batched_ms_mixed"] / 1e3)
     out["speedup_batched_mixed_vs_looped_fp32"] = out["looped_ms_fp32"] / out["batched_ms_mixed"]
     return out
+
+
+def bench_certified(api, torch, fit, steps):
+    """The certified ordering (near-ties re-decided on FP64 scores) on the fit's residuals and
+    scores, at the default score bound: its time against the plain ordering stage, the rows it
+    recomputes and whether its order differs from the plain one."""
+    E, S0 = fit.E, fit.S
+    order, _, _, nref = api.approx_order_certified(E, S0.clone())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        api.approx_order_certified(E, S0.clone())
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    return {"eps_S": api.CERT_EPS_S, "ms": ms, "rows_refined": nref,
+            "same_order_as_plain": bool(torch.equal(order, fit.order))}
 
 
 def bench_iterative(api, torch, E, stage_ms, steps):
@@ -392,7 +463,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-cols", type=int, default=160)
+    ap.add_argument("--cpu-cols", type=int, default=100,
+                    help="columns of the single-core oracle sample")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-workload section (256 uneven problems)")
     ap.add_argument("--no-backward", action="store_true",
@@ -417,6 +489,12 @@ def main():
         sys.exit(2)
 
     import numpy as np
+    # the oracle's CPU baseline runs first: its worker processes are forked before anything
+    # has initialised the GPU (rank 0, one GPU)
+    cpu = None
+    if not args.only and not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.seed, args.cpu_cols)
+        print("bench: cpu baseline done", file=sys.stderr, flush=True)
     import torch
     import synth
     from paper_2409_05500_amd import api, _lib
@@ -478,11 +556,17 @@ def main():
             stage_ms[st] = round(ms / cnt, 4)
     _lib.profile_enable(None)
 
-    # the plain FP32 form on the same input
+    # the plain FP32 form on the same input, and the FP32 Gram with one FP64 refinement step
+    # (the cheapest form on the FP32 Gram that reaches the mixed mode's accuracy)
     f32 = api.Fitter(n, m, p, "fp32", dev)
     for _ in range(args.warmup):
         f32.run(X)
     fp32_s = time_steps(f32, X, args.steps, torch)
+    f32r = api.Fitter(n, m, p, "fp32_refined", dev)
+    for _ in range(args.warmup):
+        f32r.run(X)
+    fp32r_s = time_steps(f32r, X, args.steps, torch)
+    f32r.check()
 
     # the BF16-Gram form with FP64 refinement, its VAR stages, and its distance from MIXED
     bf = api.Fitter(n, m, p, "bf16", dev)
@@ -501,10 +585,18 @@ def main():
 
     def b_rel(a, b):
         return float((a - b).abs().max() / max(float(b.abs().max()), 1e-2))
-    bf16_dev = {"B0_rel": b_rel(bf.B0, fit.B0), "B_lags_rel": b_rel(bf.B_lags, fit.B_lags),
-                "same_order": bool(torch.equal(bf.order, fit.order))}
+    def dist(o):
+        return {"B0_rel": b_rel(o.B0, fit.B0), "B_lags_rel": b_rel(o.B_lags, fit.B_lags),
+                "same_order": bool(torch.equal(o.order, fit.order))}
+    bf16_dev = dist(bf)
+    modes_vs_mixed = {"fp32": dist(f32), "fp32_refined": dist(f32r), "bf16": bf16_dev}
 
+    # measured issue rates of this part (the roofline denominators' check)
+    rates = api.probe_rates(dev)
     achieved = TRANS_PER_EVAL * evals / k_s
+    # transcendentals the kernel issues per sample-eval: two exp2, and one log per 64 samples
+    # of a lane (the running product of log cosh)
+    issued = (2.0 + 1.0 / 64.0) * evals / k_s
     out = {
         "metric": METRIC,
         "value": evals / step_s,
@@ -523,21 +615,32 @@ def main():
         "roofline": {"kernel": "pairwise_moments_kernel", "bound": "alu",
                      "achieved": achieved / 1e12, "peak": TRANS_PEAK / 1e12,
                      "unit": "Ttrans/s", "frac": achieved / TRANS_PEAK,
-                     "traffic": measured_traffic()},
+                     "traffic": measured_traffic(),
+                     "counting": "algorithmic: 3 transcendentals per sample-eval",
+                     "issued_achieved": issued / 1e12, "issued_frac": issued / TRANS_PEAK,
+                     "peak_measured": rates["exp2_per_s"] / 1e12,
+                     "frac_of_measured": achieved / rates["exp2_per_s"]},
+        "probe_rates": {"exp2_per_s": rates["exp2_per_s"],
+                        "fp32_fma_tflops": rates["fp32_fma_flops"] / 1e12,
+                        "fp64_mfma_tflops": rates["fp64_mfma_flops"] / 1e12},
         "pairwise_kernel_ms": k_s * 1e3,
         "pairwise_kernel_sample_evals_per_s": evals / k_s,
         "sample_evals_per_step": evals,
         "fit_ms_mixed": step_s * 1e3,
         "fit_ms_fp32": fp32_s * 1e3,
+        "fit_ms_fp32_refined": fp32r_s * 1e3,
         "fit_ms_bf16": bf16_s * 1e3,
         "bf16_stage_ms": bf16_stage_ms,
         "bf16_vs_mixed": bf16_dev,
+        "modes_vs_mixed": modes_vs_mixed,
         "stage_ms": stage_ms,
     }
     def progress(msg):
         print(f"bench: {msg}", file=sys.stderr, flush=True)
 
     progress("fit timings done")
+    out["certified_order"] = bench_certified(api, torch, fit, 5)
+    progress("certified ordering done")
     if not args.no_iterative:
         out["iterative"] = bench_iterative(api, torch, fit.E, stage_ms, 3)
     progress("iterative done")
@@ -556,9 +659,8 @@ def main():
     if not args.no_backward:
         out["backward"] = bench_backward(api, _lib, torch, 3, args.seed)
     progress("backward done")
-    if not args.no_cpu_baseline:
-        from oracle import varlingam as O  # noqa: F401  (CPU baseline only)
-        out["cpu_baseline"] = cpu_baseline(fit.E.cpu().numpy().astype(np.float64), args.cpu_cols)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

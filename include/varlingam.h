@@ -414,6 +414,17 @@ void varlingam_batch_destroy(vl_batch* batch);
 void varlingam_profile_enable(const char* stages);
 int varlingam_profile_read(const char* stage, double* total_ms, int64_t* count);
 
+/* ------------------------------------------------------------------------------------- */
+/* Issue-rate probes (diagnostics; the measured denominators of the rooflines): rates[0] =   */
+/* FP32 exp2 per second (the transcendental unit), rates[1] = FP32 FMA flop per second,      */
+/* rates[2] = FP64 MFMA (16x16x4) flop per second, each from a kernel of independent         */
+/* dependency chains filling every CU (8 waves per SIMD), timed with HIP events on `stream`.  */
+/* rates is a HOST pointer (3 doubles); ws a device buffer of                                 */
+/* varlingam_probe_workspace_bytes() bytes.  Synchronises `stream`.                           */
+/* ------------------------------------------------------------------------------------- */
+size_t varlingam_probe_workspace_bytes(void);
+int varlingam_probe_rates(double* rates, void* ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

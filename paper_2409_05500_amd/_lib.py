@@ -81,6 +81,8 @@ SIGNATURES = {
     "varlingam_batch_autotune": (_i32, [_p, _p, _sz, _p, _p]),
     "varlingam_batch_chunk_len": (_i32, [_p]),
     "varlingam_batch_destroy": (None, [_p]),
+    "varlingam_probe_workspace_bytes": (_sz, []),
+    "varlingam_probe_rates": (_i32, [C.POINTER(C.c_double), _p, _sz, _p]),
     "varlingam_profile_enable": (None, [C.c_char_p]),
     "varlingam_profile_read": (_i32, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(_i64)]),
 }

@@ -361,6 +361,17 @@ def prune(X: torch.Tensor, p: int, order: torch.Tensor, B0: torch.Tensor, B_lags
     return B0o, Blo, info
 
 
+def probe_rates(device="cuda:0") -> dict:
+    """Measured issue rates of this GPU (varlingam_probe_rates): FP32 exp2 per second, FP32
+    FMA flop/s and FP64 MFMA flop/s."""
+    dev = torch.device(device)
+    ws = _workspace(lib.varlingam_probe_workspace_bytes(), dev)
+    out = (C.c_double * 3)()
+    check(lib.varlingam_probe_rates(out, ws.data_ptr(), ws.numel(), _stream_ptr(dev)),
+          "varlingam_probe_rates")
+    return {"exp2_per_s": out[0], "fp32_fma_flops": out[1], "fp64_mfma_flops": out[2]}
+
+
 @dataclass
 class FitResult:
     M: torch.Tensor
