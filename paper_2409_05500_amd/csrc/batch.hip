@@ -212,7 +212,6 @@ __device__ inline CholArgs bat_chol_args(const BInst& d, int which, int32_t* st)
   a.ldli = n;
   a.diag0 = ws;
   a.Yb = ws + n;
-  a.Wb = ws + n + nb * kNb * kNb;
   a.st = st;
   return a;
 }

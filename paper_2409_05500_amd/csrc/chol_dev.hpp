@@ -116,15 +116,16 @@ __device__ __attribute__((always_inline)) inline void gemm_f64_block(
 
 // ------------------------------------------------------------------------------------------
 // Fused blocked Cholesky + forward substitution.  Panel width 64; nb = ceil(n / 64) block rows.
-// Per block k the workspace keeps Y_k = L_kk^{-1} and W_k = Y_k^T Y_k = (A_kk^{(k)})^{-1}, the
-// inverse of the diagonal block after the updates of panels < k.  Right-looking step k applies
-// panel k everywhere at once, each workgroup recomputing the panel product it needs:
-//   trailing tile (i, j), k < j <= i:   A_ij -= (A_ik W_k) A_jk^T      (= L_ik L_jk^T)
-//   right-hand tile (i, c), i > k:      R_ic -= (A_ik W_k) R_kc         (= L_ik (L^{-1} R)_kc)
-// and the workgroup of tile (k+1, k+1) goes on to factor and invert it (Y_{k+1}, W_{k+1}), so
-// one launch per panel covers the factorisation and the substitution.  Block row k of the
-// right-hand sides is final after step k - 1; step k + 1 (or the last step) scales it in place:
-//   (L^{-1} R)_kc = Y_k R_kc.
+// Per block k the workspace keeps Y_k = L_kk^{-1} (the inverse factor of the diagonal block after
+// the updates of panels < k; exact zeros above its diagonal).  Right-looking step k applies panel
+// k everywhere at once, each workgroup forming the panel rows it needs, L_ik = A_ik Y_k^T:
+//   trailing tile (i, j), k < j <= i:   A_ij -= L_ik L_jk^T
+//   right-hand tile (i, c), i > k:      R_ic -= L_ik (Y_k R_kc)        (= L_ik (L^{-1} R)_kc)
+// and the workgroup of tile (k+1, k+1) goes on to factor and invert it (Y_{k+1}), so one launch
+// per panel covers the factorisation and the substitution.  The critical chain through the
+// launches is, per step, L = A Y^T, A -= L L^T and the 64 x 64 factor; nothing else (no
+// Y^T Y product, no store beyond Y) sits on it.  Block row k of the right-hand sides is final
+// after step k - 1; step k + 1 (or the last step) scales it in place: (L^{-1} R)_kc = Y_k R_kc.
 // L^{-1} itself is the substitution applied to R = I, whose column tile c stays zero above
 // block row c (those tiles are skipped).
 // ------------------------------------------------------------------------------------------
@@ -132,18 +133,9 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kTL = kLd;  // LDS tile leading dimension (65: rows land on different banks)
 
-// D[r][c] = src[r * ld + c] for r < rows, c < cols; 0 elsewhere
-__device__ inline void tile_load(double (*D)[kTL], const double* __restrict__ src, int64_t ld,
-                                 int rows, int cols) {
-#pragma unroll 4
-  for (int e = threadIdx.x; e < kNb * kNb; e += 256) {
-    const int r = e >> 6, c = e & 63;
-    D[r][c] = (r < rows && c < cols) ? src[(int64_t)r * ld + c] : 0.0;
-  }
-}
-
-// The tile_load mapping into registers (16 values per thread) and back into LDS: the loads can
-// be issued early and stored after a product that still reads the LDS tile.
+// Tiles move global -> registers -> LDS: v[u] = src[r * ld + c] (0 outside rows x cols) for the
+// element e = threadIdx.x + 256 u, r = e / 64, c = e % 64, so all 16 loads of a thread are in
+// flight at once and can be issued before a product that still reads the LDS tile.
 __device__ inline void tile_fetch(double (&v)[16], const double* __restrict__ src, int64_t ld,
                                   int rows, int cols) {
 #pragma unroll
@@ -208,9 +200,91 @@ __device__ inline void acc_each(const f64x4 (&acc)[2][2], F f) {
         f(wi * 32 + x * 16 + (lane >> 4) + 4 * r, wj * 32 + y * 16 + (lane & 15), acc[x][y][r]);
 }
 
-// Scratch doubles of the factorisation: the original diagonal, then per 64-row block Y_k and W_k.
+// L = P Y^T with Y lower-triangular (Y_qp = 0 for p > q), so output column block c needs only
+// k < 16 (c + 1): wave w owns row block w (rows 16 w .. +15) and all four column blocks, 40 MFMAs
+// per wave instead of 64.  Result register r of block c: row 16 w + l / 16 + 4 r, column
+// 16 c + l % 16.  The skipped terms are exact zeros.
+__device__ inline void mm64_tri(const double (*P)[kTL], const double (*Yl)[kTL],
+                                f64x4 (&acc)[4]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int kk = 0; kk < kNb; kk += 4) {
+    const double a = P[16 * w + lr][kk + lk];
+#pragma unroll
+    for (int c = kk / 16; c < 4; ++c)
+      acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Yl[16 * c + lr][kk + lk], acc[c], 0, 0, 0);
+  }
+}
+
+__device__ inline void tri_zero(f64x4 (&acc)[4]) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc[c] = f64x4{0.0, 0.0, 0.0, 0.0};
+}
+
+template <class F>
+__device__ inline void tri_each(const f64x4 (&acc)[4], F f) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) f(16 * w + (lane >> 4) + 4 * r, 16 * c + (lane & 15), acc[c][r]);
+}
+
+// The lower block triangle (row block >= column block) of P P^T: ten 16 x 16 blocks over the
+// four waves as 3, 3, 2, 2 (48 MFMAs per wave at most instead of 64).  Blocks above the
+// diagonal are neither formed nor written: no consumer reads them.
+__device__ inline int lower_blocks(int w, int b, int& bi, int& bj) {
+  // wave 0: (0,0) (1,0) (1,1); wave 1: (2,0) (2,1) (2,2); wave 2: (3,0) (3,1); wave 3: (3,2) (3,3)
+  if (w == 0) {
+    bi = b == 0 ? 0 : 1;
+    bj = b == 2 ? 1 : 0;
+  } else if (w == 1) {
+    bi = 2;
+    bj = b;
+  } else {
+    bi = 3;
+    bj = 2 * (w - 2) + b;
+  }
+  return w < 2 ? 3 : 2;
+}
+
+__device__ inline void mm64_lower(const double (*P)[kTL], f64x4 (&acc)[3]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane & 15, lk = lane >> 4;
+  int bi[3], bj[3];
+  int n = 0;
+#pragma unroll
+  for (int b = 0; b < 3; ++b) n = lower_blocks(w, b, bi[b], bj[b]);
+#pragma unroll 4
+  for (int kk = 0; kk < kNb; kk += 4) {
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      if (b < n) {
+        const double x = P[16 * bi[b] + lr][kk + lk];
+        const double y = P[16 * bj[b] + lr][kk + lk];
+        acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc[b], 0, 0, 0);
+      }
+    }
+  }
+}
+
+// f(slot, row, column) for the (up to 12) result positions a lane holds in mm64_lower
+template <class F>
+__device__ inline void lower_each(F f) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    int bi, bj;
+    const int n = lower_blocks(w, b, bi, bj);
+    if (b < n) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) f(4 * b + r, 16 * bi + (lane >> 4) + 4 * r, 16 * bj + (lane & 15));
+    }
+  }
+}
+
+// Scratch doubles of the factorisation: the original diagonal, then per 64-row block Y_k.
 __host__ __device__ inline int64_t chol_ws_doubles_dev(int64_t n) {
-  return n + 2 * ((n + kNb - 1) / kNb) * kNb * kNb;
+  return n + ((n + kNb - 1) / kNb) * kNb * kNb;
 }
 
 struct CholArgs {
@@ -222,7 +296,6 @@ struct CholArgs {
   int64_t ldli;
   double* diag0;      // n: diagonal before elimination (pivot test)
   double* Yb;         // nb x 64 x 64: Y_k
-  double* Wb;         // nb x 64 x 64: W_k
   int32_t* st;
 };
 
@@ -250,49 +323,57 @@ __host__ __device__ inline StepItems step_items(int64_t nb, int64_t k, int64_t c
   return s;
 }
 
+// Y_b (zeros above the diagonal) to the workspace
+__device__ inline void store_y(const double (*Y)[kTL], const CholArgs& a, int64_t b) {
+  double* Yo = a.Yb + b * kNb * kNb;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int e = threadIdx.x + 256 * u, r = e >> 6, q = e & 63;
+    Yo[e] = q <= r ? Y[r][q] : 0.0;
+  }
+}
+
 // The critical tile's epilogue: S = the updated diagonal block (identity-padded) is factored;
-// Y_b and W_b = Y_b^T Y_b go to the workspace.
+// Y_b goes to the workspace.
 __device__ inline void factor_diag_store(double (*S)[kTL], double (*Y)[kTL], double* buf,
                                          double* D0, const CholArgs& a, int64_t b) {
   const int64_t kb = blk_rows(a.n, b);
   if (threadIdx.x < kNb) D0[threadIdx.x] = threadIdx.x < kb ? a.diag0[b * kNb + threadIdx.x] : 1.0;
   block_factor_inv(S, Y, buf, D0, a.st);
-  double* Yo = a.Yb + b * kNb * kNb;
-  for (int e = threadIdx.x; e < kNb * kNb; e += 256) {
-    const int r = e >> 6, q = e & 63;
-    Yo[e] = q <= r ? Y[r][q] : 0.0;
-  }
-  f64x4 acc[2][2];
-  acc_zero(acc);
-  mm64<true, false>(Y, Y, acc);      // Y has exact zeros above the diagonal
-  double* Wo = a.Wb + b * kNb * kNb;
-  acc_each(acc, [&](int r, int c, double v) { Wo[r * kNb + c] = v; });
+  store_y(Y, a, 0 + b);
 }
 
 // Step 0's diagonal block: the original diagonal is saved for the pivot test, block 0 is
-// factored and inverted (one workgroup).
+// factored and inverted (one workgroup).  All global loads are issued before the first store.
 __device__ __attribute__((always_inline)) inline void chol_prologue_block(const CholArgs& a) {
   __shared__ double S[kNb][kTL];
   __shared__ double Y[kNb][kTL];
   __shared__ double buf[kFactorBuf];
   __shared__ double D0[kNb];
-  for (int64_t i = threadIdx.x; i < a.n; i += 256) a.diag0[i] = a.A[i * a.lda + i];
   const int kb = (int)blk_rows(a.n, 0);
-  for (int e = threadIdx.x; e < kNb * kNb; e += 256) {
-    const int r = e >> 6, q = e & 63;
-    S[r][q] = (r < kb && q < kb) ? a.A[(int64_t)r * a.lda + q] : (r == q ? 1.0 : 0.0);
+  double v[16];
+  tile_fetch(v, a.A, a.lda, kb, kb);
+  for (int64_t i0 = 0; i0 < a.n; i0 += 4 * 256) {
+    double dg[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t i = i0 + threadIdx.x + 256 * u;
+      dg[u] = a.A[(i < a.n ? i : 0) * (a.lda + 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t i = i0 + threadIdx.x + 256 * u;
+      if (i < a.n) a.diag0[i] = dg[u];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int e = threadIdx.x + 256 * u, r = e >> 6, q = e & 63;
+    S[r][q] = (r < kb && q < kb) ? v[u] : (r == q ? 1.0 : 0.0);
   }
   if (threadIdx.x < kNb) D0[threadIdx.x] = threadIdx.x < kb ? a.A[threadIdx.x * (a.lda + 1)] : 1.0;
   block_factor_inv(S, Y, buf, D0, a.st);
-  double* Yo = a.Yb;
-  for (int e = threadIdx.x; e < kNb * kNb; e += 256) {
-    const int r = e >> 6, q = e & 63;
-    Yo[e] = q <= r ? Y[r][q] : 0.0;
-  }
-  f64x4 acc[2][2];
-  acc_zero(acc);
-  mm64<true, false>(Y, Y, acc);
-  acc_each(acc, [&](int r, int c, double v) { a.Wb[r * kNb + c] = v; });
+  store_y(Y, a, 0);
 }
 
 // L^{-1} starts as the identity (the substitution works on it in place): element e of n x n.
@@ -313,12 +394,11 @@ __device__ __attribute__((always_inline)) inline void chol_step_item(const CholA
   const int64_t nb = ceil_div(a.n, (int64_t)kNb);
   const int64_t cr = a.R ? ceil_div(a.nrhs, (int64_t)kNb) : 0;
   const StepItems s = step_items(nb, k, cr, a.Li != nullptr);
-  const int64_t t = nb - 1 - k;
   const double* Ak = a.A + k * kNb;                 // column block k of A
-  const double* Wk = a.Wb + k * kNb * kNb;
+  const double* Yk = a.Yb + k * kNb * kNb;
   f64x4 acc[2][2];
   if (e < s.trail + s.upd_r + s.upd_i) {
-    // row block i of the panel product P = A_ik W_k, into X
+    // L_ik = A_ik Y_k^T for the row block i of this item
     int64_t i, j = -1, c = -1;
     bool inv_side = false;
     if (e < s.trail) {
@@ -337,10 +417,9 @@ __device__ __attribute__((always_inline)) inline void chol_step_item(const CholA
       c = e % (k + 1);
       inv_side = true;
     }
-    (void)t;
     const int64_t ri = blk_rows(a.n, i);
-    // the tile this item updates, and the second operand: A_jk (trailing tile; the diagonal
-    // tiles reuse A_ik) or the right-hand tile of block row k
+    // the tile this item updates, and the second operand: A_jk (off-diagonal trailing tile) or
+    // the right-hand tile of block row k
     double* out;
     const double* src2 = nullptr;
     int64_t ldo, ld2 = 0, rows2 = kNb, cols;
@@ -367,47 +446,78 @@ __device__ __attribute__((always_inline)) inline void chol_step_item(const CholA
       ld2 = a.ldli;
     }
     const int64_t cols2 = j >= 0 ? kNb : cols;
-    // all global loads of the item are issued before the first product
+    const bool diag = j == i;
+    // all global loads of the item are issued before the first product; cur follows the layout
+    // of the item's last product (lower blocks for a diagonal tile)
     double cur[16], nxt[16];
     {
-      int u = 0;
-      acc_each(acc, [&](int r, int q, double) {
-        const bool ok = r < ri && q < cols;
-        cur[u++] = out[(int64_t)(ok ? r : 0) * ldo + (ok ? q : 0)];
-      });
+      double pa[16], py[16];
+      if (diag) {
+        lower_each([&](int u, int r, int q) {
+          const bool ok = r < ri && q < cols;
+          cur[u] = out[(int64_t)(ok ? r : 0) * ldo + (ok ? q : 0)];
+        });
+      } else {
+        int u = 0;
+        acc_each(acc, [&](int r, int q, double) {
+          const bool ok = r < ri && q < cols;
+          cur[u++] = out[(int64_t)(ok ? r : 0) * ldo + (ok ? q : 0)];
+        });
+      }
+      tile_fetch(pa, Ak + i * kNb * a.lda, a.lda, (int)ri, kNb);
+      tile_fetch(py, Yk, kNb, kNb, kNb);
+      if (src2) tile_fetch(nxt, src2, ld2, (int)rows2, (int)cols2);
+      tile_put(X, pa);
+      tile_put(Z, py);
     }
-    if (src2) tile_fetch(nxt, src2, ld2, (int)rows2, (int)cols2);
-    tile_load(X, Ak + i * kNb * a.lda, a.lda, (int)ri, kNb);
-    tile_load(Z, Wk, kNb, kNb, kNb);
     __syncthreads();
-    acc_zero(acc);
-    mm64<false, false>(X, Z, acc);
+    f64x4 l1[4];
+    tri_zero(l1);
+    mm64_tri(X, Z, l1);                              // L_ik
     __syncthreads();
-    if (j == i) {
-      // diagonal tile: P into Z, A_ik stays in X as the second operand (transposed)
-      acc_each(acc, [&](int r, int q, double v) { Z[r][q] = v; });
+    if (diag) {
+      // L_ik L_ik^T, lower blocks only
+      tri_each(l1, [&](int r, int q, double v) { X[r][q] = v; });
       __syncthreads();
-      acc_zero(acc);
-      mm64<false, true>(Z, X, acc);
-    } else {
-      acc_each(acc, [&](int r, int q, double v) { X[r][q] = v; });
-      tile_put(Z, nxt);
-      __syncthreads();
-      acc_zero(acc);
-      if (j >= 0) mm64<false, true>(X, Z, acc);
-      else mm64<false, false>(X, Z, acc);
-    }
-    if (j == k + 1 && i == k + 1) {
-      // the critical tile: updated block into X (identity-padded), then factor and invert
-      __syncthreads();
-      int u = 0;
-      acc_each(acc, [&](int r, int q, double v) {
-        const double o = cur[u++];
-        X[r][q] = (r < ri && q < ri) ? o - v : (r == q ? 1.0 : 0.0);
+      f64x4 lo[3];
+#pragma unroll
+      for (int u = 0; u < 3; ++u) lo[u] = f64x4{0.0, 0.0, 0.0, 0.0};
+      mm64_lower(X, lo);
+      if (i == k + 1) {
+        // the critical tile: updated block into X (identity-padded), then factor and invert
+        __syncthreads();
+        lower_each([&](int u, int r, int q) {
+          X[r][q] = (r < ri && q < ri) ? cur[u] - lo[u >> 2][u & 3] : (r == q ? 1.0 : 0.0);
+        });
+        factor_diag_store(X, Z, buf, D0, a, k + 1);
+        return;
+      }
+      lower_each([&](int u, int r, int q) {
+        if (r < ri && q < cols) out[(int64_t)r * ldo + q] = cur[u] - lo[u >> 2][u & 3];
       });
-      factor_diag_store(X, Z, buf, D0, a, k + 1);
       return;
     }
+    tile_put(X, nxt);
+    __syncthreads();
+    if (j >= 0) {
+      f64x4 l2[4];
+      tri_zero(l2);
+      mm64_tri(X, Z, l2);                            // L_jk
+      __syncthreads();
+      tri_each(l1, [&](int r, int q, double v) { X[r][q] = v; });
+      tri_each(l2, [&](int r, int q, double v) { Z[r][q] = v; });
+    } else {
+      f64x4 l2[2][2];
+      acc_zero(l2);
+      mm64<false, false>(Z, X, l2);                  // Y_k R_kc
+      __syncthreads();
+      tri_each(l1, [&](int r, int q, double v) { X[r][q] = v; });
+      acc_each(l2, [&](int r, int q, double v) { Z[r][q] = v; });
+    }
+    __syncthreads();
+    acc_zero(acc);
+    if (j >= 0) mm64<false, true>(X, Z, acc);
+    else mm64<false, false>(X, Z, acc);
     int u = 0;
     acc_each(acc, [&](int r, int q, double v) {
       const double o = cur[u++];
@@ -447,8 +557,13 @@ __device__ __attribute__((always_inline)) inline void chol_step_item(const CholA
     cols = blk_rows(a.n, c);
   }
   const int64_t rf = blk_rows(a.n, f);
-  tile_load(X, a.Yb + f * kNb * kNb, kNb, kNb, kNb);
-  tile_load(Z, tile, ld, (int)rf, (int)cols);
+  {
+    double py[16], pt[16];
+    tile_fetch(py, a.Yb + f * kNb * kNb, kNb, kNb, kNb);
+    tile_fetch(pt, tile, ld, (int)rf, (int)cols);
+    tile_put(X, py);
+    tile_put(Z, pt);
+  }
   __syncthreads();
   acc_zero(acc);
   mm64<false, false>(X, Z, acc);

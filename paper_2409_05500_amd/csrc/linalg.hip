@@ -60,7 +60,6 @@ int chol_solve_lower(double* A, int64_t n, int64_t lda, double* R, int64_t nrhs,
   a.ldli = ldli;
   a.diag0 = ws;
   a.Yb = ws + n;
-  a.Wb = ws + n + nb * kNb * kNb;
   a.st = st;
   const int64_t cr = a.R ? ceil_div(nrhs, (int64_t)kNb) : 0;
   const unsigned init = Linv ? (unsigned)ceil_div(n * n, (int64_t)256) : 0u;

@@ -15,17 +15,36 @@ constexpr int kNb = 64;  // panel width
 // Diagonal block of the blocked Cholesky (kb <= 64; rows/columns >= kb act as identity): its
 // factor L11 and the inverse L11^{-1}.  A pivot d is rejected (VL_ERR_SINGULAR) unless
 // d > kPivotRel * diag0 (the diagonal entry before any elimination), i.e. unless the leading
-// block is better conditioned than ~1e11; a rejected pivot is replaced by 1 so that no NaN
-// spreads.  1/sqrt(d) is v_rsq_f64 refined by two Newton steps.
+// block is better conditioned than ~1e11; a rejected pivot is raised to that floor (to 1 when
+// diag0 itself is not a positive finite number), so a non-positive pivot spreads no NaN.  The
+// floor is one v_max_f64 on the pivot chain (maxNum: a NaN pivot takes the floor too); the test
+// that raises the status runs beside the chain.
 // ------------------------------------------------------------------------------------------
 constexpr double kPivotRel = 1e-11;
 constexpr int kLd = kNb + 1;
 
-__device__ inline double rsqrt_f64(double d) {
-  double r = __builtin_amdgcn_rsq(d);
-  r = r * fma(-0.5 * d, r * r, 1.5);
-  r = r * fma(-0.5 * d, r * r, 1.5);
-  return r;
+// sqrt(d) and 1/(2 sqrt(d)) from v_rsq_f64 by two coupled Goldschmidt steps
+// (g -> sqrt(d), h -> 1/(2 sqrt(d)); each step r = 1/2 - g h, g += g r, h += h r, the error
+// squaring per step): five dependent operations after the seed, one fewer than two Newton
+// steps on 1/sqrt(d).
+struct SqrtPair {
+  double g, h;
+};
+__device__ __attribute__((always_inline)) inline SqrtPair sqrt_pair_f64(double d) {
+  const double y = __builtin_amdgcn_rsq(d);
+  double g = d * y, h = 0.5 * y;
+  double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  return {g, h};
+}
+
+// the pivot floor of a row whose diagonal before elimination is d0
+__device__ __attribute__((always_inline)) inline double pivot_floor(double d0) {
+  return (d0 > 0.0 && d0 < INFINITY) ? kPivotRel * d0 : 1.0;
 }
 
 
@@ -55,16 +74,18 @@ __device__ __attribute__((always_inline)) inline void leaf_update(double (&a)[kL
 
 template <int C, int... Qs>
 __device__ __attribute__((always_inline)) inline void leaf_column(
-    std::integer_sequence<int, Qs...>, double (&a)[kLeaf], int r, double d0, double& isd_own,
-    bool& bad_any) {
-  double d = row_bcast<C>(a[C]);
-  const bool bad = !(d > kPivotRel * row_bcast<C>(d0)) || !isfinite(d);
-  bad_any |= bad;
-  if (bad) d = 1.0;
-  const double isd = rsqrt_f64(d);
-  const double l = (r == C ? d : a[C]) * isd;
+    std::integer_sequence<int, Qs...>, double (&a)[kLeaf], int r, double floor_own,
+    double& isd_own, bool& bad_any) {
+  const double d_raw = row_bcast<C>(a[C]);
+  const double fl = row_bcast<C>(floor_own);
+  bad_any |= !(d_raw > fl) || !isfinite(d_raw);
+  const double d = __builtin_fmax(d_raw, fl);
+  // on lane C, a_CC equals the pivot unless it was rejected (then the status is raised and the
+  // leaf's values only need to stay finite)
+  const SqrtPair sp = sqrt_pair_f64(d);
+  const double l = (2.0 * a[C]) * sp.h;
   a[C] = l;
-  if (r == C) isd_own = isd;
+  if (r == C) isd_own = 2.0 * sp.h;
   (leaf_update<C, Qs>(a, l), ...);
 }
 
@@ -90,9 +111,10 @@ __device__ __attribute__((always_inline)) inline void leaf_inverse_row(
 
 template <int... Cs>
 __device__ __attribute__((always_inline)) inline void leaf_factor(
-    std::integer_sequence<int, Cs...>, double (&a)[kLeaf], int r, double d0, double& isd_own,
-    bool& bad_any) {
-  (leaf_column<Cs>(std::make_integer_sequence<int, kLeaf>{}, a, r, d0, isd_own, bad_any), ...);
+    std::integer_sequence<int, Cs...>, double (&a)[kLeaf], int r, double floor_own,
+    double& isd_own, bool& bad_any) {
+  (leaf_column<Cs>(std::make_integer_sequence<int, kLeaf>{}, a, r, floor_own, isd_own, bad_any),
+   ...);
 }
 
 template <int... Rs>
@@ -112,9 +134,9 @@ __device__ __attribute__((always_inline)) inline void leaf_factor_inv(double (*S
   double a[kLeaf];
 #pragma unroll
   for (int q = 0; q < kLeaf; ++q) a[q] = S[b + r][b + q];
-  const double d0 = D0[b + r];
+  const double floor_own = pivot_floor(D0[b + r]);
   double isd_own = 1.0;
-  leaf_factor(std::make_integer_sequence<int, kLeaf>{}, a, r, d0, isd_own, bad_any);
+  leaf_factor(std::make_integer_sequence<int, kLeaf>{}, a, r, floor_own, isd_own, bad_any);
   double y[kLeaf];
   leaf_inverse(std::make_integer_sequence<int, kLeaf>{}, y, a, r, isd_own);
   if (lane < kLeaf) {
