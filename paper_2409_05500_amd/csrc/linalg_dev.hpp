@@ -172,6 +172,20 @@ __device__ inline void blk16_each(const f64x4_t& acc, F f) {
   for (int r = 0; r < 4; ++r) f((lane >> 4) + 4 * r, lane & 15, acc[r]);
 }
 
+// Block (t, u), u < t, of L^{-1} below the diagonal: Y_tu = -Y_tt sum_{u <= v < t} L_tv Y_vu.
+// One wave; T is 16 x 16 doubles of LDS scratch of its own.
+__device__ __attribute__((always_inline)) inline void inv_block(double (*S)[kLd], double (*Y)[kLd],
+                                                                double* T, int t, int u) {
+  f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
+  for (int v = u; v < t; ++v)
+    mfma_blk16<false>(&S[t * kLeaf][v * kLeaf], kLd, &Y[v * kLeaf][u * kLeaf], kLd, acc);
+  blk16_each(acc, [&](int i, int j, double v) { T[i * kLeaf + j] = v; });
+  // the same wave reads its block back (LDS accesses of a wave complete in order)
+  f64x4_t acc2 = {0.0, 0.0, 0.0, 0.0};
+  mfma_blk16<false>(&Y[t * kLeaf][t * kLeaf], kLd, T, kLeaf, acc2);
+  blk16_each(acc2, [&](int i, int j, double v) { Y[t * kLeaf + i][u * kLeaf + j] = -v; });
+}
+
 // Factor and invert the 64 x 64 block already in S (LDS; rows / columns >= kb hold the identity)
 // with D0 (LDS) the diagonal before any elimination.  On return the lower triangle of S holds
 // L11 and Y holds L11^{-1} (strict upper triangle zero); buf is kFactorBuf doubles of LDS
@@ -180,8 +194,9 @@ __device__ inline void blk16_each(const f64x4_t& acc, F f) {
 //   leaf s (wave 0):            L_ss and L_ss^{-1}
 //   panel (wave per block row):  L_is = A_is L_ss^{-T} for the block rows below the leaf
 //   trailing (wave per block):   A_ij -= L_is L_js^T  (blocks on and below the diagonal)
-// then the blocks of L^{-1} below the diagonal, block row t after block row t - 1, one wave per
-// block:  Y_tu = -Y_tt sum_{u <= v < t} L_tv Y_vu.
+// Row t of L^{-1} below the diagonal (blocks Y_tu, u < t) needs only leaves <= t and panels
+// < t, so waves 1.. compute it while wave 0 factors leaf t + 1; the last row follows the last
+// leaf.
 constexpr int kFactorBuf = 3 * kLeaf * kLeaf;
 
 __device__ __attribute__((always_inline)) inline void block_factor_inv(double (*S)[kLd],
@@ -197,6 +212,7 @@ __device__ __attribute__((always_inline)) inline void block_factor_inv(double (*
   for (int sb = 0; sb < kB; ++sb) {
     const int b = sb * kLeaf;
     if (w == 0) leaf_factor_inv(S, Y, D0, b, bad_any);
+    else if (w < sb) inv_block(S, Y, buf + (w - 1) * kLeaf * kLeaf, sb - 1, w - 1);
     __syncthreads();
     if (sb == kB - 1) break;
     // panel: wave w takes block row sb + 1 + w (reads and writes only its own block)
@@ -220,22 +236,9 @@ __device__ __attribute__((always_inline)) inline void block_factor_inv(double (*
     }
     __syncthreads();
   }
-  // blocks of L^{-1} below the diagonal; wave u computes block (t, u), u < t
-  for (int t = 1; t < kB; ++t) {
-    if (w < t) {
-      const int u = w;
-      f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
-      for (int v = u; v < t; ++v)
-        mfma_blk16<false>(&S[t * kLeaf][v * kLeaf], kLd, &Y[v * kLeaf][u * kLeaf], kLd, acc);
-      double* T = buf + u * kLeaf * kLeaf;
-      blk16_each(acc, [&](int i, int j, double v) { T[i * kLeaf + j] = v; });
-      // the same wave reads its block back (LDS accesses of a wave complete in order)
-      f64x4_t acc2 = {0.0, 0.0, 0.0, 0.0};
-      mfma_blk16<false>(&Y[t * kLeaf][t * kLeaf], kLd, T, kLeaf, acc2);
-      blk16_each(acc2, [&](int i, int j, double v) { Y[t * kLeaf + i][u * kLeaf + j] = -v; });
-    }
-    __syncthreads();
-  }
+  // the last row of L^{-1}: blocks (kB - 1, u), one wave each
+  if (w < kB - 1) inv_block(S, Y, buf + w * kLeaf * kLeaf, kB - 1, w);
+  __syncthreads();
   if (bad_any) raise_status(st, VL_ERR_SINGULAR);
 }
 
