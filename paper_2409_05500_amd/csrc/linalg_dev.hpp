@@ -190,13 +190,14 @@ __device__ __attribute__((always_inline)) inline void inv_block(double (*S)[kLd]
 // with D0 (LDS) the diagonal before any elimination.  On return the lower triangle of S holds
 // L11 and Y holds L11^{-1} (strict upper triangle zero); buf is kFactorBuf doubles of LDS
 // scratch.  Raises VL_ERR_SINGULAR on a rejected pivot.  Starts and ends with a workgroup
-// barrier.  Blocked by 16-column leaves (right-looking), 16 x 16 block products on MFMA:
-//   leaf s (wave 0):            L_ss and L_ss^{-1}
-//   panel (wave per block row):  L_is = A_is L_ss^{-T} for the block rows below the leaf
-//   trailing (wave per block):   A_ij -= L_is L_js^T  (blocks on and below the diagonal)
-// Row t of L^{-1} below the diagonal (blocks Y_tu, u < t) needs only leaves <= t and panels
-// < t, so waves 1.. compute it while wave 0 factors leaf t + 1; the last row follows the last
-// leaf.
+// barrier.  Blocked by 16-column leaves (right-looking), 16 x 16 block products on MFMA; after
+// leaf s:
+//   panel (wave per block row):  L_is = A_is L_ss^{-T} for the block rows i > s
+//   then wave 0 alone updates the next diagonal block, A_{s+1,s+1} -= L_{s+1,s} L_{s+1,s}^T,
+//   and factors leaf s + 1 at once, while waves 1.. apply the rest of the trailing update
+//   (A_ij -= L_is L_js^T, s < j <= i, (i, j) != (s+1, s+1)) and row s of L^{-1} below the
+//   diagonal, Y_su = -Y_ss sum_{u <= v < s} L_sv Y_vu (it needs only leaves <= s and panels
+//   < s).  The last row of L^{-1} follows the last leaf.
 constexpr int kFactorBuf = 3 * kLeaf * kLeaf;
 
 __device__ __attribute__((always_inline)) inline void block_factor_inv(double (*S)[kLd],
@@ -209,12 +210,10 @@ __device__ __attribute__((always_inline)) inline void block_factor_inv(double (*
   for (int e = tid; e < kNb * kNb; e += 256) Y[e >> 6][e & 63] = 0.0;
   __syncthreads();
   bool bad_any = false;
-  for (int sb = 0; sb < kB; ++sb) {
+  if (w == 0) leaf_factor_inv(S, Y, D0, 0, bad_any);
+  __syncthreads();
+  for (int sb = 0; sb < kB - 1; ++sb) {
     const int b = sb * kLeaf;
-    if (w == 0) leaf_factor_inv(S, Y, D0, b, bad_any);
-    else if (w < sb) inv_block(S, Y, buf + (w - 1) * kLeaf * kLeaf, sb - 1, w - 1);
-    __syncthreads();
-    if (sb == kB - 1) break;
     // panel: wave w takes block row sb + 1 + w (reads and writes only its own block)
     if (sb + 1 + w < kB) {
       const int i0 = (sb + 1 + w) * kLeaf;
@@ -223,16 +222,31 @@ __device__ __attribute__((always_inline)) inline void block_factor_inv(double (*
       blk16_each(acc, [&](int i, int j, double v) { S[i0 + i][b + j] = v; });
     }
     __syncthreads();
-    // trailing blocks (i, j), sb < j <= i < kB
-    const int t = kB - 1 - sb, nblk = t * (t + 1) / 2;
-    for (int e = w; e < nblk; e += 4) {
-      int ii = 0;
-      while ((ii + 1) * (ii + 2) / 2 <= e) ++ii;
-      const int jj = e - ii * (ii + 1) / 2;
-      const int i0 = (sb + 1 + ii) * kLeaf, j0 = (sb + 1 + jj) * kLeaf;
+    if (w == 0) {
+      const int d0 = b + kLeaf;
       f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
-      mfma_blk16<true>(&S[i0][b], kLd, &S[j0][b], kLd, acc);
-      blk16_each(acc, [&](int i, int j, double v) { S[i0 + i][j0 + j] -= v; });
+      mfma_blk16<true>(&S[d0][b], kLd, &S[d0][b], kLd, acc);
+      blk16_each(acc, [&](int i, int j, double v) { S[d0 + i][d0 + j] -= v; });
+      // the same wave reads the block back (LDS accesses of a wave complete in order)
+      leaf_factor_inv(S, Y, D0, d0, bad_any);
+    } else {
+      // tasks: the trailing blocks (i, j), sb < j <= i < kB, but (sb+1, sb+1), then the blocks
+      // (sb, u), u < sb, of L^{-1}; round-robin over waves 1..3
+      const int t = kB - 1 - sb, ntrail = t * (t + 1) / 2 - 1;
+      for (int e = w - 1; e < ntrail + sb; e += 3) {
+        if (e < ntrail) {
+          const int f = e + 1;                   // skip block 0 = (sb+1, sb+1)
+          int ii = 0;
+          while ((ii + 1) * (ii + 2) / 2 <= f) ++ii;
+          const int jj = f - ii * (ii + 1) / 2;
+          const int i0 = (sb + 1 + ii) * kLeaf, j0 = (sb + 1 + jj) * kLeaf;
+          f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
+          mfma_blk16<true>(&S[i0][b], kLd, &S[j0][b], kLd, acc);
+          blk16_each(acc, [&](int i, int j, double v) { S[i0 + i][j0 + j] -= v; });
+        } else {
+          inv_block(S, Y, buf + (w - 1) * kLeaf * kLeaf, sb, e - ntrail);
+        }
+      }
     }
     __syncthreads();
   }
