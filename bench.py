@@ -132,6 +132,10 @@ def bench_batched(api, torch, steps: int, seed: int):
         bf = api.BatchFitter(shapes, 1, prec, dev)
         bf.load([i.X32 for i in insts])
         out[f"chunk_len_{prec}"] = bf.autotune()
+        hist = {}
+        for c in bf.chunk_lens():
+            hist[str(c)] = hist.get(str(c), 0) + 1
+        out[f"chunk_len_histogram_{prec}"] = hist
         for _ in range(2):
             bf.run()
         torch.cuda.synchronize()

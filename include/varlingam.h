@@ -367,9 +367,17 @@ int varlingam_edge_frequency(const int32_t* orders, const double* B0s, const dou
 /* caller may capture it in a HIP graph and replay it after refilling the X buffers.        */
 /* dev_status has one word per problem (VL_OK or that problem's first data-dependent error); */
 /* an error in one problem does not stop the others.                                        */
-/* varlingam_batch_autotune() times the candidate sample-chunk lengths of the pairwise      */
-/* stage with full fits on the bound data, keeps the fastest (cached per batch shape and    */
-/* precision for the process) and rebinds.                                                  */
+/* varlingam_batch_autotune() picks the sample-chunk length of the pairwise stage per      */
+/* bucket of problems (m <= 32, 64, 128, 256 times n - p <= 1024, 2048, 4096, more), timing */
+/* whole fits on the bound data: first the fastest length common to all buckets, then one  */
+/* pass of coordinate descent over the buckets by decreasing m^2 (n - p) work (a change is  */
+/* kept if the fit gets at least 1% faster); then it rebinds.  Choices are cached per       */
+/* device, precision and bucket in the process and in a text file: $VL_TUNE_CACHE (empty:  */
+/* no file), else $XDG_CACHE_HOME/varlingam/batch_tune.txt, else                            */
+/* $HOME/.cache/varlingam/batch_tune.txt; buckets found there are not timed again.          */
+/* Calls on one batch must not overlap.  varlingam_batch_chunk_len() returns the length of  */
+/* the bucket with the most problems, varlingam_batch_chunk_len_of() that of one problem    */
+/* (0 for a bad index).                                                                     */
 /* Host errors: VL_ERR_SHAPE for a problem outside the limits, VL_ERR_INVALID_ARG for null  */
 /* pointers, a bad precision or a workspace that is not the bound one.                      */
 /* ------------------------------------------------------------------------------------- */
@@ -397,6 +405,7 @@ int varlingam_fit_batched(const vl_batch* batch, void* ws, int32_t* dev_status, 
 int varlingam_batch_autotune(vl_batch* batch, void* ws, size_t ws_bytes, int32_t* dev_status,
                              void* stream);
 int varlingam_batch_chunk_len(const vl_batch* batch);
+int varlingam_batch_chunk_len_of(const vl_batch* batch, int problem);
 void varlingam_batch_destroy(vl_batch* batch);
 
 /* ------------------------------------------------------------------------------------- */

@@ -80,6 +80,7 @@ SIGNATURES = {
     "varlingam_fit_batched": (_i32, [_p, _p, _p, _p]),
     "varlingam_batch_autotune": (_i32, [_p, _p, _sz, _p, _p]),
     "varlingam_batch_chunk_len": (_i32, [_p]),
+    "varlingam_batch_chunk_len_of": (_i32, [_p, _i32]),
     "varlingam_batch_destroy": (None, [_p]),
     "varlingam_probe_workspace_bytes": (_sz, []),
     "varlingam_probe_rates": (_i32, [C.POINTER(C.c_double), _p, _sz, _p]),

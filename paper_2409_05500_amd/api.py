@@ -521,7 +521,9 @@ class BatchFitter:
                                         _stream_ptr(self.dev)), "varlingam_fit_batched")
 
     def autotune(self) -> int:
-        """Time the pairwise chunk-length candidates on the loaded data; keep the fastest."""
+        """Choose the pairwise chunk length per (m, n) bucket by timing whole fits on the loaded
+        data (cached per device and bucket, also on disk); returns the length of the bucket
+        with the most problems."""
         check(lib.varlingam_batch_autotune(self._h, self.ws.data_ptr(), self.ws.numel(),
                                            self.status.data_ptr(), _stream_ptr(self.dev)),
               "varlingam_batch_autotune")
@@ -530,6 +532,10 @@ class BatchFitter:
     @property
     def chunk_len(self) -> int:
         return lib.varlingam_batch_chunk_len(self._h)
+
+    def chunk_lens(self) -> list:
+        """The pairwise chunk length of every problem."""
+        return [lib.varlingam_batch_chunk_len_of(self._h, b) for b in range(len(self.X))]
 
     def check(self) -> list:
         """Per-problem status codes (0 = ok); synchronises."""

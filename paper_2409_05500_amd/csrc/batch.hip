@@ -13,6 +13,11 @@
 //
 // The Gram tiles here run over all samples in one block (no split-K; the batch supplies the
 // parallelism), so results differ from the single-problem path by summation order only.
+#include <stdio.h>
+#include <stdlib.h>
+#include <sys/stat.h>
+#include <unistd.h>
+
 #include <algorithm>
 #include <map>
 #include <mutex>
@@ -414,6 +419,17 @@ using namespace vl;
 namespace {
 
 constexpr int kChunkCandidates[] = {512, 1024, 2048, 4096, 8192};
+constexpr int kNumCand = sizeof(kChunkCandidates) / sizeof(int);
+
+// Autotune buckets: 4 classes of m times 4 classes of n - p; every problem of a bucket takes
+// the bucket's sample-chunk length for the pairwise stage.
+constexpr int kNumBuckets = 16;
+int bucket_of(const vl_instance& in) {
+  const int64_t m = in.m, ne = in.n - in.p;
+  const int mb = m <= 32 ? 0 : m <= 64 ? 1 : m <= 128 ? 2 : 3;
+  const int nb = ne <= 1024 ? 0 : ne <= 2048 ? 1 : ne <= 4096 ? 2 : 3;
+  return mb * 4 + nb;
+}
 
 struct InstLayout {
   size_t off = 0;                 // byte offset of this problem's slice in the workspace
@@ -502,8 +518,8 @@ struct vl_batch {
   std::vector<vl_instance> inst;
   int count = 0;
   int prec = VL_PREC_MIXED;
-  int chunk = 2048;
-  size_t ws_bytes = 0;       // enough for every chunk candidate
+  int chunk[kNumBuckets];    // sample-chunk length per autotune bucket
+  size_t ws_bytes = 0;       // enough for any mix of chunk candidates
   // current layout
   std::vector<InstLayout> lay;
   int64_t total[kNumMaps] = {};
@@ -522,7 +538,7 @@ size_t build_layout(vl_batch* B) {
   for (int k = 0; k < kNumMaps; ++k) {
     int64_t tot = 0;
     for (int b = 0; b < n; ++b) {
-      if (k == 0) B->lay[b] = layout_for(B->inst[b], B->chunk);
+      if (k == 0) B->lay[b] = layout_for(B->inst[b], B->chunk[bucket_of(B->inst[b])]);
       tot += blocks_for(k, B->inst[b], B->lay[b]);
     }
     B->total[k] = tot;
@@ -539,6 +555,33 @@ size_t build_layout(vl_batch* B) {
   for (int b = 0; b < n; ++b) {
     B->lay[b].off = used;
     used += carve_inst(B->inst[b], B->lay[b], nullptr, nullptr);
+  }
+  return used;
+}
+
+// Workspace bound over every mix of per-bucket chunk lengths: each problem's table blocks and
+// slice at its largest candidate.
+size_t layout_bound(const vl_batch* B) {
+  const int n = B->count;
+  size_t used = round_up((int64_t)(n * sizeof(BInst)), 256);
+  for (int k = 0; k < kNumMaps; ++k) {
+    int64_t tot = 0;
+    for (int b = 0; b < n; ++b) {
+      int64_t mx = 0;
+      for (int c : kChunkCandidates)
+        mx = std::max(mx, blocks_for(k, B->inst[b], layout_for(B->inst[b], c)));
+      tot += mx;
+    }
+    used += round_up((int64_t)((tot + 8) * sizeof(int32_t)), 256);
+    used += round_up((int64_t)(n * sizeof(int64_t)), 256);
+  }
+  for (int b = 0; b < n; ++b)
+    used += round_up(B->inst[b].m * (B->inst[b].p + 1) * (int64_t)sizeof(int64_t), 256);
+  for (int b = 0; b < n; ++b) {
+    size_t mx = 0;
+    for (int c : kChunkCandidates)
+      mx = std::max(mx, carve_inst(B->inst[b], layout_for(B->inst[b], c), nullptr, nullptr));
+    used += mx;
   }
   return used;
 }
@@ -693,18 +736,88 @@ int launch_fit(const vl_batch* B, void* ws, int32_t* st, hipStream_t s) {
   return VL_OK;
 }
 
+// Autotune cache: per device and precision, the chunk length chosen for each bucket.  Kept in
+// the process and in a text file (one "key chunk" line per bucket), read before tuning and
+// rewritten after it through a temporary file and a rename.  The file is
+// $VL_TUNE_CACHE if that is set (an empty value turns the file off), else
+// $XDG_CACHE_HOME/varlingam/batch_tune.txt, else $HOME/.cache/varlingam/batch_tune.txt.
+// File errors only cost a re-tune.
 std::mutex g_tune_mu;
 std::map<std::string, int> g_tune_cache;
+bool g_tune_loaded = false;
 
-std::string tune_key(const vl_batch* B) {
-  std::vector<std::string> parts;
-  for (const auto& in : B->inst)
-    parts.push_back(std::to_string(in.m) + "x" + std::to_string(in.n - in.p) + "p" +
-                    std::to_string(in.p));
-  std::sort(parts.begin(), parts.end());
-  std::string k = std::to_string(B->prec);
-  for (const auto& p : parts) k += "," + p;
-  return k;
+std::string tune_file() {
+  if (const char* e = getenv("VL_TUNE_CACHE")) return std::string(e);
+  std::string dir;
+  if (const char* x = getenv("XDG_CACHE_HOME"); x && *x) dir = x;
+  else if (const char* h = getenv("HOME"); h && *h) dir = std::string(h) + "/.cache";
+  else return std::string();
+  return dir + "/varlingam/batch_tune.txt";
+}
+
+void tune_read(const std::string& path, std::map<std::string, int>& into) {
+  if (path.empty()) return;
+  FILE* f = fopen(path.c_str(), "r");
+  if (!f) return;
+  char key[256];
+  int v = 0;
+  while (fscanf(f, "%255s %d", key, &v) == 2)
+    for (int c : kChunkCandidates)
+      if (v == c) into[key] = v;
+  fclose(f);
+}
+
+void tune_write(const std::string& path, const std::map<std::string, int>& entries) {
+  if (path.empty()) return;
+  const size_t slash = path.rfind('/');
+  if (slash != std::string::npos && slash > 0) {
+    // create the directory chain (the cache's own folder and its parent at most)
+    const std::string dir = path.substr(0, slash);
+    const size_t up = dir.rfind('/');
+    if (up != std::string::npos && up > 0) mkdir(dir.substr(0, up).c_str(), 0755);
+    mkdir(dir.c_str(), 0755);
+  }
+  std::map<std::string, int> all;
+  tune_read(path, all);
+  for (const auto& kv : entries) all[kv.first] = kv.second;
+  const std::string tmp = path + ".tmp." + std::to_string((long)getpid());
+  FILE* f = fopen(tmp.c_str(), "w");
+  if (!f) return;
+  bool ok = true;
+  for (const auto& kv : all) ok = ok && fprintf(f, "%s %d\n", kv.first.c_str(), kv.second) > 0;
+  ok = (fclose(f) == 0) && ok;
+  if (!ok || rename(tmp.c_str(), path.c_str()) != 0) remove(tmp.c_str());
+}
+
+std::string device_tag() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return "unknown";
+  std::string arch = prop.gcnArchName;
+  for (char& ch : arch)
+    if (ch == ' ' || ch == ':') ch = '_';
+  return arch + "-cu" + std::to_string(prop.multiProcessorCount);
+}
+
+std::string bucket_key(const std::string& dev, int prec, int bucket) {
+  return dev + ":p" + std::to_string(prec) + ":b" + std::to_string(bucket);
+}
+
+// The whole batch fit, warm-up and 3 timed repetitions, at the current chunk lengths.
+int time_fit(vl_batch* B, void* ws, int32_t* dev_status, hipStream_t s, hipEvent_t e0,
+             hipEvent_t e1, float* ms) {
+  build_layout(B);
+  int rc = upload(B, ws, s);
+  if (rc) return rc;
+  rc = launch_fit(B, ws, dev_status, s);
+  if (rc) return rc;
+  hipEventRecord(e0, s);
+  for (int r = 0; r < 3 && !rc; ++r) rc = launch_fit(B, ws, dev_status, s);
+  hipEventRecord(e1, s);
+  if (rc) return rc;
+  if (hipEventSynchronize(e1) != hipSuccess) return VL_ERR_HIP;
+  return hipEventElapsedTime(ms, e0, e1) == hipSuccess ? VL_OK : VL_ERR_HIP;
 }
 
 }  // namespace
@@ -729,21 +842,29 @@ int varlingam_batch_create(const vl_instance* inst, int count, int prec, vl_batc
   B->inst.assign(inst, inst + count);
   B->count = count;
   B->prec = prec;
-  size_t mx = 0;
-  for (int c : kChunkCandidates) {
-    B->chunk = c;
-    mx = std::max(mx, build_layout(B));
-  }
-  B->chunk = 2048;
-  build_layout(B);
-  B->ws_bytes = mx;
+  for (int k = 0; k < kNumBuckets; ++k) B->chunk[k] = 2048;
+  B->ws_bytes = std::max(layout_bound(B), build_layout(B));
   *out = B;
   return VL_OK;
 }
 
 size_t varlingam_batch_workspace_bytes(const vl_batch* B) { return B ? B->ws_bytes : 0; }
 
-int varlingam_batch_chunk_len(const vl_batch* B) { return B ? B->chunk : 0; }
+// the chunk length of the bucket that holds the most problems (ties: the lower bucket)
+int varlingam_batch_chunk_len(const vl_batch* B) {
+  if (!B) return 0;
+  int cnt[kNumBuckets] = {};
+  for (const auto& in : B->inst) ++cnt[bucket_of(in)];
+  int best = 0;
+  for (int k = 1; k < kNumBuckets; ++k)
+    if (cnt[k] > cnt[best]) best = k;
+  return B->chunk[best];
+}
+
+int varlingam_batch_chunk_len_of(const vl_batch* B, int problem) {
+  if (!B || problem < 0 || problem >= B->count) return 0;
+  return B->chunk[bucket_of(B->inst[problem])];
+}
 
 int varlingam_batch_bind(vl_batch* B, void* ws, size_t ws_bytes, void* stream) {
   if (!B || !ws) return VL_ERR_INVALID_ARG;
@@ -757,51 +878,83 @@ int varlingam_fit_batched(const vl_batch* B, void* ws, int32_t* dev_status, void
   return launch_fit(B, ws, dev_status, reinterpret_cast<hipStream_t>(stream));
 }
 
+// Search: every occupied bucket starts at the fastest uniform chunk length (all buckets
+// equal), then coordinate descent visits the buckets by decreasing pairwise work (sum of
+// m^2 (n - p)) and keeps a candidate only if the whole fit gets at least 1% faster.  Buckets
+// found in the cache are not searched; with all of them cached nothing is timed.
 int varlingam_batch_autotune(vl_batch* B, void* ws, size_t ws_bytes, int32_t* dev_status,
                              void* stream) {
   if (!B || !ws || !dev_status) return VL_ERR_INVALID_ARG;
   if (ws_bytes < B->ws_bytes || (reinterpret_cast<uintptr_t>(ws) & 255u)) return VL_ERR_WORKSPACE;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const std::string key = tune_key(B);
-  int best = -1;
+  const std::string dev = device_tag(), path = tune_file();
+  double work[kNumBuckets] = {};
+  for (const auto& in : B->inst)
+    work[bucket_of(in)] += (double)in.m * (double)in.m * (double)(in.n - in.p);
+  std::vector<int> occupied;
+  for (int k = 0; k < kNumBuckets; ++k)
+    if (work[k] > 0) occupied.push_back(k);
+  std::stable_sort(occupied.begin(), occupied.end(),
+                   [&](int a, int c) { return work[a] > work[c]; });
+  std::vector<int> todo;
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
-    auto it = g_tune_cache.find(key);
-    if (it != g_tune_cache.end()) best = it->second;
+    if (!g_tune_loaded) {
+      tune_read(path, g_tune_cache);
+      g_tune_loaded = true;
+    }
+    for (int k : occupied) {
+      auto it = g_tune_cache.find(bucket_key(dev, B->prec, k));
+      if (it != g_tune_cache.end()) B->chunk[k] = it->second;
+      else todo.push_back(k);
+    }
   }
-  if (best < 0) {
+  if (!todo.empty()) {
     hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return VL_ERR_HIP;
-    float best_ms = 0.f;
+    if (hipEventCreate(&e0) != hipSuccess) return VL_ERR_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+      hipEventDestroy(e0);
+      return VL_ERR_HIP;
+    }
     int rc = VL_OK;
-    for (int c : kChunkCandidates) {
-      B->chunk = c;
-      build_layout(B);
-      rc = upload(B, ws, s);
-      if (rc) break;
-      rc = launch_fit(B, ws, dev_status, s);                     // warm-up
-      if (rc) break;
-      hipEventRecord(e0, s);
-      for (int r = 0; r < 3 && !rc; ++r) rc = launch_fit(B, ws, dev_status, s);
-      hipEventRecord(e1, s);
-      if (rc || hipEventSynchronize(e1) != hipSuccess) {
-        rc = rc ? rc : VL_ERR_HIP;
-        break;
-      }
+    float best_ms = 0.f;
+    // uniform start for the buckets to search
+    int best_c = B->chunk[todo[0]];
+    for (int ci = 0; ci < kNumCand && !rc; ++ci) {
+      for (int k : todo) B->chunk[k] = kChunkCandidates[ci];
       float ms = 0.f;
-      hipEventElapsedTime(&ms, e0, e1);
-      if (best < 0 || ms < best_ms) {
-        best = c;
+      rc = time_fit(B, ws, dev_status, s, e0, e1, &ms);
+      if (!rc && (ci == 0 || ms < best_ms)) {
         best_ms = ms;
+        best_c = kChunkCandidates[ci];
       }
+    }
+    for (int k : todo) B->chunk[k] = best_c;
+    // coordinate descent, one pass
+    for (size_t t = 0; t < todo.size() && !rc && todo.size() > 1; ++t) {
+      const int k = todo[t], keep = B->chunk[k];
+      int bestk = keep;
+      for (int c : kChunkCandidates) {
+        if (c == keep || rc) continue;
+        B->chunk[k] = c;
+        float ms = 0.f;
+        rc = time_fit(B, ws, dev_status, s, e0, e1, &ms);
+        if (!rc && ms < 0.99f * best_ms) {
+          best_ms = ms;
+          bestk = c;
+        }
+      }
+      B->chunk[k] = bestk;
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (rc) return rc;
+    std::map<std::string, int> found;
+    for (int k : todo) found[bucket_key(dev, B->prec, k)] = B->chunk[k];
     std::lock_guard<std::mutex> g(g_tune_mu);
-    g_tune_cache[key] = best;
+    for (const auto& kv : found) g_tune_cache[kv.first] = kv.second;
+    tune_write(path, found);
   }
-  B->chunk = best;
   build_layout(B);
   return upload(B, ws, s);
 }

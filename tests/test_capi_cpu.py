@@ -233,6 +233,8 @@ def test_batch_plan_host_checks(L):
     assert lib.varlingam_batch_create(ok, 4, 1, ctypes.byref(h)) == L.VL_OK
     assert lib.varlingam_batch_workspace_bytes(h) > 4 * 8000 * 200 * 4   # >= the Xs copies
     assert lib.varlingam_batch_chunk_len(h) == 2048
+    assert [lib.varlingam_batch_chunk_len_of(h, b) for b in range(4)] == [2048] * 4
+    assert lib.varlingam_batch_chunk_len_of(h, 4) == 0 and lib.varlingam_batch_chunk_len_of(h, -1) == 0
     assert lib.varlingam_batch_bind(h, FAKE, 64, None) == L.VL_ERR_WORKSPACE
     assert lib.varlingam_fit_batched(h, FAKE, FAKE, None) == L.VL_ERR_INVALID_ARG  # not bound
     lib.varlingam_batch_destroy(h)

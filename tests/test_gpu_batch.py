@@ -170,6 +170,61 @@ def test_batch_autotune_keeps_results(api):
         _check_problem(r, inst, 1)
 
 
+def _read_tune(path):
+    out = {}
+    for line in open(path):
+        k, v = line.split()
+        out[k] = int(v)
+    return out
+
+
+def test_batch_autotune_per_bucket_cache(api, tmp_path, monkeypatch):
+    """Per-bucket chunk lengths: the search writes one cache line per (device, precision,
+    bucket) of the batch, every problem runs at its bucket's length, the mixed layout keeps the
+    results, and a fresh process that finds all buckets in the file takes them as they are
+    (no timing: the forced values below are not what the search chose)."""
+    import json
+    import os
+    import subprocess
+    import sys
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("VL_TUNE_CACHE", str(cache))
+    # buckets (m class, n class): (0, 1), (2, 2), (3, 3)
+    spec = [(24, 1500, 1, "laplace"), (100, 3000, 1, "uniform"), (140, 5000, 1, "laplace")]
+    insts = _instances(spec, seed0=61)
+    shapes = [i.X32.shape for i in insts]
+    bf = api.BatchFitter(shapes, 1, "mixed")
+    bf.load([i.X32 for i in insts])
+    bf.autotune()
+    lens = bf.chunk_lens()
+    cands = (512, 1024, 2048, 4096, 8192)
+    assert all(c in cands for c in lens)
+    entries = _read_tune(cache)
+    buckets = [f":p1:b{b}" for b in (1, 10, 15)]
+    keys = [next(k for k in entries if k.endswith(sfx)) for sfx in buckets]
+    assert [entries[k] for k in keys] == lens
+    bf.run()
+    assert bf.check() == [0, 0, 0]
+    for r, inst in zip(bf.results, insts):
+        _check_problem(r, inst, 1)
+    # a fresh process reads forced values from the file and times nothing
+    forced = [1024 if c != 1024 else 4096 for c in lens]
+    cache2 = tmp_path / "tune2.txt"
+    cache2.write_text("".join(f"{k} {v}\n" for k, v in zip(keys, forced)))
+    before = cache2.read_text()
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import json, sys; sys.path.insert(0, %r); "
+            "from paper_2409_05500_amd import api; import torch; "
+            "bf = api.BatchFitter(%r, 1, 'mixed'); bf.autotune(); "
+            "print(json.dumps(bf.chunk_lens()))" % (root, [tuple(x) for x in shapes]))
+    env = dict(os.environ, VL_TUNE_CACHE=str(cache2))
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                         timeout=120)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert json.loads(out.stdout.strip().splitlines()[-1]) == forced
+    assert cache2.read_text() == before
+
+
 def test_batch_full_workload_sampled(api):
     """The 256-problem workload (m in [20, 200], n in [500, 8000], uniform / Laplace):
     every problem checked for structure, four problems recomputed by the oracle."""
