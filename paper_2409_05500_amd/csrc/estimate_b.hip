@@ -14,31 +14,21 @@
 
 namespace vl {
 
-// P[a][b] = Cov[K_a][K_b]; seen[] counts each index (the permutation check).
+// P[a][b] = Cov[K_a][K_b].  The permutation check rides along: an index out of range, or two
+// positions a != b holding the same index (m values in [0, m) without a repeat are a
+// permutation), raises VL_ERR_INVALID_ARG before the factorisation can raise anything.
 __global__ void permute_cov_kernel(const double* __restrict__ Cov, const int32_t* __restrict__ K,
-                                   int64_t m, double* __restrict__ P, int32_t* __restrict__ seen,
-                                   int32_t* st) {
+                                   int64_t m, double* __restrict__ P, int32_t* st) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= m * m) return;
   const int64_t a = e / m, b = e % m;
   const int32_t ka = K[a], kb = K[b];
-  if (ka < 0 || ka >= m || kb < 0 || kb >= m) {
+  if (ka < 0 || ka >= m || kb < 0 || kb >= m || (a != b && ka == kb)) {
     raise_status(st, VL_ERR_INVALID_ARG);
     P[e] = a == b ? 1.0 : 0.0;
     return;
   }
   P[e] = Cov[(int64_t)ka * m + kb];
-  if (b == 0) atomicAdd(reinterpret_cast<int*>(seen + ka), 1);
-}
-
-__global__ void check_perm_kernel(const int32_t* __restrict__ seen, int64_t m, int32_t* st) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < m && seen[e] != 1) raise_status(st, VL_ERR_INVALID_ARG);
-}
-
-__global__ void zero_i32_kernel(int32_t* __restrict__ a, int64_t n) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n) a[e] = 0;
 }
 
 // B0[K_a][K_b] = -Linv[a][b] / Linv[a][a] for b < a (Lc[a][a] = 1 / Linv[a][a]); 0 otherwise
@@ -68,7 +58,6 @@ size_t b_ws_bytes(int64_t m, void* base, BWs* out) {
   BWs w;
   w.P = c.take<double>(m * m);
   w.Linv = c.take<double>(m * m);
-  w.seen = c.take<int32_t>(m);
   w.chol = c.take<double>(chol_ws_doubles(m));
   if (out) *out = w;
   return c.used;
@@ -78,11 +67,7 @@ int run_estimate_b(const BWs& w, const double* Cov, const double* M, const int32
                    int p, double* B0, double* Blag, int32_t* st, hipStream_t stream) {
   ProfileScope ps("estimate_b", stream);
   const unsigned g = (unsigned)ceil_div(m * m, 256);
-  zero_i32_kernel<<<(unsigned)ceil_div(m, 256), 256, 0, stream>>>(w.seen, m);
-  VL_LAUNCH_CHECK();
-  permute_cov_kernel<<<g, 256, 0, stream>>>(Cov, K, m, w.P, w.seen, st);
-  VL_LAUNCH_CHECK();
-  check_perm_kernel<<<(unsigned)ceil_div(m, 256), 256, 0, stream>>>(w.seen, m, st);
+  permute_cov_kernel<<<g, 256, 0, stream>>>(Cov, K, m, w.P, st);
   VL_LAUNCH_CHECK();
   int rc = chol_solve_lower(w.P, m, m, nullptr, 0, 0, w.Linv, m, w.chol, st, stream);
   if (rc) return rc;

@@ -7,7 +7,6 @@ namespace vl {
 struct BWs {
   double* P = nullptr;     // m x m permuted covariance (destroyed by the factorisation)
   double* Linv = nullptr;  // m x m inverse of the factor
-  int32_t* seen = nullptr; // m permutation counters
   double* chol = nullptr;  // factorisation scratch
 };
 

@@ -79,21 +79,27 @@ __device__ inline double sum_splits_at(const double* __restrict__ P, int splits,
 }
 
 __global__ void colmean_final_kernel(const double* __restrict__ part, int64_t ncol, int splits,
-                                     int64_t K, double* __restrict__ mean) {
+                                     int64_t K, double* __restrict__ mean,
+                                     double* __restrict__ rep, int64_t rep_m,
+                                     int64_t rep_blocks) {
   int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncol) return;
-  mean[c] = sum_splits_at(part, splits, ncol, c) / (double)K;
+  const double v = sum_splits_at(part, splits, ncol, c) / (double)K;
+  mean[c] = v;
+  if (rep && c < rep_m)
+    for (int64_t h = 0; h < rep_blocks; ++h) rep[h * rep_m + c] = v;
 }
 
 int colmeans(const float* A, int64_t lda, const int64_t* colmap, int64_t ncol, int64_t K,
-             double* mean, double* scratch, int32_t* st, hipStream_t stream) {
+             double* mean, double* scratch, int32_t* st, hipStream_t stream, double* rep,
+             int64_t rep_m, int64_t rep_blocks) {
   const int splits = colmean_splits(K);
   const int64_t rows = ceil_div(K, splits);
   dim3 grid((unsigned)ceil_div(ncol, 64), (unsigned)splits);
   colsum_partial_kernel<<<grid, 256, 0, stream>>>(A, lda, colmap, ncol, K, rows, scratch, st);
   VL_LAUNCH_CHECK();
-  colmean_final_kernel<<<(unsigned)ceil_div(ncol, 256), 256, 0, stream>>>(scratch, ncol, splits,
-                                                                          K, mean);
+  colmean_final_kernel<<<(unsigned)ceil_div(ncol, 256), 256, 0, stream>>>(
+      scratch, ncol, splits, K, mean, rep, rep_m, rep_blocks);
   VL_LAUNCH_CHECK();
   return VL_OK;
 }

@@ -11,8 +11,10 @@ inline int colmean_splits(int64_t K) {
 }
 
 // mean[c] = (1/K) sum_{t<K} A[map(c) + t*lda]  (FP64);  raises VL_ERR_NONFINITE on NaN/Inf.
+// With rep: rep[h * rep_m + c] = mean[c] for c < rep_m and h < rep_blocks as well.
 int colmeans(const float* A, int64_t lda, const int64_t* colmap, int64_t ncol, int64_t K,
-             double* mean, double* scratch, int32_t* st, hipStream_t stream);
+             double* mean, double* scratch, int32_t* st, hipStream_t stream,
+             double* rep = nullptr, int64_t rep_m = 0, int64_t rep_blocks = 0);
 
 // Split-K factor of gram_tn(); scratch must hold gram_splits(M,N,K) * M * N doubles.  About
 // 1024 workgroups (four per CU): with M == N the tiles counted are the lower triangle's, which

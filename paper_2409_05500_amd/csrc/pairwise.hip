@@ -36,23 +36,24 @@ __global__ __launch_bounds__(256) void standardize_transpose_kernel(
                    (int64_t)blockIdx.y * gridDim.x + blockIdx.x, (int64_t)gridDim.x * gridDim.y);
 }
 
-// 1024 threads per variable: one workgroup per variable is all the parallelism there is (a few
-// hundred workgroups in a fit, a handful late in the iterative search), so each works its
-// samples with 16 waves.  Measured effect is small: the iterative search at m = 400 went
+// Hx takes 1024 threads per variable: one workgroup per variable is all the parallelism there
+// is (a few hundred workgroups in a fit, a handful late in the iterative search), so each works
+// its samples with 16 waves.  Measured effect is small: the iterative search at m = 400 went
 // 118.7 -> 117.4 ms, the fit's preparation stage 40.3 -> 39.8 us.
 constexpr int kHxThreads = 1024;
-__global__ __launch_bounds__(kHxThreads) void hx_kernel(const float* __restrict__ Xs,
-                                                        int64_t n_pad, int64_t n_eff,
-                                                        double* __restrict__ Hx,
-                                                        double* __restrict__ momx) {
-  hx_block<kHxThreads>(Xs, n_pad, n_eff, Hx, momx, blockIdx.x);
-}
 
-__global__ void pair_coef_kernel(const double* __restrict__ cov, int64_t m, int64_t m_pad,
-                                 float2* __restrict__ coef, int nt, int64_t tiles,
-                                 int32_t* __restrict__ clist, int32_t* st) {
+// One launch for the two independent preparation steps: blocks [0, m) are hx_kernel's, the
+// blocks after them form the pair coefficients, one element per thread.
+__global__ __launch_bounds__(kHxThreads) void prep_kernel(
+    const float* __restrict__ Xs, int64_t n_pad, int64_t n_eff, double* __restrict__ Hx,
+    double* __restrict__ momx, const double* __restrict__ cov, int64_t m, int64_t m_pad,
+    float2* __restrict__ coef, int nt, int64_t tiles, int32_t* __restrict__ clist, int32_t* st) {
+  if ((int64_t)blockIdx.x < m) {
+    hx_block<kHxThreads>(Xs, n_pad, n_eff, Hx, momx, blockIdx.x);
+    return;
+  }
   pair_coef_elem(cov, m, m_pad, coef, nt, tiles, clist, st,
-                 (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+                 ((int64_t)blockIdx.x - m) * kHxThreads + threadIdx.x);
 }
 
 // Blocks are remapped so that XCD x (block id mod 8) processes a contiguous range of items in
@@ -179,10 +180,9 @@ int run_pairwise(const PairwisePlan& p, const PairwiseWs& w, const float* E, int
     int rc = standardize_to(E, lde, n_eff, m, w.mu, cov, w.Xs, p.n_pad, p.m_pad, st, stream,
                             w.clist, p.tiles + 1);
     if (rc) return rc;
-    hx_kernel<<<(unsigned)m, kHxThreads, 0, stream>>>(w.Xs, p.n_pad, n_eff, Hx, w.momx);
-    VL_LAUNCH_CHECK();
-    pair_coef_kernel<<<(unsigned)ceil_div(p.m_pad * p.m_pad, 256), 256, 0, stream>>>(
-        cov, m, p.m_pad, w.coef, p.nt, p.tiles, w.clist, st);
+    prep_kernel<<<(unsigned)(m + ceil_div(p.m_pad * p.m_pad, (int64_t)kHxThreads)), kHxThreads,
+                  0, stream>>>(w.Xs, p.n_pad, n_eff, Hx, w.momx, cov, m, p.m_pad, w.coef, p.nt,
+                               p.tiles, w.clist, st);
     VL_LAUNCH_CHECK();
   }
   {

@@ -38,11 +38,6 @@ __global__ void lag_colmap_kernel(int64_t m, int p, int64_t ldx, int64_t* __rest
   colmap[c] = (p - tau) * ldx + i;
 }
 
-__global__ void fill_f64_kernel(double* __restrict__ a, int64_t n, double v) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n) a[e] = v;
-}
-
 __global__ void to_f32_kernel(const double* __restrict__ a, int64_t n, float* __restrict__ b) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < n) b[e] = (float)a[e];
@@ -159,21 +154,23 @@ static void launch_residual_f64w(const float* X, int64_t ldx, const int64_t* col
   }
 }
 
-// M[(tau-1) m m + i m + k] = Coef[(tau-1) m + k][i]
-__global__ void var_lag_matrices_kernel(const double* __restrict__ Coef, int64_t m, int p,
-                                        double* __restrict__ M) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)p * m * m) return;
-  const int64_t tau1 = e / (m * m), rem = e % (m * m), i = rem / m, k = rem % m;
-  M[e] = Coef[(tau1 * m + k) * m + i];
-}
-
-// c[i] = muY[i] - sum_k' Coef[k'][i] muZ[k'], one wave per variable
-__global__ __launch_bounds__(256) void var_intercept_kernel(const double* __restrict__ Coef,
-                                                            const double* __restrict__ mu,
-                                                            int64_t m, int64_t dz,
-                                                            double* __restrict__ intercept) {
-  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+// After the solve, in one launch: blocks [0, nlag) write the lag matrices,
+// M[(tau-1) m m + i m + k] = Coef[(tau-1) m + k][i]; the blocks after them the intercepts,
+// c[i] = muY[i] - sum_k' Coef[k'][i] muZ[k'], one wave per variable.
+__global__ __launch_bounds__(256) void var_post_kernel(const double* __restrict__ Coef,
+                                                       const double* __restrict__ mu, int64_t m,
+                                                       int p, int64_t nlag,
+                                                       double* __restrict__ M,
+                                                       double* __restrict__ intercept) {
+  if ((int64_t)blockIdx.x < nlag) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)p * m * m) return;
+    const int64_t tau1 = e / (m * m), rem = e % (m * m), i = rem / m, k = rem % m;
+    M[e] = Coef[(tau1 * m + k) * m + i];
+    return;
+  }
+  const int64_t dz = m * p;
+  const int64_t i = ((int64_t)blockIdx.x - nlag) * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (i >= m) return;
   double s = 0.0;
@@ -198,7 +195,6 @@ size_t var_ws_bytes(const VarPlan& v, void* base, VarWs* out) {
   const int64_t nc = v.m * (v.p + 1);
   w.colmap = c.take<int64_t>(nc);
   w.mu = c.take<double>(nc);
-  w.zeros = c.take<double>(v.m);
   w.G = c.take<double>(v.dz * v.dz);
   w.Coef = c.take<double>(v.dz * v.m);
   w.Rres = c.take<double>(v.dz * v.m);
@@ -240,12 +236,6 @@ static int var_residual(const VarPlan& v, const VarWs& w, const float* X, int64_
   return VL_OK;
 }
 
-// mu0[h m + j] = mu[j]: every lag block of the lag products is centred by the lag-0 means.
-__global__ void lag_mu0_kernel(const double* __restrict__ mu, int64_t m, int64_t nc,
-                               double* __restrict__ mu0) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < nc) mu0[e] = mu[e % m];
-}
 
 // G (dz x dz, both triangles) and R (dz x m) of the VAR normal equations from the lag products
 // F (see var_normal_equations).  Column (tau, i) of the regression is x_i(t - tau), t = p .. n-1,
@@ -303,13 +293,12 @@ static int var_normal_equations(const VarPlan& v, const VarWs& w, const float* X
     ProfileScope ps("var_gram", stream);
     lag_colmap_kernel<<<(unsigned)ceil_div(nc, 256), 256, 0, stream>>>(m, v.p, ldx, w.colmap);
     VL_LAUNCH_CHECK();
-    fill_f64_kernel<<<(unsigned)ceil_div(m, 256), 256, 0, stream>>>(w.zeros, m, 0.0);
-    VL_LAUNCH_CHECK();
-    rc = colmeans(X, ldx, w.colmap, nc, n_eff, w.mu, w.scratch, st, stream);
+    // MIXED also needs the lag-0 means once per lag block (mu0), written by the same pass
+    const bool fp64 = gmode == GramMode::kFp64;
+    rc = colmeans(X, ldx, w.colmap, nc, n_eff, w.mu, w.scratch, st, stream,
+                  fp64 ? w.mu0 : nullptr, m, v.p + 1);
     if (rc) return rc;
-    if (gmode == GramMode::kFp64) {
-      lag_mu0_kernel<<<(unsigned)ceil_div(nc, 256), 256, 0, stream>>>(w.mu, m, nc, w.mu0);
-      VL_LAUNCH_CHECK();
+    if (fp64) {
       rc = gram_tn(X, ldx, w.colmap, w.mu, m, X, ldx, w.colmap, w.mu0, nc, n_eff, gmode, 1.0,
                    w.F, nc, w.scratch, stream);
       if (rc) return rc;
@@ -401,11 +390,12 @@ int run_var(const VarPlan& v, const VarWs& w, const float* X, int64_t ldx, int p
     rc = var_residual(v, w, X, ldx, E, lde, !plain, stream);
     if (rc) return rc;
   }
-  var_lag_matrices_kernel<<<(unsigned)ceil_div(dz * m, 256), 256, 0, stream>>>(w.Coef, m, v.p, M);
-  VL_LAUNCH_CHECK();
-  var_intercept_kernel<<<(unsigned)ceil_div(m, 4), 256, 0, stream>>>(w.Coef, w.mu, m, dz,
-                                                                    intercept);
-  VL_LAUNCH_CHECK();
+  {
+    const int64_t nlag = ceil_div(dz * m, (int64_t)256);
+    var_post_kernel<<<(unsigned)(nlag + ceil_div(m, (int64_t)4)), 256, 0, stream>>>(
+        w.Coef, w.mu, m, v.p, nlag, M, intercept);
+    VL_LAUNCH_CHECK();
+  }
   return VL_OK;
 }
 

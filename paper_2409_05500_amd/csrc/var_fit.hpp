@@ -12,7 +12,6 @@ struct VarPlan {
 struct VarWs {
   int64_t* colmap = nullptr;  // m (p+1) sample offsets of the lag-embedded columns
   double* mu = nullptr;       // m (p+1) column means (Y first, then Z)
-  double* zeros = nullptr;    // m zeros (mean of E in the refinement Gram)
   double* G = nullptr;        // dz x dz Gram (destroyed by the factorisation)
   double* Coef = nullptr;     // dz x m solution
   double* Rres = nullptr;     // dz x m refinement right-hand side
