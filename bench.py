@@ -35,8 +35,8 @@ TRANS_PER_EVAL = 3
 # exactly: x1).  Keyed by the SHA-256 of the kernel sources the counters were taken with
 # (kernel_source_digest); any other source reports null.
 MEASURED_TRAFFIC = {
-    # FETCH_SIZE 34733.7 KiB x 2, WRITE_SIZE 8559.7 KiB x 1 per dispatch (18 dispatches)
-    "28a3b4009a508f92e96ec501768d8c4ac9254edee39afa4b3c7c5f14afc30b8d": 79899794,
+    # FETCH_SIZE 35186.4 KiB x 2, WRITE_SIZE 8547.2 KiB x 1 per dispatch (18 dispatches)
+    "0aad8ec81e63ac74d3c8332c3f56b6255d63b711c76380dd155f276db58dd332": 80814148,
 }
 STAGES = ("var_gram", "var_solve", "var_residual", "var_refine", "pairwise_cov",
           "pairwise_prep", "pairwise_moments", "pairwise_combine", "order", "estimate_b")
