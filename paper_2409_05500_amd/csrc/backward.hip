@@ -14,30 +14,44 @@
 //   dE_i(t) = (dx_i(t) - mean dx_i - x_i(t) mean(dx_i x_i)) / sd_i      (standardisation)
 //
 // The per-sample terms are recomputed (nothing of size m^2 n is stored).  The transcendental
-// pass is owner-computes: one wave owns 4 variables and a 128-sample chunk and visits every
-// partner block, so each dx_i(t) is summed in registers in a fixed order (no atomics); the
-// pair's R contribution of that chunk is reduced across the wave and written per chunk.
+// pass evaluates each pair once: a workgroup takes one 128-sample chunk and a row a of the
+// 32 x 32 tiles of variable pairs (blocks a <= b of 32 variables); each wave keeps its own 4
+// rows of block a in registers over the row and visits the 4-row blocks of b in a rotation
+// that gives every block of b to one wave per round, whose sums go through LDS.  Each pair adds
+// its two terms to dx_i and dx_j and its chunk's R partial; the sums of block b from row a are
+// written as one partial per (row, variable) and summed in a fixed order afterwards, so the
+// result is deterministic with no atomics.
+#include <algorithm>
+#include <type_traits>
+
 #include "backward.hpp"
 #include "profile.hpp"
 
 namespace vl {
 
-constexpr int kBT = 4;        // variables per wave (owner block)
-constexpr int kBSpl = 2;      // samples per lane (67 VGPRs: many waves hide the trans latency)
+// 8 waves: three workgroups share a CU (76 VGPRs), so one workgroup's round barrier overlaps
+// the others' work (16 waves at one workgroup per CU: 15% slower)
+constexpr int kTW = 8;              // waves per workgroup of the pair-tile pass
+constexpr int kTT = 4;              // variables per wave block
+constexpr int kTK = kTW * kTT;      // 32 variables per tile side
+constexpr int kBSpl = 2;            // samples per lane
 constexpr int kBChunk = 64 * kBSpl;
+constexpr int64_t kPdBytes = int64_t(2) << 30;   // per-partner-block sums of one window
+constexpr double kExpMinusHalf = 0.60653065971263342360;   // e^{-1/2}
 
 // Per ordered pair (i, j), i != j, the wave-uniform constants of the transcendental pass:
 //   (a, b)      w0 = a x_i - b x_j = c u_ij,  w1 = a x_j - b x_i = c u_ji
 //   rho         dx_i += G0 - rho G1  with G0 = g_ij / s, G1 = g_ji / s
 //   per direction d (0: u_ij with alpha_ij, beta_ij; 1: u_ji with alpha_ji, beta_ji), with
 //   A = alpha / (n s), B = beta / (n s):  G = A tanh u + B (1 - u^2) e^{-u^2/2}
-//      = 2A r - A + (B - B q / c^2) e,   q = w^2, e = exp2(-q), r = 1 / (1 + e^{-2u})
-//   stored as (2A, -A, B, -B / c^2).
+//      = 2A r - A + Bq h exp2(-h),   h = w^2 - c^2,  r = 1 / (1 + e^{-2u}),
+//   since c^2 = log2(e) / 2 makes exp2(-w^2) = e^{-1/2} exp2(-h) and B (1 - u^2) = -B h / c^2:
+//   stored as (2A, -A, Bq = -B e^{-1/2} / c^2).
 struct BwdPair {
-  float a, b, rho, pad;
-  float a2[2], na[2], bb[2], bq[2];
+  float a, b, rho;
+  float a2[2], na[2], bq[2];
 };
-static_assert(sizeof(BwdPair) == 48, "BwdPair is read with scalar loads");
+static_assert(sizeof(BwdPair) == 36, "BwdPair is read with scalar loads");
 
 __device__ inline void pair_geometry(const double* __restrict__ cov, int64_t m, int64_t i,
                                      int64_t j, double& rho, double& s) {
@@ -68,23 +82,28 @@ __global__ void bwd_pair_kernel(const double* __restrict__ cov, const double* __
       const double be = -2.0 * kK2 * B[d] * dh[d] * k;
       p.a2[d] = (float)(2.0 * al);
       p.na[d] = (float)(-al);
-      p.bb[d] = (float)be;
-      p.bq[d] = (float)(-be / (kWScale * kWScale));
+      p.bq[d] = (float)(-be * kExpMinusHalf / (kWScale * kWScale));
     }
   }
   bp[j * m_pad + i] = p;
 }
 
-// Hx-term coefficients per variable: (alpha^x_i, beta^x_i) / n
-__global__ void bwd_var_kernel(const double* __restrict__ momx, const double* __restrict__ G,
-                               int64_t m, int64_t m_pad, int64_t n_eff,
-                               float2* __restrict__ vx) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Hx-term coefficients per variable: (alpha^x_i, beta^x_i) / n.  One wave per variable: its
+// lanes stride over k for sum_k G_ki - G_ik (FP64), then a wave sum.
+__global__ __launch_bounds__(256) void bwd_var_kernel(const double* __restrict__ momx,
+                                                      const double* __restrict__ G, int64_t m,
+                                                      int64_t m_pad, int64_t n_eff,
+                                                      float2* __restrict__ vx) {
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (i >= m_pad) return;
+  double c = 0.0;
+  if (i < m)
+    for (int64_t k = lane; k < m; k += 64) c += G[k * m + i] - G[i * m + k];
+  c = wave_sum_d(c);
+  if (lane != 0) return;
   float2 v = make_float2(0.f, 0.f);
   if (i < m) {
-    double c = 0.0;
-    for (int64_t k = 0; k < m; ++k) c += G[k * m + i] - G[i * m + k];
     const double inv_n = 1.0 / (double)n_eff;
     v.x = (float)(-2.0 * kK1 * (momx[2 * i] - kGamma) * c * inv_n);
     v.y = (float)(-2.0 * kK2 * momx[2 * i + 1] * c * inv_n);
@@ -93,95 +112,225 @@ __global__ void bwd_var_kernel(const double* __restrict__ momx, const double* __
 }
 
 // One direction's pre-scaled dL/du from w = c u (constants as stored in BwdPair):
-//   2A r - A + (B + Bq q) e,  r = 1 / (1 + exp2(kTScale w)) (exact limits 0 and 1 for large |w|)
-__device__ __forceinline__ float dir_grad(float w, float a2, float na, float bb, float bq) {
-  const float q = w * w;
-  const float e = __builtin_amdgcn_exp2f(-q);
+//   2A r - A + Bq h exp2(-h),  h = w^2 - c^2 (one rounding),  r = 1 / (1 + exp2(kTScale w))
+//   (exact limits 0 and 1 for large |w|)
+__device__ __forceinline__ float dir_grad(float w, float a2, float na, float bq) {
+  const float h = fmaf(w, w, -(float)(kWScale * kWScale));
+  const float e = __builtin_amdgcn_exp2f(-h);
   const float t = __builtin_amdgcn_exp2f(w * (float)kTScale);
   const float r = __builtin_amdgcn_rcpf(1.f + t);
-  return fmaf(a2, r, fmaf(fmaf(q, bq, bb), e, na));
+  return fmaf(a2, r, fmaf(bq * h, e, na));
 }
 
-// One wave per (block I of 4 variables, 128-sample chunk); lane l holds samples
-// chunk * 128 + 2 l + [0, 2).  The wave walks every partner j (runtime loop, next partner's
-// samples prefetched), and for the 4 pairs (i, j), i in I: dx_i += g_ij / s - rho g_ji / s and
-// the chunk's R partial of (i, j) is summed across the wave.  Output: dx (m_pad x n_pad,
-// variable-major FP32: direct and Hx terms) and Rp[chunk][i][j] for j > i.
-// Pair constants are stored transposed, bp[j * m_pad + i], so the 4 pairs of one step are
-// contiguous (wave-uniform scalar loads).
-__global__ __launch_bounds__(256) void bwd_owner_kernel(
-    const float* __restrict__ Xs, int64_t n_pad, const BwdPair* __restrict__ bp,
-    const float2* __restrict__ vx, int64_t m_pad, int64_t m, int nt, int64_t nchunk,
-    float* __restrict__ dx, float* __restrict__ Rp) {
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  const int64_t item = (int64_t)blockIdx.x * 4 + wave;
-  if (item >= (int64_t)nt * nchunk) return;
-  const int64_t chunk = item / nt;
-  const int bi = (int)(item - chunk * nt);
-  const int64_t i0 = (int64_t)bi * kBT;
-  const int64_t tb = chunk * kBChunk + kBSpl * lane;
+// A lane's kBSpl consecutive samples: FP32 loads and stores, FP64 LDS sums.
+typedef std::conditional_t<kBSpl == 2, double2, double> SlotT;
+static_assert(kBSpl == 1 || kBSpl == 2, "one or two samples per lane");
+__device__ __forceinline__ void load_spl(const float* p, float* dst) {
+  if constexpr (kBSpl == 2) {
+    const float2 f = *reinterpret_cast<const float2*>(p);
+    dst[0] = f.x;
+    dst[1] = f.y;
+  } else {
+    dst[0] = *p;
+  }
+}
+__device__ __forceinline__ void store_spl(float* p, const double* v) {
+  if constexpr (kBSpl == 2)
+    *reinterpret_cast<float2*>(p) = make_float2((float)v[0], (float)v[1]);
+  else
+    *p = (float)v[0];
+}
+__device__ __forceinline__ void slot_add(double2& s, const double* v) {
+  s.x += v[0];
+  s.y += v[1];
+}
+__device__ __forceinline__ void slot_add(double& s, const double* v) { s += v[0]; }
+__device__ __forceinline__ void slot_get(const double2& s, double* v) {
+  v[0] = s.x;
+  v[1] = s.y;
+}
+__device__ __forceinline__ void slot_get(double s, double* v) { v[0] = s; }
 
+// Both terms of the pair (i, j) at one sample (x = x_i(t), y = x_j(t), constants of the
+// ordered pair (i, j)): dx_i += g_ij / s - rho g_ji / s, dx_j += g_ji / s - rho g_ij / s, and
+// the rho chain's (g_ij / s)(c u_ji) + (g_ji / s)(c u_ij) (= -R_ij c / s summed over t).
+__device__ __forceinline__ void pair_terms(const BwdPair& c, float x, float y, double& ai,
+                                           double& aj, float& r) {
+  const float w0 = fmaf(x, c.a, -(y * c.b));      // c u_ij
+  const float w1 = fmaf(y, c.a, -(x * c.b));      // c u_ji
+  const float g0 = dir_grad(w0, c.a2[0], c.na[0], c.bq[0]);   // g_ij / s
+  const float g1 = dir_grad(w1, c.a2[1], c.na[1], c.bq[1]);   // g_ji / s
   // dL/dx_i(t) is summed in FP64: the Hx term and the sum of the pair terms nearly cancel
   // (each pair term follows Hr_ij - Hx_i, a small difference), so FP32 partial sums would
   // carry rounding at many times the scale of the result.
-  float xi[kBT][kBSpl], xj[kBSpl];
-  double acc[kBT][kBSpl];
-  static_assert(kBSpl == 2, "float2 loads and stores");
-  auto load_x = [&](const float* src, int64_t row, float* dst) {
-    const float2 f = *reinterpret_cast<const float2*>(src + row * n_pad + tb);
-    dst[0] = f.x;
-    dst[1] = f.y;
-  };
+  ai += (double)fmaf(-c.rho, g1, g0);
+  aj += (double)fmaf(-c.rho, g0, g1);
+  r = fmaf(g0, w1, fmaf(g1, w0, r));
+}
+
+// Row of Pd holding partial p (p <= v / 32) of variable v: the partials of one variable are
+// consecutive, block B of variables holding B + 1 partials per variable.
+__host__ __device__ inline int64_t pd_row(int64_t v, int64_t p) {
+  const int64_t B = v / kTK, r = v - B * kTK;
+  return kTK * B * (B + 1) / 2 + r * (B + 1) + p;
+}
+__host__ __device__ inline int64_t pd_rows(int64_t nblk) { return kTK * nblk * (nblk + 1) / 2; }
+
+// One workgroup (8 waves) per (row a of the 32-variable blocks, 128-sample chunk); rows in
+// increasing a (the longest first).  The workgroup visits the tiles (a, b), b = a .. P - 1.
+// Lane l holds samples chunk * 128 + 2 l + [0, 2).  Wave w owns rows a * 32 + 4 w + [0, 4), their
+// sums in registers over the whole row of tiles.  In round r of a tile it takes the rows
+// b * 32 + 4 y + [0, 4), y = (w + r) mod 8: within a round every y has one wave, so the partner
+// sums are added to LDS rows with one writer, and a barrier orders the rounds.  Off-diagonal
+// tiles run 8 rounds; the diagonal tile (b = a) runs the pairs inside the own block (round 0)
+// and the rotations 1..4 (rotation 4 by waves 0..3 only), so each unordered pair is visited
+// once.  After a tile, each wave moves its 4 LDS rows out: into its own sums (b = a) or to the
+// partial a of the variables of b.  The launch covers chunks [chunk0, chunk0 + nchunk) (a window
+// of the samples); outputs, FP32, with t - chunk0 * 128 as the column (row stride ldp):
+// partial a of each variable of blocks a .. P - 1 (rows pd_row; for block a the own sums with
+// the Hx term), and Rp[chunk][i][j] for each pair, i < j < m.  Pair constants are stored
+// transposed, bp[j * m_pad + i], so the 4 own rows of one partner are contiguous (scalar loads).
+__global__ __launch_bounds__(kTW * 64) void bwd_tile_kernel(
+    const float* __restrict__ Xs, int64_t n_pad, const BwdPair* __restrict__ bp,
+    const float2* __restrict__ vx, int64_t m_pad, int64_t m, int P, int64_t chunk0,
+    int64_t nchunk, float* __restrict__ Pd, int64_t ldp, float* __restrict__ Rp) {
+  __shared__ SlotT slot[kTK][64];     // sums of the rows of block b: [row][lane] (32 KB)
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int a = (int)((int64_t)blockIdx.x / nchunk);
+  const int64_t chunk = chunk0 + ((int64_t)blockIdx.x - (int64_t)a * nchunk);
+  const int64_t ia0 = (int64_t)a * kTK + kTT * wave;
+  const int64_t tb = chunk * kBChunk + kBSpl * lane;
+  float* const pd = Pd + (tb - chunk0 * kBChunk);     // this lane's column of the window
+  auto load_x = [&](int64_t row, float* dst) { load_spl(Xs + row * n_pad + tb, dst); };
+  float xa[kTT][kBSpl];
+  double acc[kTT][kBSpl];
 #pragma unroll
-  for (int ii = 0; ii < kBT; ++ii) {
-    load_x(Xs, i0 + ii, xi[ii]);
-    // Hx term: the standardised column's own entropy moments
-    const float2 cx = vx[i0 + ii];
+  for (int ii = 0; ii < kTT; ++ii) {
+    load_x(ia0 + ii, xa[ii]);
+    // Hx term: the column's own entropy moments
+    const float2 cx = vx[ia0 + ii];
 #pragma unroll
     for (int e = 0; e < kBSpl; ++e)
-      acc[ii][e] = (double)dir_grad(xi[ii][e] * (float)kWScale, 2.f * cx.x, -cx.x, cx.y,
-                                    cx.y * (float)(-1.0 / (kWScale * kWScale)));
+      acc[ii][e] = (double)dir_grad(xa[ii][e] * (float)kWScale, 2.f * cx.x, -cx.x,
+                                    cx.y * (float)(-kExpMinusHalf / (kWScale * kWScale)));
+    slot[kTT * wave + ii][lane] = SlotT{};
   }
-  load_x(Xs, 0, xj);
 
-  for (int64_t j = 0; j < m; ++j) {
-    float xn[kBSpl];
-    load_x(Xs, j + 1 < m_pad ? j + 1 : j, xn);      // prefetch the next partner
-    const BwdPair* c4 = bp + j * m_pad + i0;
-    float rs[kBT];
+  for (int b = a; b < P; ++b) {
+    __syncthreads();     // the LDS rows are clear
+    const bool diag = b == a;
+    const int nround = diag ? kTW / 2 + 1 : kTW;
+    for (int r = 0; r < nround; ++r) {
+      const int y = (wave + r) & (kTW - 1);
+      const bool self = diag && r == 0;
+      const bool active = !diag || r < kTW / 2 || wave < kTW / 2;
+      if (active) {
+        const int64_t ib0 = (int64_t)b * kTK + kTT * y;
+        float rs[kTT * kTT];   // rho-chain partial of pair (ii, jj) at index 4 ii + jj
 #pragma unroll
-    for (int ii = 0; ii < kBT; ++ii) {
-      const BwdPair c = c4[ii];
-      float r = 0.f;
+        for (int k = 0; k < kTT * kTT; ++k) rs[k] = 0.f;
+        if (self) {
+          // pairs inside the own block, ii < jj: both sides are own rows
 #pragma unroll
-      for (int e = 0; e < kBSpl; ++e) {
-        const float x = xi[ii][e], y = xj[e];
-        const float w0 = fmaf(x, c.a, -(y * c.b));      // c u_ij
-        const float w1 = fmaf(y, c.a, -(x * c.b));      // c u_ji
-        const float g0 = dir_grad(w0, c.a2[0], c.na[0], c.bb[0], c.bq[0]);   // g_ij / s
-        const float g1 = dir_grad(w1, c.a2[1], c.na[1], c.bb[1], c.bq[1]);   // g_ji / s
-        acc[ii][e] += (double)fmaf(-c.rho, g1, g0);
-        // rho chain: (g_ij / s)(c u_ji) + (g_ji / s)(c u_ij), = -R_ij c / s summed over t
-        r = fmaf(g0, w1, fmaf(g1, w0, r));
+          for (int jj = 1; jj < kTT; ++jj) {
+            const BwdPair* c4 = bp + (ia0 + jj) * m_pad + ia0;
+#pragma unroll
+            for (int ii = 0; ii < jj; ++ii) {
+              const BwdPair c = c4[ii];
+#pragma unroll
+              for (int e = 0; e < kBSpl; ++e)
+                pair_terms(c, xa[ii][e], xa[jj][e], acc[ii][e], acc[jj][e], rs[kTT * ii + jj]);
+            }
+          }
+        } else {
+          float xb[kTT][kBSpl];
+          double accb[kTT][kBSpl];
+#pragma unroll
+          for (int jj = 0; jj < kTT; ++jj) {
+            load_x(ib0 + jj, xb[jj]);
+#pragma unroll
+            for (int e = 0; e < kBSpl; ++e) accb[jj][e] = 0.0;
+          }
+#pragma unroll
+          for (int jj = 0; jj < kTT; ++jj) {
+            const BwdPair* c4 = bp + (ib0 + jj) * m_pad + ia0;
+#pragma unroll
+            for (int ii = 0; ii < kTT; ++ii) {
+              const BwdPair c = c4[ii];
+#pragma unroll
+              for (int e = 0; e < kBSpl; ++e)
+                pair_terms(c, xa[ii][e], xb[jj][e], acc[ii][e], accb[jj][e], rs[kTT * ii + jj]);
+            }
+          }
+#pragma unroll
+          for (int jj = 0; jj < kTT; ++jj) {
+            SlotT sv = slot[kTT * y + jj][lane];
+            slot_add(sv, accb[jj]);
+            slot[kTT * y + jj][lane] = sv;
+          }
+        }
+        const float v = wave_reduce_scatter16(rs);   // sum over the chunk of pair lane >> 2
+        if ((lane & 3) == 0) {
+          const int p = lane >> 2, ii = p / kTT, jj = p % kTT;
+          const int64_t i = ia0 + ii, j = ib0 + jj;
+          if (i < m && j < m && (!self || ii < jj)) {
+            const int64_t lo = i < j ? i : j, hi = i < j ? j : i;
+            Rp[(chunk * m + lo) * m + hi] = v;
+          }
+        }
       }
-      rs[ii] = r;
+      __syncthreads();
     }
+    // this wave's 4 LDS rows: into the own sums (b = a) or out as partial a of block b
 #pragma unroll
-    for (int ii = 0; ii < kBT; ++ii) rs[ii] = wave_sum(rs[ii]);
-    if (lane < kBT) {
-      float v = rs[0];
+    for (int jj = 0; jj < kTT; ++jj) {
+      const SlotT sv = slot[kTT * wave + jj][lane];
+      double v[kBSpl];
+      slot_get(sv, v);
+      if (diag) {
 #pragma unroll
-      for (int ii = 1; ii < kBT; ++ii) v = lane == ii ? rs[ii] : v;
-      if (i0 + lane < j) Rp[(chunk * m + i0 + lane) * m + j] = v;    // j > i: one copy
+        for (int e = 0; e < kBSpl; ++e) acc[jj][e] += v[e];
+      } else {
+        store_spl(pd + pd_row((int64_t)b * kTK + kTT * wave + jj, a) * ldp, v);
+      }
+      slot[kTT * wave + jj][lane] = SlotT{};
     }
-#pragma unroll
-    for (int e = 0; e < kBSpl; ++e) xj[e] = xn[e];
   }
 #pragma unroll
-  for (int ii = 0; ii < kBT; ++ii)
-    *reinterpret_cast<float2*>(dx + (i0 + ii) * n_pad + tb) =
-        make_float2((float)acc[ii][0], (float)acc[ii][1]);
+  for (int ii = 0; ii < kTT; ++ii) store_spl(pd + pd_row(ia0 + ii, a) * ldp, acc[ii]);
+}
+
+// One window of the samples, columns [t0, t0 + nw) of dx: dx[v][t0 + t] = sum over the partials
+// p = 0 .. v / 32 (in order) of row pd_row(v, p) of Pd (row stride ldp), in FP64; 4 consecutive
+// samples a thread (nw, ldp, t0 and n_pad multiples of 4).
+__global__ void bwd_reduce_kernel(const float* __restrict__ Pd, int64_t m_pad, int64_t ldp,
+                                  int64_t nw, int64_t t0, int64_t n_pad,
+                                  float* __restrict__ dx) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nq = nw / 4;
+  if (q >= m_pad * nq) return;
+  const int64_t v = q / nq, t = (q - v * nq) * 4;
+  const int np = (int)(v / kTK) + 1;
+  const float* src = Pd + pd_row(v, 0) * ldp + t;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  auto add = [&](const float4& x4) {
+    s0 += x4.x;
+    s1 += x4.y;
+    s2 += x4.z;
+    s3 += x4.w;
+  };
+  int p = 0;
+  for (; p + 8 <= np; p += 8) {     // eight loads in flight, summed in order
+    float4 x4[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x4[k] = *reinterpret_cast<const float4*>(src + (p + k) * ldp);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) add(x4[k]);
+  }
+  for (; p < np; ++p) add(*reinterpret_cast<const float4*>(src + p * ldp));
+  *reinterpret_cast<float4*>(dx + v * n_pad + t0 + t) =
+      make_float4((float)s0, (float)s1, (float)s2, (float)s3);
 }
 
 // R[i][j] = R[j][i] = -(sum over chunks of Rp[c][i][j], i < j) / (c s n)  (FP64 sum), the
@@ -313,10 +462,15 @@ __global__ __launch_bounds__(256) void bwd_std_kernel(const float* __restrict__ 
 BwdPlan plan_backward(int64_t n_eff, int64_t m) {
   BwdPlan b;
   b.fwd = plan_pairwise(n_eff, m);
-  b.nt = (int)ceil_div(m, kBT);
-  b.m_pad = (int64_t)b.nt * kBT;
+  b.nblk = (int)ceil_div(m, kTK);
+  b.m_pad = (int64_t)b.nblk * kTK;
   b.nchunk = ceil_div(n_eff, kBChunk);
   b.n_pad = b.nchunk * kBChunk;
+  // sample windows of the pair pass, of equal length: its per-partner-block sums take at most
+  // kPdBytes
+  const int64_t per_chunk = pd_rows(b.nblk) * kBChunk * (int64_t)sizeof(float);
+  const int64_t most = std::max<int64_t>(1, kPdBytes / per_chunk);
+  b.win_chunks = b.nblk > 1 ? ceil_div(b.nchunk, ceil_div(b.nchunk, most)) : b.nchunk;
   return b;
 }
 
@@ -336,6 +490,8 @@ size_t bwd_ws_bytes(const BwdPlan& b, void* base, BwdWs* out) {
   w.bp = c.take<BwdPair>(b.m_pad * b.m_pad);
   w.vx = c.take<float2>(b.m_pad);
   w.dx = c.take<float>(b.m_pad * b.n_pad);
+  // one block of variables: the tile pass writes dx directly
+  w.Pd = b.nblk > 1 ? c.take<float>((size_t)pd_rows(b.nblk) * b.win_chunks * kBChunk) : w.dx;
   w.Rp = c.take<float>((size_t)b.nchunk * m * m);
   w.Rf = c.take<float>(b.m_pad * b.m_pad);
   w.sums = c.take<double>(2 * m);
@@ -368,16 +524,29 @@ int run_backward(const BwdPlan& b, const BwdWs& w, const float* E, int64_t lde, 
     bwd_pair_kernel<<<(unsigned)ceil_div(b.m_pad * b.m_pad, 256), 256, 0, stream>>>(
         cov, mom, G, m, b.m_pad, n_eff, w.bp);
     VL_LAUNCH_CHECK();
-    bwd_var_kernel<<<(unsigned)ceil_div(b.m_pad, 256), 256, 0, stream>>>(momx, G, m, b.m_pad,
-                                                                        n_eff, w.vx);
+    bwd_var_kernel<<<(unsigned)ceil_div(b.m_pad, 4), 256, 0, stream>>>(momx, G, m, b.m_pad,
+                                                                      n_eff, w.vx);
     VL_LAUNCH_CHECK();
   }
   {
-    ProfileScope ps("backward_owner", stream);
-    const int64_t items = (int64_t)b.nt * b.nchunk;
-    bwd_owner_kernel<<<(unsigned)ceil_div(items, 4), 256, 0, stream>>>(
-        w.Xs, b.n_pad, w.bp, w.vx, b.m_pad, m, b.nt, b.nchunk, w.dx, w.Rp);
-    VL_LAUNCH_CHECK();
+    // one block of variables: the tile pass writes dx directly (one window)
+    const int64_t ldp = b.nblk > 1 ? b.win_chunks * kBChunk : b.n_pad;
+    for (int64_t c0 = 0; c0 < b.nchunk; c0 += b.win_chunks) {
+      const int64_t nc = std::min(b.win_chunks, b.nchunk - c0);
+      {
+        ProfileScope ps("backward_pairs", stream);
+        bwd_tile_kernel<<<(unsigned)(b.nblk * nc), kTW * 64, 0, stream>>>(
+            w.Xs, b.n_pad, w.bp, w.vx, b.m_pad, m, b.nblk, c0, nc, w.Pd, ldp, w.Rp);
+        VL_LAUNCH_CHECK();
+      }
+      if (b.nblk > 1) {
+        ProfileScope ps("backward_reduce", stream);
+        const int64_t nq = b.m_pad * nc * kBChunk / 4;
+        bwd_reduce_kernel<<<(unsigned)ceil_div(nq, 256), 256, 0, stream>>>(
+            w.Pd, b.m_pad, ldp, nc * kBChunk, c0 * kBChunk, b.n_pad, w.dx);
+        VL_LAUNCH_CHECK();
+      }
+    }
   }
   {
     ProfileScope ps("backward_tail", stream);

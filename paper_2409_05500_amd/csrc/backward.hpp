@@ -9,10 +9,11 @@ struct BwdPair;   // per ordered pair constants of the transcendental pass (back
 
 struct BwdPlan {
   PairwisePlan fwd;        // forward recompute
-  int nt = 0;              // 4-variable blocks
-  int64_t m_pad = 0;       // nt * 4
+  int nblk = 0;            // 32-variable blocks (tile sides of the pair pass)
+  int64_t m_pad = 0;       // nblk * 32
   int64_t nchunk = 0;      // 128-sample chunks
   int64_t n_pad = 0;       // nchunk * 128
+  int64_t win_chunks = 0;  // chunks per launch of the pair pass (bounds its partial sums)
 };
 
 struct BwdWs {
@@ -26,6 +27,8 @@ struct BwdWs {
   BwdPair* bp = nullptr;   // m_pad x m_pad
   float2* vx = nullptr;    // m_pad: Hx-term coefficients
   float* dx = nullptr;     // m_pad x n_pad: dL/dx
+  float* Pd = nullptr;     // nblk x m_pad x (win_chunks * 128): dL/dx sums per partner block,
+                           // one sample window (dx itself if nblk = 1)
   float* Rp = nullptr;     // nchunk x m x m: per-chunk dL/drho partials
   float* Rf = nullptr;     // m_pad x m_pad: dL/drho / n
   double* sums = nullptr;  // 2 m: sum dx, sum dx x

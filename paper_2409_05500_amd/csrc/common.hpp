@@ -132,6 +132,33 @@ __device__ inline float wave_reduce_scatter64(float (&v)[64]) {
   return v[0];
 }
 
+// Reduce-scatter of 16 values held by every lane: on return lane l holds the sum over all 64
+// lanes of v[l >> 2] (the four lanes of a quad hold the same sum).  v is destroyed.  Levels as
+// in wave_reduce_scatter64 down to the half-row mirror (index bits 3..0 = lane bits 5..2); the
+// lanes of a quad then hold the same index over complementary lane sets and are summed.
+__device__ inline float wave_reduce_scatter16(float (&v)[16]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[k]), __float_as_uint(v[k + 8]),
+                                              false, false);
+    v[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[k]), __float_as_uint(v[k + 4]),
+                                              false, false);
+    v[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  const bool b3 = lane & 8, b2 = lane & 4;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) v[k] = rs_level_dpp<kDppRowMirror>(v[k], v[k + 2], b3);
+  float s = rs_level_dpp<kDppHalfMirror>(v[0], v[1], b2);
+  s += dpp_mov<kDppQuadXor2>(s);
+  s += dpp_mov<kDppQuadXor1>(s);
+  return s;
+}
+
 // v if keep, else +0.0, by masking the bits.  The mask is made opaque to the optimiser (an
 // empty asm statement on the mask, which no load feeds): otherwise it proves the masked value
 // dead and branches around the load that produces it, with a wait per load.

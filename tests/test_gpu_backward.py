@@ -10,7 +10,8 @@ coefficients, exp2 and rcp approximations good to 1 ulp): K_ULP = 16 units.  The
 from the forward pass, whose FP32 sums leave them accurate to DA = 1e-7 (the bound the forward
 tests use).  The sum for dL/dx_i(t) is ill-conditioned by construction (each pair term follows
 Hr_ij - Hx_i, a small difference): on the m = 1000 Laplace workload mag is ~500 times |dE|.
-The partner sums run in FP64 on the GPU, so rounding does not accumulate with m.  Any dropped
+The partner sums run in FP64 on the GPU (FP32 only for the per-row partials of the pair pass,
+one per 32-variable block), so rounding does not accumulate with m.  Any dropped
 or mis-signed term moves dE by far more than the bound (>= 1e-1 of max|dE|).
 """
 import numpy as np
@@ -67,7 +68,7 @@ def _check(dE, E32, G, ref=None, cols=None, rel_max=None):
 
 
 @pytest.mark.parametrize("m,n", [(2, 37), (3, 17), (4, 512), (6, 700), (13, 1537), (33, 2100),
-                                 (64, 1025)])
+                                 (64, 1025), (97, 901), (131, 1000)])
 @pytest.mark.parametrize("prec", ["mixed", "fp32"])
 def test_backward_matches_autograd_reference(api, dev, m, n, prec):
     print(f"backward m={m} n={n} prec={prec}", flush=True)
@@ -121,9 +122,12 @@ def test_backward_full_size_sampled_columns(api, dev):
     assert torch.count_nonzero(api.pairwise_stats_backward(Ed, _dev(Gs, dev))).item() == 0
 
 
-def test_backward_deterministic(api, dev):
-    E = _dev(_residuals(37, 3000, 1), dev)
-    G = _dev(np.random.default_rng(2).normal(size=(37, 37)), dev)
+@pytest.mark.parametrize("m", [37, 100])
+def test_backward_deterministic(api, dev, m):
+    """Bit-identical repeats: one tile of variable blocks (m = 37) and several (m = 100), whose
+    sums meet in a fixed order."""
+    E = _dev(_residuals(m, 3000, 1), dev)
+    G = _dev(np.random.default_rng(2).normal(size=(m, m)), dev)
     a = api.pairwise_stats_backward(E, G)
     b = api.pairwise_stats_backward(E, G)
     assert torch.equal(a, b)
