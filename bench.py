@@ -35,8 +35,8 @@ TRANS_PER_EVAL = 3
 # exactly: x1).  Keyed by the SHA-256 of the kernel sources the counters were taken with
 # (kernel_source_digest); any other source reports null.
 MEASURED_TRAFFIC = {
-    # FETCH_SIZE 35186.4 KiB x 2, WRITE_SIZE 8547.2 KiB x 1 per dispatch (18 dispatches)
-    "0aad8ec81e63ac74d3c8332c3f56b6255d63b711c76380dd155f276db58dd332": 80814148,
+    # FETCH_SIZE 35164.7 KiB x 2, WRITE_SIZE 8546.2 KiB x 1 per dispatch (18 dispatches)
+    "39a8eef9fcc8ebb7e1bc804bd862522873d06c7fcea76aa0e8cda18e188e874f": 80768661,
 }
 STAGES = ("var_gram", "var_solve", "var_residual", "var_refine", "pairwise_cov",
           "pairwise_prep", "pairwise_moments", "pairwise_combine", "order", "estimate_b")
@@ -588,13 +588,26 @@ def main():
             bf16_stage_ms[st] = round(ms / cnt, 4)
     _lib.profile_enable(None)
 
+    # MIXED with the compensated moment sums (VL_PAIRWISE_COMPENSATED): whole fit and its
+    # moment kernel
+    fc = api.Fitter(n, m, p, "mixed", dev, compensated=True)
+    for _ in range(args.warmup):
+        fc.run(X)
+    _lib.profile_enable("pairwise_moments")
+    comp_s = time_steps(fc, X, args.steps, torch)
+    cms, ccount = _lib.profile_read("pairwise_moments")
+    _lib.profile_enable(None)
+    fc.check()
+
     def b_rel(a, b):
         return float((a - b).abs().max() / max(float(b.abs().max()), 1e-2))
     def dist(o):
         return {"B0_rel": b_rel(o.B0, fit.B0), "B_lags_rel": b_rel(o.B_lags, fit.B_lags),
                 "same_order": bool(torch.equal(o.order, fit.order))}
     bf16_dev = dist(bf)
-    modes_vs_mixed = {"fp32": dist(f32), "fp32_refined": dist(f32r), "bf16": bf16_dev}
+    modes_vs_mixed = {"fp32": dist(f32), "fp32_refined": dist(f32r), "bf16": bf16_dev,
+                      "mixed_compensated": dict(dist(fc), S_max_abs_diff=float(
+                          (fc.S - fit.S).abs().max()))}
 
     # measured issue rates of this part (the roofline denominators' check)
     rates = api.probe_rates(dev)
@@ -635,6 +648,8 @@ def main():
         "fit_ms_fp32": fp32_s * 1e3,
         "fit_ms_fp32_refined": fp32r_s * 1e3,
         "fit_ms_bf16": bf16_s * 1e3,
+        "fit_ms_mixed_compensated": comp_s * 1e3,
+        "pairwise_kernel_ms_compensated": cms / ccount,
         "bf16_stage_ms": bf16_stage_ms,
         "bf16_vs_mixed": bf16_dev,
         "modes_vs_mixed": modes_vs_mixed,

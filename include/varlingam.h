@@ -61,12 +61,21 @@ typedef enum {
  *                  refinement step as in VL_PREC_BF16 (same convergence check), residual GEMM
  *                  and covariance as MIXED.  The cheapest form on the FP32 Gram that meets
  *                  the FP64 solution's accuracy.
- * The batched fit takes FP32 and MIXED only. */
+ * The batched fit takes FP32 and MIXED only.
+ *   VL_PAIRWISE_COMPENSATED: a flag OR-ed into the precision of pairwise_stats,
+ *                  pairwise_stats_noalloc and pairwise_stats_workspace_bytes (no other call
+ *                  takes it).  The pairwise moments are summed per lane with Kahan
+ *                  compensation (Sec. 3 step 3, Eq. 2: the two sample means of each ordered
+ *                  pair), reduced across the wave and stored per chunk in FP64, so their
+ *                  rounding no longer grows with the samples a lane sums; the per-sample
+ *                  evaluation stays FP32.  Costs six VALU operations more per pair, sample and
+ *                  direction, and twice the chunk partials' workspace. */
 typedef enum {
   VL_PREC_FP32 = 0,
   VL_PREC_MIXED = 1,
   VL_PREC_BF16 = 2,
-  VL_PREC_FP32_REFINED = 3
+  VL_PREC_FP32_REFINED = 3,
+  VL_PAIRWISE_COMPENSATED = 16
 } vl_precision;
 
 /* Human-readable name of a status code (static string, never NULL). */

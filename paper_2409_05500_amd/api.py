@@ -95,11 +95,18 @@ def select_lag(X: torch.Tensor, p_max: int, status: "DeviceStatus | None" = None
     return logdet, aic, bic, (int(b[0]), int(b[1]))
 
 
-def pairwise_stats(E: torch.Tensor, prec="mixed", status: "DeviceStatus | None" = None):
-    """Hx [m], Hr [m, m], S [m, m], Cov [m, m] (all f64) from the n_eff x m residuals."""
+def _pairwise_prec(prec, compensated: bool) -> int:
+    return _prec(prec) | (_lib.PAIRWISE_COMPENSATED if compensated else 0)
+
+
+def pairwise_stats(E: torch.Tensor, prec="mixed", status: "DeviceStatus | None" = None,
+                   compensated: bool = False):
+    """Hx [m], Hr [m, m], S [m, m], Cov [m, m] (all f64) from the n_eff x m residuals.
+    compensated: Kahan-compensated moment sums with FP64 partials (VL_PAIRWISE_COMPENSATED)."""
     _require(E, torch.float32, "E")
     n_eff, m = E.shape
     dev = E.device
+    prec = _pairwise_prec(prec, compensated)
     Hx = torch.empty(m, dtype=torch.float64, device=dev)
     Hr = torch.empty((m, m), dtype=torch.float64, device=dev)
     S = torch.empty((m, m), dtype=torch.float64, device=dev)
@@ -116,10 +123,11 @@ def pairwise_stats(E: torch.Tensor, prec="mixed", status: "DeviceStatus | None" 
 
 
 def pairwise_stats_noalloc(E: torch.Tensor, prec="mixed", status: "DeviceStatus | None" = None,
-                           out=None):
+                           out=None, compensated: bool = False):
     """pairwise_stats through the entry point that takes no workspace (the library's static
     per-GPU scratch).  `out` may hold preallocated (Hx, Hr, S, Cov) f64 device tensors, so that
     the call itself allocates nothing."""
+    prec = _pairwise_prec(prec, compensated)
     _require(E, torch.float32, "E")
     n_eff, m = E.shape
     dev = E.device
@@ -411,9 +419,13 @@ class Fitter:
 
     STAGES = ("varlingam_fit_var", "pairwise_stats", "approx_order", "estimate_B")
 
-    def __init__(self, n: int, m: int, p: int, prec="mixed", device="cuda:0"):
+    def __init__(self, n: int, m: int, p: int, prec="mixed", device="cuda:0",
+                 compensated: bool = False):
+        """compensated: the precompute's moment sums with Kahan compensation (the
+        VL_PAIRWISE_COMPENSATED flag on its pairwise_stats call)."""
         dev = torch.device(device)
         self.n, self.m, self.p, self.prec, self.dev = n, m, p, _prec(prec), dev
+        self.pw_prec = _pairwise_prec(prec, compensated)
         f64 = dict(dtype=torch.float64, device=dev)
         self.M = torch.empty((p, m, m), **f64)
         self.intercept = torch.empty(m, **f64)
@@ -427,7 +439,7 @@ class Fitter:
         self.B0 = torch.empty((m, m), **f64)
         self.B_lags = torch.empty((p, m, m), **f64)
         need = max(lib.varlingam_fit_var_workspace_bytes(n, m, p, self.prec),
-                   lib.pairwise_stats_workspace_bytes(n - p, m, self.prec),
+                   lib.pairwise_stats_workspace_bytes(n - p, m, self.pw_prec),
                    lib.approx_order_workspace_bytes(m), lib.estimate_B_workspace_bytes(m, p))
         if need == 0:
             raise ValueError(f"unsupported shape n={n} m={m} p={p}")
@@ -445,9 +457,9 @@ class Fitter:
         check(lib.varlingam_fit_var(X.data_ptr(), n, m, X.stride(0), p, pr, self.M.data_ptr(),
                                     self.intercept.data_ptr(), self.E.data_ptr(), m, ws, nb, st,
                                     s), "varlingam_fit_var")
-        check(lib.pairwise_stats(self.E.data_ptr(), n - p, m, m, pr, self.Hx.data_ptr(),
-                                 self.Hr.data_ptr(), self.S.data_ptr(), self.Cov.data_ptr(), ws,
-                                 nb, st + 4, s), "pairwise_stats")
+        check(lib.pairwise_stats(self.E.data_ptr(), n - p, m, m, self.pw_prec,
+                                 self.Hx.data_ptr(), self.Hr.data_ptr(), self.S.data_ptr(),
+                                 self.Cov.data_ptr(), ws, nb, st + 4, s), "pairwise_stats")
         check(lib.approx_order(self.S.data_ptr(), m, self.order.data_ptr(),
                                self.margin.data_ptr(), ws, nb, st + 8, s), "approx_order")
         check(lib.estimate_B(self.Cov.data_ptr(), self.M.data_ptr(), self.order.data_ptr(), m, p,

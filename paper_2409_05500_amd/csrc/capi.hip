@@ -23,6 +23,11 @@ inline bool valid_prec(int prec) {
          prec == VL_PREC_FP32_REFINED;
 }
 
+// The precompute's entry points also take the compensated-sum flag.
+inline bool valid_pairwise_prec(int prec) { return valid_prec(prec & ~VL_PAIRWISE_COMPENSATED); }
+inline bool compensated(int prec) { return (prec & VL_PAIRWISE_COMPENSATED) != 0;
+}
+
 inline bool aligned256(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
 
 int begin(int32_t* dev_status, hipStream_t stream) {
@@ -120,18 +125,18 @@ int varlingam_select_lag(const float* X, int64_t n, int64_t m, int64_t ldx, int 
 
 // ----------------------------------------------------------------------------------------
 size_t pairwise_stats_workspace_bytes(int64_t n_eff, int64_t m, int prec) {
-  (void)prec;
-  if (m < 2 || n_eff < 2 || m > 65536) return 0;
-  return pairwise_ws_bytes(plan_pairwise(n_eff, m), nullptr, nullptr);
+  if (m < 2 || n_eff < 2 || m > 65536 || !valid_pairwise_prec(prec)) return 0;
+  return pairwise_ws_bytes(plan_pairwise(n_eff, m, compensated(prec)), nullptr, nullptr);
 }
 
 int pairwise_stats(const float* E, int64_t n_eff, int64_t m, int64_t lde, int prec, double* Hx,
                    double* Hr, double* S, double* Cov, void* ws, size_t ws_bytes,
                    int32_t* dev_status, void* stream) {
-  if (!E || !Hx || !Hr || !S || !dev_status || !valid_prec(prec)) return VL_ERR_INVALID_ARG;
+  if (!E || !Hx || !Hr || !S || !dev_status || !valid_pairwise_prec(prec))
+    return VL_ERR_INVALID_ARG;
   if (m < 2 || n_eff < 2 || m > 65536) return VL_ERR_SHAPE;
   if (lde < m) return VL_ERR_INVALID_ARG;
-  const PairwisePlan p = plan_pairwise(n_eff, m);
+  const PairwisePlan p = plan_pairwise(n_eff, m, compensated(prec));
   const size_t need = pairwise_ws_bytes(p, nullptr, nullptr);
   if (!ws || ws_bytes < need || !aligned256(ws)) return VL_ERR_WORKSPACE;
   PairwiseWs w;
@@ -147,10 +152,11 @@ size_t pairwise_stats_noalloc_max_bytes(void) { return kNoAllocScratchBytes; }
 int pairwise_stats_noalloc(const float* E, int64_t n_eff, int64_t m, int64_t lde, int prec,
                            double* Hx, double* Hr, double* S, double* Cov, int32_t* dev_status,
                            void* stream) {
-  if (!E || !Hx || !Hr || !S || !dev_status || !valid_prec(prec)) return VL_ERR_INVALID_ARG;
+  if (!E || !Hx || !Hr || !S || !dev_status || !valid_pairwise_prec(prec))
+    return VL_ERR_INVALID_ARG;
   if (m < 2 || n_eff < 2 || m > 65536) return VL_ERR_SHAPE;
   if (lde < m) return VL_ERR_INVALID_ARG;
-  const PairwisePlan p = plan_pairwise(n_eff, m);
+  const PairwisePlan p = plan_pairwise(n_eff, m, compensated(prec));
   if (pairwise_ws_bytes(p, nullptr, nullptr) > kNoAllocScratchBytes) return VL_ERR_WORKSPACE;
   void* ws = nullptr;
   int rc = scratch_address(&ws);

@@ -132,6 +132,59 @@ __device__ inline float wave_reduce_scatter64(float (&v)[64]) {
   return v[0];
 }
 
+// The FP64 form of wave_reduce_scatter64 (same levels and lane pairing; each double moves as
+// its two 32-bit halves).
+template <int kCtrl>
+__device__ inline double dpp_mov_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), kCtrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), kCtrl, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int kCtrl>
+__device__ inline double rs_level_dpp_d(double keep_lo, double keep_hi, bool upper) {
+  const double send = upper ? keep_lo : keep_hi;
+  const double keep = upper ? keep_hi : keep_lo;
+  return keep + dpp_mov_d<kCtrl>(send);
+}
+
+// One permlane swap level on doubles: lanes of the lower group keep a (summed with the
+// partner's a), lanes of the upper group keep b.
+template <bool k32>
+__device__ inline double swap_level_d(double a, double b) {
+  const unsigned long long ua = (unsigned long long)__double_as_longlong(a);
+  const unsigned long long ub = (unsigned long long)__double_as_longlong(b);
+  auto swap = [](unsigned x, unsigned y) {
+    if constexpr (k32)
+      return __builtin_amdgcn_permlane32_swap(x, y, false, false);
+    else
+      return __builtin_amdgcn_permlane16_swap(x, y, false, false);
+  };
+  const auto lo = swap((unsigned)ua, (unsigned)ub);
+  const auto hi = swap((unsigned)(ua >> 32), (unsigned)(ub >> 32));
+  auto make = [](unsigned l, unsigned h) {
+    return __longlong_as_double((long long)(((unsigned long long)h << 32) | l));
+  };
+  return make(lo[0], hi[0]) + make(lo[1], hi[1]);
+}
+
+__device__ inline double wave_reduce_scatter64_d(double (&v)[64]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < 32; ++k) v[k] = swap_level_d<true>(v[k], v[k + 32]);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = swap_level_d<false>(v[k], v[k + 16]);
+  const bool b3 = lane & 8, b2 = lane & 4, b1 = lane & 2, b0 = lane & 1;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = rs_level_dpp_d<kDppRowMirror>(v[k], v[k + 8], b3);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v[k] = rs_level_dpp_d<kDppHalfMirror>(v[k], v[k + 4], b2);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) v[k] = rs_level_dpp_d<kDppQuadXor2>(v[k], v[k + 2], b1);
+  return rs_level_dpp_d<kDppQuadXor1>(v[0], v[1], b0);
+}
+
 // Reduce-scatter of 16 values held by every lane: on return lane l holds the sum over all 64
 // lanes of v[l >> 2] (the four lanes of a quad hold the same sum).  v is destroyed.  Levels as
 // in wave_reduce_scatter64 down to the half-row mirror (index bits 3..0 = lane bits 5..2); the

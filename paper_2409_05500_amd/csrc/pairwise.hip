@@ -58,26 +58,33 @@ __global__ __launch_bounds__(kHxThreads) void prep_kernel(
 
 // Blocks are remapped so that XCD x (block id mod 8) processes a contiguous range of items in
 // chunk-major order, i.e. mostly one sample chunk per XCD and its L2.
+// TP = float: plain FP32 moment sums; TP = double: compensated sums, FP64 partials.
+template <class TP>
 __global__ __launch_bounds__(256) void pairwise_moments_kernel(
     const float* __restrict__ Xs, int64_t n_pad, const float2* __restrict__ coef, int64_t m_pad,
     int64_t m, int nt, int64_t tiles, int chunk_len, int64_t items,
-    float* __restrict__ partU, float* __restrict__ partB) {
+    TP* __restrict__ partU, TP* __restrict__ partB) {
   const int64_t nb = gridDim.x;                     // a multiple of 8
   const int64_t b = blockIdx.x;
   const int64_t lb = (b & 7) * (nb >> 3) + (b >> 3);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t item = lb * 4 + wave;
   if (item >= items) return;
-  pairwise_moments_item(Xs, n_pad, coef, m_pad, m, nt, tiles, chunk_len, item, partU, partB);
+  if constexpr (std::is_same<TP, double>::value)
+    pairwise_moments_item_comp(Xs, n_pad, coef, m_pad, m, nt, tiles, chunk_len, item, partU,
+                               partB);
+  else
+    pairwise_moments_item(Xs, n_pad, coef, m_pad, m, nt, tiles, chunk_len, item, partU, partB);
 }
 
 // The (listed tile, chunk) items of the near-collinear micro-tiles, grid-stride over the list
 // the coefficient stage built (count = clist[tiles]); with no listed tile every wave returns
 // at once.
+template <class TP>
 __global__ __launch_bounds__(256) void pairwise_collinear_kernel(
     const float* __restrict__ E, int64_t lde, int64_t n_eff, const double* __restrict__ mu,
     const double* __restrict__ cov, int64_t m, int nt, int64_t tiles, int nc, int chunk_len,
-    const int32_t* __restrict__ clist, float* __restrict__ partU, float* __restrict__ partB) {
+    const int32_t* __restrict__ clist, TP* __restrict__ partU, TP* __restrict__ partB) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t total = (int64_t)clist[tiles] * nc;
   for (int64_t w = (int64_t)blockIdx.x * 4 + wave; w < total; w += (int64_t)gridDim.x * 4) {
@@ -87,7 +94,8 @@ __global__ __launch_bounds__(256) void pairwise_collinear_kernel(
   }
 }
 
-__global__ void combine_hr_kernel(const float* __restrict__ partU, const float* __restrict__ partB,
+template <class TP>
+__global__ void combine_hr_kernel(const TP* __restrict__ partU, const TP* __restrict__ partB,
                                   int nc, int64_t m, int64_t n_eff, double* __restrict__ Hr,
                                   double* __restrict__ mom) {
   combine_hr_elem(partU, partB, nc, m, n_eff, Hr, mom,
@@ -106,8 +114,9 @@ __global__ void score_kernel(const double* __restrict__ Hx, const double* __rest
 // samples (4 steps of 2 samples per lane), chunks a multiple of 128.  Measured at one launch
 // per fit: m = 400 (n = 10^4) within 1% of the best chunk count, m = 1000 (n = 5 10^4) within
 // 0.5%, m = 100 (n = 5000) within 4% (a floor of 2048 samples per chunk was 49% slower there).
-PairwisePlan plan_pairwise(int64_t n_eff, int64_t m) {
+PairwisePlan plan_pairwise(int64_t n_eff, int64_t m, bool compensated) {
   PairwisePlan p;
+  p.comp = compensated;
   p.m = m;
   p.n_eff = n_eff;
   p.nt = (int)ceil_div(m, kT);
@@ -137,8 +146,15 @@ size_t pairwise_ws_bytes(const PairwisePlan& p, void* base, PairwiseWs* out) {
   Carver b(region);                              // stages 2-5
   w.Xs = b.take<float>(p.m_pad * p.n_pad);
   w.coef = b.take<float2>(p.m_pad * p.m_pad);
-  w.partU = b.take<float>((size_t)p.nc * p.m * p.m);
-  w.partB = b.take<float>((size_t)p.nc * p.m * p.m);
+  // FP32 partials, or FP64 ones for the compensated sums (the same region either way)
+  const size_t np = (size_t)p.nc * p.m * p.m;
+  if (p.comp) {
+    w.partU64 = b.take<double>(np);
+    w.partB64 = b.take<double>(np);
+  } else {
+    w.partU = b.take<float>(np);
+    w.partB = b.take<float>(np);
+  }
   w.clist = b.take<int32_t>(2 * p.tiles + 1);
   if (out) *out = w;
   return c.used + std::max(a.used, b.used);
@@ -160,6 +176,37 @@ int standardize_to(const float* E, int64_t lde, int64_t n_eff, int64_t m, const 
   return VL_OK;
 }
 
+// Stages 4-5 with FP32 (plain sums) or FP64 (compensated sums) partials.
+template <class TP>
+static int launch_moments(const PairwisePlan& p, const PairwiseWs& w, const float* E,
+                          int64_t lde, const double* cov, const double* Hx, double* Hr,
+                          double* S, double* mom, TP* partU, TP* partB, hipStream_t stream) {
+  const int64_t m = p.m, n_eff = p.n_eff;
+  {
+    ProfileScope ps("pairwise_moments", stream);
+    pairwise_moments_kernel<TP><<<(unsigned)p.blocks, 256, 0, stream>>>(
+        w.Xs, p.n_pad, w.coef, p.m_pad, m, p.nt, p.tiles, p.chunk_len, p.items, partU, partB);
+    VL_LAUNCH_CHECK();
+  }
+  {
+    ProfileScope ps("pairwise_collinear", stream);
+    const int64_t blocks = std::min<int64_t>(ceil_div(p.items, 4), 256);
+    pairwise_collinear_kernel<TP><<<(unsigned)blocks, 256, 0, stream>>>(
+        E, lde, n_eff, w.mu, cov, m, p.nt, p.tiles, p.nc, p.chunk_len, w.clist, partU,
+        partB);
+    VL_LAUNCH_CHECK();
+  }
+  {
+    ProfileScope ps("pairwise_combine", stream);
+    combine_hr_kernel<TP><<<(unsigned)ceil_div(m * m, 256), 256, 0, stream>>>(
+        partU, partB, p.nc, m, n_eff, Hr, mom);
+    VL_LAUNCH_CHECK();
+    score_kernel<<<(unsigned)ceil_div(m * m, 256), 256, 0, stream>>>(Hx, Hr, m, S);
+    VL_LAUNCH_CHECK();
+  }
+  return VL_OK;
+}
+
 int run_pairwise(const PairwisePlan& p, const PairwiseWs& w, const float* E, int64_t lde,
                  int prec, double* Hx, double* Hr, double* S, double* Cov, double* mom,
                  int32_t* st, hipStream_t stream) {
@@ -170,8 +217,9 @@ int run_pairwise(const PairwisePlan& p, const PairwiseWs& w, const float* E, int
     int rc = colmeans(E, lde, nullptr, m, n_eff, w.mu, w.scratch, st, stream);
     if (rc) return rc;
     // covariance: exact products and FP64 sums (plain FP32 mode: FP32 MFMA throughout)
+    const bool fp32 = (prec & ~VL_PAIRWISE_COMPENSATED) == VL_PREC_FP32;
     rc = gram_tn(E, lde, nullptr, w.mu, m, E, lde, nullptr, w.mu, m, n_eff,
-                 prec == VL_PREC_FP32 ? GramMode::kFp32 : GramMode::kFp64, 1.0 / (double)n_eff,
+                 fp32 ? GramMode::kFp32 : GramMode::kFp64, 1.0 / (double)n_eff,
                  cov, m, w.scratch, stream, true);
     if (rc) return rc;
   }
@@ -185,30 +233,9 @@ int run_pairwise(const PairwisePlan& p, const PairwiseWs& w, const float* E, int
                                p.tiles, w.clist, st);
     VL_LAUNCH_CHECK();
   }
-  {
-    ProfileScope ps("pairwise_moments", stream);
-    pairwise_moments_kernel<<<(unsigned)p.blocks, 256, 0, stream>>>(
-        w.Xs, p.n_pad, w.coef, p.m_pad, m, p.nt, p.tiles, p.chunk_len, p.items, w.partU,
-        w.partB);
-    VL_LAUNCH_CHECK();
-  }
-  {
-    ProfileScope ps("pairwise_collinear", stream);
-    const int64_t blocks = std::min<int64_t>(ceil_div(p.items, 4), 256);
-    pairwise_collinear_kernel<<<(unsigned)blocks, 256, 0, stream>>>(
-        E, lde, n_eff, w.mu, cov, m, p.nt, p.tiles, p.nc, p.chunk_len, w.clist, w.partU,
-        w.partB);
-    VL_LAUNCH_CHECK();
-  }
-  {
-    ProfileScope ps("pairwise_combine", stream);
-    combine_hr_kernel<<<(unsigned)ceil_div(m * m, 256), 256, 0, stream>>>(
-        w.partU, w.partB, p.nc, m, n_eff, Hr, mom);
-    VL_LAUNCH_CHECK();
-    score_kernel<<<(unsigned)ceil_div(m * m, 256), 256, 0, stream>>>(Hx, Hr, m, S);
-    VL_LAUNCH_CHECK();
-  }
-  return VL_OK;
+  if (p.comp)
+    return launch_moments(p, w, E, lde, cov, Hx, Hr, S, mom, w.partU64, w.partB64, stream);
+  return launch_moments(p, w, E, lde, cov, Hx, Hr, S, mom, w.partU, w.partB, stream);
 }
 
 }  // namespace vl

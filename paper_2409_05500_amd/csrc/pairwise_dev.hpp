@@ -1,6 +1,8 @@
 // Device bodies of the pairwise-statistic precompute (Sec. 4.2 steps 1-2), shared by the
 // single-problem kernels and the batched kernels.
 #pragma once
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace vl {
@@ -169,7 +171,8 @@ __device__ inline void pair_coef_elem(const double* __restrict__ cov, int64_t m,
 //     Uacc += c ln2 (log2 P - count),  P = 1
 // which leaves Uacc = c * sum log cosh u exactly in real arithmetic.  Zero-padded samples
 // give w = 0, t = 1, factor 2: they add exactly 0 to Uacc and Bacc.
-// Two transcendentals and seven other VALU operations per (pair, sample, direction).
+// Two transcendentals and seven other VALU operations per (pair, sample, direction); the
+// compensated variant adds three per sum (Kahan), 13 in all.
 //
 // At the end the 2 x 2 x kT x kT wave sums are formed by a reduce-scatter (lane l ends with
 // value l) and written to per-chunk FP32 partials part{U,B}[chunk][row][col].
@@ -186,29 +189,109 @@ __device__ __forceinline__ void moment_step(float w, float& U, float& P, float& 
   U += aw;
 }
 
+// Kahan accumulation s += x: the true sum is s - c.
+__device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
+  const float y = x - c;
+  const float t = s + y;
+  c = (t - s) - y;
+  s = t;
+}
+
+// The moment accumulators of one (pair, direction), fed w = c u sample by sample: U sums |w|
+// (and at each flush the log term of the running product P), B sums w e.  Plain FP32 sums
+// (Comp = false), or Kahan-compensated ones (Comp = true): the compensation terms cU, cB keep
+// a lane's sums within a few units of their last place whatever the sample count, where a
+// plain running sum's rounding grows with it.
+template <bool Comp>
+struct MomentAcc;
+
+template <>
+struct MomentAcc<false> {
+  float U, P, B;
+  __device__ __forceinline__ void init() {
+    U = 0.f;
+    P = 1.f;
+    B = 0.f;
+  }
+  __device__ __forceinline__ void step(float w) {
+    const float q = w * w;
+    const float e = __builtin_amdgcn_exp2f(-q);
+    B = fmaf(w, e, B);
+    const float aw = fabsf(w);
+    const float t = __builtin_amdgcn_exp2f(aw * (float)kTScale);
+    P = fmaf(P, t, P);
+    U += aw;
+  }
+  __device__ __forceinline__ void flush(float cnt, float cln2) {
+    U = fmaf(__builtin_amdgcn_logf(P) - cnt, cln2, U);
+    P = 1.f;
+  }
+  __device__ __forceinline__ float u() const { return U; }
+  __device__ __forceinline__ float b() const { return B; }
+};
+
+template <>
+struct MomentAcc<true> {
+  float U, cU, P, B, cB;
+  __device__ __forceinline__ void init() {
+    U = cU = B = cB = 0.f;
+    P = 1.f;
+  }
+  __device__ __forceinline__ void step(float w) {
+    const float q = w * w;
+    const float e = __builtin_amdgcn_exp2f(-q);
+    const float yb = fmaf(w, e, -cB);      // the product enters with one rounding
+    const float tb = B + yb;
+    cB = (tb - B) - yb;
+    B = tb;
+    const float aw = fabsf(w);
+    const float t = __builtin_amdgcn_exp2f(aw * (float)kTScale);
+    P = fmaf(P, t, P);
+    kahan_add(U, cU, aw);
+  }
+  __device__ __forceinline__ void flush(float cnt, float cln2) {
+    const float y = fmaf(__builtin_amdgcn_logf(P) - cnt, cln2, -cU);
+    const float t = U + y;
+    cU = (t - U) - y;
+    U = t;
+    P = 1.f;
+  }
+  __device__ __forceinline__ double u() const { return (double)U - (double)cU; }
+  __device__ __forceinline__ double b() const { return (double)B - (double)cB; }
+};
+
 // Writes the 2 x 2 x kT x kT wave sums of one item: a reduce-scatter (lane l ends with value
-// l), then the chunk partials part{U,B}[chunk][row][col] of the valid ordered pairs.
-__device__ __forceinline__ void write_moment_partials(
-    float (&U)[2][kT][kT], float (&B)[2][kT][kT], int64_t i0, int64_t j0, int64_t m,
-    int64_t chunk, float* __restrict__ partU, float* __restrict__ partB) {
+// l), then the chunk partials part{U,B}[chunk][row][col] of the valid ordered pairs.  FP32
+// partials take the plain sums (FP32 reduce-scatter); FP64 partials the compensated ones
+// (each lane's exact value U - cU in FP64, FP64 reduce-scatter).
+template <class TP, bool Comp>
+__device__ __forceinline__ void write_moment_partials(MomentAcc<Comp> (&acc)[2][kT][kT],
+                                                      int64_t i0, int64_t j0, int64_t m,
+                                                      int64_t chunk, TP* __restrict__ partU,
+                                                      TP* __restrict__ partB) {
+  static_assert(std::is_same<TP, double>::value == Comp, "FP64 partials with compensation");
   const int lane = threadIdx.x & 63;
   // value index v = kind*32 + d*16 + ii*4 + jj (kind 0: U, 1: B)
-  float v[64];
+  TP v[64];
 #pragma unroll
   for (int d = 0; d < 2; ++d)
 #pragma unroll
     for (int ii = 0; ii < kT; ++ii)
 #pragma unroll
       for (int jj = 0; jj < kT; ++jj) {
-        v[d * 16 + ii * 4 + jj] = U[d][ii][jj];
-        v[32 + d * 16 + ii * 4 + jj] = B[d][ii][jj];
+        v[d * 16 + ii * 4 + jj] = acc[d][ii][jj].u();
+        v[32 + d * 16 + ii * 4 + jj] = acc[d][ii][jj].b();
       }
-  const float sum = wave_reduce_scatter64(v);
+  TP sum;
+  if constexpr (Comp)
+    sum = wave_reduce_scatter64_d(v);
+  else
+    sum = wave_reduce_scatter64(v);
   const int kind = lane >> 5, d = (lane >> 4) & 1, ii = (lane >> 2) & 3, jj = lane & 3;
   const int64_t i = i0 + ii, j = j0 + jj;
   if (i < m && j < m && i != j) {
     const int64_t row = d ? j : i, col = d ? i : j;
-    float* dst = kind ? partB : partU;
+    TP* dst = kind ? partB : partU;
     dst[chunk * m * m + row * m + col] = sum;
   }
 }
@@ -326,15 +409,107 @@ __device__ __attribute__((always_inline)) inline void pairwise_moments_item(
   }
 }
 
+// The same work item with Kahan-compensated sums and FP64 partials (231 VGPRs, 2 waves per
+// SIMD).  A separate body: folding both forms into one template changed the schedule the
+// compiler chose for the plain one (6% slower).
+__device__ __attribute__((always_inline)) inline void pairwise_moments_item_comp(
+    const float* __restrict__ Xs, int64_t n_pad, const float2* __restrict__ coef, int64_t m_pad,
+    int64_t m, int nt, int64_t tiles, int chunk_len, int64_t item,
+    double* __restrict__ partU, double* __restrict__ partB) {
+  constexpr bool Comp = true;
+  const int lane = threadIdx.x & 63;
+  const int64_t chunk = item / tiles;
+  const int64_t tile = item - chunk * tiles;
+  int bi, bj;
+  tile_coords(tile, nt, bi, bj);
+  const int64_t i0 = (int64_t)bi * kT, j0 = (int64_t)bj * kT;
+
+  float ca[kT][kT], cb[kT][kT];
+#pragma unroll
+  for (int ii = 0; ii < kT; ++ii)
+#pragma unroll
+    for (int jj = 0; jj < kT; ++jj) {
+      // read-only for this kernel: the constant address space lets these wave-uniform loads
+      // be scalar loads into SGPRs whatever the pointer's provenance
+      typedef const __attribute__((address_space(4))) float* const_f32p;
+      const const_f32p cp = (const_f32p)(uintptr_t)coef;
+      const int64_t ci = 2 * ((i0 + ii) * m_pad + j0 + jj);
+      const float2 c = make_float2(cp[ci], cp[ci + 1]);
+      ca[ii][jj] = c.x;
+      cb[ii][jj] = c.y;
+    }
+
+  MomentAcc<Comp> acc[2][kT][kT];
+#pragma unroll
+  for (int d = 0; d < 2; ++d)
+#pragma unroll
+    for (int ii = 0; ii < kT; ++ii)
+#pragma unroll
+      for (int jj = 0; jj < kT; ++jj) acc[d][ii][jj].init();
+
+  // uniform row bases (scalar registers) and one 32-bit per-lane sample offset; 2 consecutive
+  // samples per lane per step keep the live state at 168 VGPRs (3 waves per SIMD)
+  const uint32_t tb = (uint32_t)(chunk * chunk_len) + 2u * (uint32_t)lane;
+  const float* xi_r[kT];
+  const float* xj_r[kT];
+#pragma unroll
+  for (int k = 0; k < kT; ++k) {
+    xi_r[k] = Xs + (i0 + k) * n_pad;
+    xj_r[k] = Xs + (j0 + k) * n_pad;
+  }
+  const float cln2 = (float)(kWScale * kLn2);
+  const int steps = chunk_len / 128;                // 2 samples per lane per step
+  int since_flush = 0;
+  for (int s = 0; s < steps; ++s) {
+    float2 xi[kT], xj[kT];
+#pragma unroll
+    for (int k = 0; k < kT; ++k) {
+      const uint32_t o = tb + 128u * (uint32_t)s;
+      xi[k] = *reinterpret_cast<const float2*>(xi_r[k] + o);
+      xj[k] = *reinterpret_cast<const float2*>(xj_r[k] + o);
+    }
+#pragma unroll
+    for (int ii = 0; ii < kT; ++ii) {
+#pragma unroll
+      for (int jj = 0; jj < kT; ++jj) {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const float xv = e ? xi[ii].y : xi[ii].x;
+          const float yv = e ? xj[jj].y : xj[jj].x;
+          const float w0 = fmaf(xv, ca[ii][jj], -(yv * cb[ii][jj]));
+          const float w1 = fmaf(yv, ca[ii][jj], -(xv * cb[ii][jj]));
+          acc[0][ii][jj].step(w0);
+          acc[1][ii][jj].step(w1);
+        }
+      }
+    }
+    since_flush += 2;
+    if (since_flush == 64 || s == steps - 1) {
+      const float cnt = (float)since_flush;
+#pragma unroll
+      for (int d = 0; d < 2; ++d)
+#pragma unroll
+        for (int ii = 0; ii < kT; ++ii)
+#pragma unroll
+          for (int jj = 0; jj < kT; ++jj) acc[d][ii][jj].flush(cnt, cln2);
+      since_flush = 0;
+    }
+  }
+  (void)lane;
+  write_moment_partials(acc, i0, j0, m, chunk, partU, partB);
+}
+
 // The same item, (tile, chunk), for a listed micro-tile.  Lanes run over samples, one per step.  Each sample of the tile's 2 kT variables
 // is standardised in FP64 from E (x = (e - mu) / sd, population moments), the residuals of
 // both directions are formed in FP64, d = x_i - rho x_j, and only the scaled residual
 // w = d c / sqrt(1 - rho^2) is rounded to FP32: its relative error is then that of one
 // rounding, as for a well-conditioned pair.  The moment terms are the fast item's.
+template <class TP>
 __device__ inline void pairwise_collinear_item(
     const float* __restrict__ E, int64_t lde, int64_t n_eff, const double* __restrict__ mu,
     const double* __restrict__ cov, int64_t m, int nt, int chunk_len, int64_t tile,
-    int64_t chunk, float* __restrict__ partU, float* __restrict__ partB) {
+    int64_t chunk, TP* __restrict__ partU, TP* __restrict__ partB) {
+  constexpr bool Comp = std::is_same<TP, double>::value;
   const int lane = threadIdx.x & 63;
   int bi, bj;
   tile_coords(tile, nt, bi, bj);
@@ -367,17 +542,13 @@ __device__ inline void pairwise_collinear_item(
       }
     }
 
-  float U[2][kT][kT], P[2][kT][kT], B[2][kT][kT];
+  MomentAcc<Comp> acc[2][kT][kT];
 #pragma unroll
   for (int d = 0; d < 2; ++d)
 #pragma unroll
     for (int ii = 0; ii < kT; ++ii)
 #pragma unroll
-      for (int jj = 0; jj < kT; ++jj) {
-        U[d][ii][jj] = 0.f;
-        P[d][ii][jj] = 1.f;
-        B[d][ii][jj] = 0.f;
-      }
+      for (int jj = 0; jj < kT; ++jj) acc[d][ii][jj].init();
   const float cln2 = (float)(kWScale * kLn2);
   const int steps = chunk_len / 64;
   int since_flush = 0;
@@ -397,8 +568,8 @@ __device__ inline void pairwise_collinear_item(
       for (int jj = 0; jj < kT; ++jj) {
         const float w0 = (float)(fma(-rho[ii][jj], xj[jj], xi[ii]) * kc[ii][jj]);
         const float w1 = (float)(fma(-rho[ii][jj], xi[ii], xj[jj]) * kc[ii][jj]);
-        moment_step(w0, U[0][ii][jj], P[0][ii][jj], B[0][ii][jj]);
-        moment_step(w1, U[1][ii][jj], P[1][ii][jj], B[1][ii][jj]);
+        acc[0][ii][jj].step(w0);
+        acc[1][ii][jj].step(w1);
       }
     since_flush += 1;
     if (since_flush == 64 || s == steps - 1) {
@@ -408,21 +579,19 @@ __device__ inline void pairwise_collinear_item(
 #pragma unroll
         for (int ii = 0; ii < kT; ++ii)
 #pragma unroll
-          for (int jj = 0; jj < kT; ++jj) {
-            U[d][ii][jj] = fmaf(__builtin_amdgcn_logf(P[d][ii][jj]) - cnt, cln2, U[d][ii][jj]);
-            P[d][ii][jj] = 1.f;
-          }
+          for (int jj = 0; jj < kT; ++jj) acc[d][ii][jj].flush(cnt, cln2);
       since_flush = 0;
     }
   }
-  write_moment_partials(U, B, i0, j0, m, chunk, partU, partB);
+  write_moment_partials(acc, i0, j0, m, chunk, partU, partB);
 }
 
 // ------------------------------------------------------------------------------------------
 // Stage 5: FP64 combine.  Hr[i][j] from the chunk partials (fixed order), then S.
 // ------------------------------------------------------------------------------------------
-__device__ inline void combine_hr_elem(const float* __restrict__ partU,
-                                       const float* __restrict__ partB, int nc, int64_t m,
+template <class TP>
+__device__ inline void combine_hr_elem(const TP* __restrict__ partU,
+                                       const TP* __restrict__ partB, int nc, int64_t m,
                                        int64_t n_eff, double* __restrict__ Hr,
                                        double* __restrict__ mom, int64_t e) {
   if (e >= m * m) return;

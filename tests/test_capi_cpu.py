@@ -57,6 +57,13 @@ def test_workspace_queries(L):
     assert lib.pairwise_stats_backward_workspace_bytes(10000, 400, 1) > \
         lib.pairwise_stats_workspace_bytes(10000, 400, 1) + 2 * 400 * 10000 * 4
     assert lib.pairwise_stats_backward_workspace_bytes(10, 1, 1) == 0
+    # the compensated-sum flag: FP64 chunk partials instead of FP32 (in a region the covariance
+    # stage's split partials may already size); a bad precision under the flag gives 0
+    comp = L.PAIRWISE_COMPENSATED
+    plain = lib.pairwise_stats_workspace_bytes(10000, 400, 1)
+    assert lib.pairwise_stats_workspace_bytes(10000, 400, 1 | comp) >= plain
+    assert lib.pairwise_stats_workspace_bytes(10000, 400, 0 | comp) > 0
+    assert lib.pairwise_stats_workspace_bytes(10000, 400, 7 | comp) == 0
 
 
 FAKE = 0x10000   # a non-null, 256-aligned dummy pointer: never dereferenced on these paths
@@ -80,6 +87,11 @@ def test_host_validation_without_gpu(L):
                               None) == L.VL_ERR_INVALID_ARG
     assert lib.pairwise_stats(FAKE, 100, 4, 4, 7, FAKE, FAKE, FAKE, None, FAKE, 1 << 30, FAKE,
                               None) == L.VL_ERR_INVALID_ARG
+    # the compensated-sum flag is taken by the precompute's calls only
+    assert lib.pairwise_stats(FAKE, 100, 4, 4, 7 | L.PAIRWISE_COMPENSATED, FAKE, FAKE, FAKE,
+                              None, FAKE, 1 << 30, FAKE, None) == L.VL_ERR_INVALID_ARG
+    assert lib.varlingam_fit_var(FAKE, 100, 4, 4, 1, 1 | L.PAIRWISE_COMPENSATED, FAKE, FAKE, FAKE,
+                                 4, FAKE, 1 << 30, FAKE, None) == L.VL_ERR_INVALID_ARG
     # workspace too small or misaligned
     assert lib.pairwise_stats(FAKE, 100, 4, 4, 1, FAKE, FAKE, FAKE, None, FAKE, 16, FAKE,
                               None) == L.VL_ERR_WORKSPACE
