@@ -573,6 +573,21 @@ def main():
     fp32r_s = time_steps(f32r, X, args.steps, torch)
     f32r.check()
 
+    # the int8-slice products (Ozaki scheme) in place of MIXED's FP64-MFMA ones, and its stages
+    fs = api.Fitter(n, m, p, "sliced", dev)
+    for _ in range(args.warmup):
+        fs.run(X)
+    sliced_s = time_steps(fs, X, args.steps, torch)
+    fs.check()
+    _lib.profile_enable("*")
+    time_steps(fs, X, max(3, args.steps // 4), torch)
+    sliced_stage_ms = {}
+    for st in STAGES:
+        ms, cnt = _lib.profile_read(st)
+        if cnt:
+            sliced_stage_ms[st] = round(ms / cnt, 4)
+    _lib.profile_enable(None)
+
     # the BF16-Gram form with FP64 refinement, its VAR stages, and its distance from MIXED
     bf = api.Fitter(n, m, p, "bf16", dev)
     for _ in range(args.warmup):
@@ -606,6 +621,7 @@ def main():
                 "same_order": bool(torch.equal(o.order, fit.order))}
     bf16_dev = dist(bf)
     modes_vs_mixed = {"fp32": dist(f32), "fp32_refined": dist(f32r), "bf16": bf16_dev,
+                      "sliced": dist(fs),
                       "mixed_compensated": dict(dist(fc), S_max_abs_diff=float(
                           (fc.S - fit.S).abs().max()))}
 
@@ -649,6 +665,8 @@ def main():
         "fit_ms_fp32_refined": fp32r_s * 1e3,
         "fit_ms_bf16": bf16_s * 1e3,
         "fit_ms_mixed_compensated": comp_s * 1e3,
+        "fit_ms_sliced": sliced_s * 1e3,
+        "sliced_stage_ms": sliced_stage_ms,
         "pairwise_kernel_ms_compensated": cms / ccount,
         "bf16_stage_ms": bf16_stage_ms,
         "bf16_vs_mixed": bf16_dev,

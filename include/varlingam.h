@@ -61,6 +61,13 @@ typedef enum {
  *                  refinement step as in VL_PREC_BF16 (same convergence check), residual GEMM
  *                  and covariance as MIXED.  The cheapest form on the FP32 Gram that meets
  *                  the FP64 solution's accuracy.
+ *   VL_PREC_SLICED: the three products of MIXED by int8 MFMA on slices of the data (each
+ *                  vector scaled by a power of two and written as six signed 7-bit digits; the
+ *                  digit pairs' products summed exactly in int32 and combined in FP64: the
+ *                  Ozaki scheme), FP64 Cholesky.  Each product term is within 2^-39 of
+ *                  2^(e_a + e_b), the two vectors' power-of-two scales: FP64-grade for the
+ *                  Grams, far below the FP32 rounding of E.  Workspace: six int8 planes of the
+ *                  lag-embedded columns (fit) or of E's columns (covariance).
  * The batched fit takes FP32 and MIXED only.
  *   VL_PAIRWISE_COMPENSATED: a flag OR-ed into the precision of pairwise_stats,
  *                  pairwise_stats_noalloc and pairwise_stats_workspace_bytes (no other call
@@ -75,6 +82,7 @@ typedef enum {
   VL_PREC_MIXED = 1,
   VL_PREC_BF16 = 2,
   VL_PREC_FP32_REFINED = 3,
+  VL_PREC_SLICED = 4,
   VL_PAIRWISE_COMPENSATED = 16
 } vl_precision;
 

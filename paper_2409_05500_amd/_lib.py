@@ -17,7 +17,7 @@ VL_ERR_NONFINITE = -5
 VL_ERR_WORKSPACE = -6
 VL_ERR_HIP = -7
 
-PREC = {"fp32": 0, "mixed": 1, "bf16": 2, "fp32_refined": 3}
+PREC = {"fp32": 0, "mixed": 1, "bf16": 2, "fp32_refined": 3, "sliced": 4}
 PAIRWISE_COMPENSATED = 16   # flag OR-ed into the precision of the pairwise calls
 
 _p = C.c_void_p

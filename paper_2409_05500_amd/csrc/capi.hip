@@ -20,12 +20,13 @@ inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s);
 
 inline bool valid_prec(int prec) {
   return prec == VL_PREC_FP32 || prec == VL_PREC_MIXED || prec == VL_PREC_BF16 ||
-         prec == VL_PREC_FP32_REFINED;
+         prec == VL_PREC_FP32_REFINED || prec == VL_PREC_SLICED;
 }
 
 // The precompute's entry points also take the compensated-sum flag.
 inline bool valid_pairwise_prec(int prec) { return valid_prec(prec & ~VL_PAIRWISE_COMPENSATED); }
-inline bool compensated(int prec) { return (prec & VL_PAIRWISE_COMPENSATED) != 0;
+inline bool compensated(int prec) { return (prec & VL_PAIRWISE_COMPENSATED) != 0; }
+inline bool sliced(int prec) { return (prec & ~VL_PAIRWISE_COMPENSATED) == VL_PREC_SLICED;
 }
 
 inline bool aligned256(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
@@ -78,9 +79,8 @@ const char* varlingam_status_string(int status) {
 
 // ----------------------------------------------------------------------------------------
 size_t varlingam_fit_var_workspace_bytes(int64_t n, int64_t m, int p, int prec) {
-  (void)prec;
   if (m < 1 || p < 1 || n - p <= m * p + 1) return 0;
-  return var_ws_bytes(plan_var(n, m, p), nullptr, nullptr);
+  return var_ws_bytes(plan_var(n, m, p, prec == VL_PREC_SLICED), nullptr, nullptr);
 }
 
 int varlingam_fit_var(const float* X, int64_t n, int64_t m, int64_t ldx, int p, int prec,
@@ -89,7 +89,7 @@ int varlingam_fit_var(const float* X, int64_t n, int64_t m, int64_t ldx, int p, 
   if (!X || !M || !intercept || !E || !dev_status || !valid_prec(prec)) return VL_ERR_INVALID_ARG;
   if (m < 1 || p < 1 || n - p <= m * p + 1 || m * p > 4096) return VL_ERR_SHAPE;
   if (ldx < m || lde < m) return VL_ERR_INVALID_ARG;
-  const VarPlan v = plan_var(n, m, p);
+  const VarPlan v = plan_var(n, m, p, prec == VL_PREC_SLICED);
   const size_t need = var_ws_bytes(v, nullptr, nullptr);
   if (!ws || ws_bytes < need || !aligned256(ws)) return VL_ERR_WORKSPACE;
   VarWs w;
@@ -126,7 +126,8 @@ int varlingam_select_lag(const float* X, int64_t n, int64_t m, int64_t ldx, int 
 // ----------------------------------------------------------------------------------------
 size_t pairwise_stats_workspace_bytes(int64_t n_eff, int64_t m, int prec) {
   if (m < 2 || n_eff < 2 || m > 65536 || !valid_pairwise_prec(prec)) return 0;
-  return pairwise_ws_bytes(plan_pairwise(n_eff, m, compensated(prec)), nullptr, nullptr);
+  return pairwise_ws_bytes(plan_pairwise(n_eff, m, compensated(prec), sliced(prec)), nullptr,
+                           nullptr);
 }
 
 int pairwise_stats(const float* E, int64_t n_eff, int64_t m, int64_t lde, int prec, double* Hx,
@@ -136,7 +137,7 @@ int pairwise_stats(const float* E, int64_t n_eff, int64_t m, int64_t lde, int pr
     return VL_ERR_INVALID_ARG;
   if (m < 2 || n_eff < 2 || m > 65536) return VL_ERR_SHAPE;
   if (lde < m) return VL_ERR_INVALID_ARG;
-  const PairwisePlan p = plan_pairwise(n_eff, m, compensated(prec));
+  const PairwisePlan p = plan_pairwise(n_eff, m, compensated(prec), sliced(prec));
   const size_t need = pairwise_ws_bytes(p, nullptr, nullptr);
   if (!ws || ws_bytes < need || !aligned256(ws)) return VL_ERR_WORKSPACE;
   PairwiseWs w;
@@ -156,7 +157,7 @@ int pairwise_stats_noalloc(const float* E, int64_t n_eff, int64_t m, int64_t lde
     return VL_ERR_INVALID_ARG;
   if (m < 2 || n_eff < 2 || m > 65536) return VL_ERR_SHAPE;
   if (lde < m) return VL_ERR_INVALID_ARG;
-  const PairwisePlan p = plan_pairwise(n_eff, m, compensated(prec));
+  const PairwisePlan p = plan_pairwise(n_eff, m, compensated(prec), sliced(prec));
   if (pairwise_ws_bytes(p, nullptr, nullptr) > kNoAllocScratchBytes) return VL_ERR_WORKSPACE;
   void* ws = nullptr;
   int rc = scratch_address(&ws);

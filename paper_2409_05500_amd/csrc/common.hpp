@@ -212,6 +212,14 @@ __device__ inline float wave_reduce_scatter16(float (&v)[16]) {
   return s;
 }
 
+// Exponent e with |v| < 2^e for every value of a set whose largest magnitude is mx (0 for mx = 0;
+// a non-finite mx, which the callers' finiteness checks report, gives 0 as well).
+__device__ __forceinline__ int32_t exponent_of(double mx) {
+  int ex = 0;
+  if (mx > 0.0 && mx < INFINITY) frexp(mx, &ex);
+  return ex;
+}
+
 // v if keep, else +0.0, by masking the bits.  The mask is made opaque to the optimiser (an
 // empty asm statement on the mask, which no load feeds): otherwise it proves the masked value
 // dead and branches around the load that produces it, with a wait per load.

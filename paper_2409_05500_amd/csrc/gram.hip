@@ -20,6 +20,9 @@ __global__ void reset_status_kernel(int32_t* st) {
 // Column sums over K samples, split over row blocks: part[rs * ncol + c] (FP64), plus a
 // finiteness check.  Block = 256 threads = 64 columns x 4 row lanes.
 // ------------------------------------------------------------------------------------------
+// kRange: also each column's minimum and maximum over the split, at part[splits ncol + ...]
+// and part[2 splits ncol + ...] (for the slice exponents).
+template <bool kRange>
 __global__ __launch_bounds__(256) void colsum_partial_kernel(const float* __restrict__ A,
                                                              int64_t lda,
                                                              const int64_t* __restrict__ colmap,
@@ -28,11 +31,13 @@ __global__ __launch_bounds__(256) void colsum_partial_kernel(const float* __rest
                                                              double* __restrict__ part,
                                                              int32_t* st) {
   __shared__ double red[4][64];
+  __shared__ float rmin[kRange ? 4 : 1][64], rmax[kRange ? 4 : 1][64];
   const int cc = threadIdx.x & 63, rg = threadIdx.x >> 6;
   const int64_t c = (int64_t)blockIdx.x * 64 + cc;
   const int64_t r0 = (int64_t)blockIdx.y * rows_per_split;
   const int64_t r1 = r0 + rows_per_split < K ? r0 + rows_per_split : K;
   double s = 0.0;
+  float mn = INFINITY, mx = -INFINITY;
   bool bad = false;
   if (c < ncol) {
     const float* p = A + (colmap ? colmap[c] : c);
@@ -45,19 +50,39 @@ __global__ __launch_bounds__(256) void colsum_partial_kernel(const float* __rest
       for (int q = 0; q < 8; ++q) {
         bad |= !isfinite(v[q]);
         s += (double)v[q];
+        if constexpr (kRange) {
+          mn = fminf(mn, v[q]);
+          mx = fmaxf(mx, v[q]);
+        }
       }
     }
     for (; t < r1; t += 4) {
       const float v = p[t * lda];
       bad |= !isfinite(v);
       s += (double)v;
+      if constexpr (kRange) {
+        mn = fminf(mn, v);
+        mx = fmaxf(mx, v);
+      }
     }
   }
   if (bad) raise_status(st, VL_ERR_NONFINITE);
   red[rg][cc] = s;
+  if constexpr (kRange) {
+    rmin[rg][cc] = mn;
+    rmax[rg][cc] = mx;
+  }
   __syncthreads();
-  if (rg == 0 && c < ncol)
+  if (rg == 0 && c < ncol) {
     part[(int64_t)blockIdx.y * ncol + c] = ((red[0][cc] + red[1][cc]) + red[2][cc]) + red[3][cc];
+    if constexpr (kRange) {
+      const int64_t sn = (int64_t)gridDim.y * ncol;
+      part[sn + (int64_t)blockIdx.y * ncol + c] =
+          fminf(fminf(rmin[0][cc], rmin[1][cc]), fminf(rmin[2][cc], rmin[3][cc]));
+      part[2 * sn + (int64_t)blockIdx.y * ncol + c] =
+          fmaxf(fmaxf(rmax[0][cc], rmax[1][cc]), fmaxf(rmax[2][cc], rmax[3][cc]));
+    }
+  }
 }
 
 // sum_{z < splits} P[z * stride + e] in split order.  Eight loads are issued before they are
@@ -81,25 +106,58 @@ __device__ inline double sum_splits_at(const double* __restrict__ P, int splits,
 __global__ void colmean_final_kernel(const double* __restrict__ part, int64_t ncol, int splits,
                                      int64_t K, double* __restrict__ mean,
                                      double* __restrict__ rep, int64_t rep_m,
-                                     int64_t rep_blocks) {
+                                     int64_t rep_blocks, int32_t* __restrict__ range_exp,
+                                     int64_t centre_m) {
   int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncol) return;
   const double v = sum_splits_at(part, splits, ncol, c) / (double)K;
   mean[c] = v;
   if (rep && c < rep_m)
     for (int64_t h = 0; h < rep_blocks; ++h) rep[h * rep_m + c] = v;
+  if (range_exp) {
+    // |x - mu0| <= max(max - mu0, mu0 - min) over the column, mu0 the mean of column
+    // c mod centre_m (the same sum, so the same value)
+    const int64_t sn = (int64_t)splits * ncol, c0 = c % centre_m;
+    const double mu0 = c0 == c ? v : sum_splits_at(part, splits, ncol, c0) / (double)K;
+    double mn = INFINITY, mx = -INFINITY;
+    int z = 0;
+    for (; z + 8 <= splits; z += 8) {      // eight of each in flight
+      double a[8], b[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        a[q] = part[sn + (int64_t)(z + q) * ncol + c];
+        b[q] = part[2 * sn + (int64_t)(z + q) * ncol + c];
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        mn = fmin(mn, a[q]);
+        mx = fmax(mx, b[q]);
+      }
+    }
+    for (; z < splits; ++z) {
+      mn = fmin(mn, part[sn + (int64_t)z * ncol + c]);
+      mx = fmax(mx, part[2 * sn + (int64_t)z * ncol + c]);
+    }
+    range_exp[c] = exponent_of(fmax(mx - mu0, mu0 - mn));
+  }
 }
 
 int colmeans(const float* A, int64_t lda, const int64_t* colmap, int64_t ncol, int64_t K,
              double* mean, double* scratch, int32_t* st, hipStream_t stream, double* rep,
-             int64_t rep_m, int64_t rep_blocks) {
+             int64_t rep_m, int64_t rep_blocks, int32_t* range_exp, int64_t centre_m) {
   const int splits = colmean_splits(K);
   const int64_t rows = ceil_div(K, splits);
   dim3 grid((unsigned)ceil_div(ncol, 64), (unsigned)splits);
-  colsum_partial_kernel<<<grid, 256, 0, stream>>>(A, lda, colmap, ncol, K, rows, scratch, st);
+  if (range_exp)
+    colsum_partial_kernel<true><<<grid, 256, 0, stream>>>(A, lda, colmap, ncol, K, rows,
+                                                          scratch, st);
+  else
+    colsum_partial_kernel<false><<<grid, 256, 0, stream>>>(A, lda, colmap, ncol, K, rows,
+                                                           scratch, st);
   VL_LAUNCH_CHECK();
   colmean_final_kernel<<<(unsigned)ceil_div(ncol, 256), 256, 0, stream>>>(
-      scratch, ncol, splits, K, mean, rep, rep_m, rep_blocks);
+      scratch, ncol, splits, K, mean, rep, rep_m, rep_blocks, range_exp,
+      centre_m > 0 ? centre_m : ncol);
   VL_LAUNCH_CHECK();
   return VL_OK;
 }
@@ -263,6 +321,19 @@ __global__ void sum_splits_sym_kernel(const double* __restrict__ P, int splits, 
   const double s = sum_splits_at(P, splits, M * M, e);
   C[i * ldc + j] = s * scale;
   C[j * ldc + i] = s * scale;
+}
+
+int sum_splits(const double* P, int splits, int64_t M, int64_t N, double scale, double* C,
+               int64_t ldc, bool sym, hipStream_t stream) {
+  const int64_t tot = M * N;
+  if (sym)
+    sum_splits_sym_kernel<<<(unsigned)ceil_div(tot, 256), 256, 0, stream>>>(P, splits, M, scale,
+                                                                            C, ldc);
+  else
+    sum_splits_kernel<<<(unsigned)ceil_div(tot, 256), 256, 0, stream>>>(P, splits, M, N, scale,
+                                                                       C, ldc);
+  VL_LAUNCH_CHECK();
+  return VL_OK;
 }
 
 int gram_tn(const float* A, int64_t lda, const int64_t* mapA, const double* muA, int64_t M,

@@ -12,9 +12,12 @@ inline int colmean_splits(int64_t K) {
 
 // mean[c] = (1/K) sum_{t<K} A[map(c) + t*lda]  (FP64);  raises VL_ERR_NONFINITE on NaN/Inf.
 // With rep: rep[h * rep_m + c] = mean[c] for c < rep_m and h < rep_blocks as well.
+// With range_exp: range_exp[c] = e with |A(t, c) - mean[c mod centre_m]| < 2^e for every t < K
+// (from the column's range; centre_m = 0: ncol), and scratch holds 3 splits ncol doubles.
 int colmeans(const float* A, int64_t lda, const int64_t* colmap, int64_t ncol, int64_t K,
              double* mean, double* scratch, int32_t* st, hipStream_t stream,
-             double* rep = nullptr, int64_t rep_m = 0, int64_t rep_blocks = 0);
+             double* rep = nullptr, int64_t rep_m = 0, int64_t rep_blocks = 0,
+             int32_t* range_exp = nullptr, int64_t centre_m = 0);
 
 // Split-K factor of gram_tn(); scratch must hold gram_splits(M,N,K) * M * N doubles.  About
 // 1024 workgroups (four per CU): with M == N the tiles counted are the lower triangle's, which
@@ -46,6 +49,11 @@ int gram_tn(const float* A, int64_t lda, const int64_t* mapA, const double* muA,
             const float* B, int64_t ldb, const int64_t* mapB, const double* muB, int64_t N,
             int64_t K, GramMode mode, double scale, double* C, int64_t ldc, double* scratch,
             hipStream_t stream, bool sym = false);
+
+// C[i*ldc + j] = scale * sum_{z < splits} P[z][i][j] (P: splits x M x N), in split order; sym
+// (M == N): the lower triangle's sums, written to both triangles.
+int sum_splits(const double* P, int splits, int64_t M, int64_t N, double scale, double* C,
+               int64_t ldc, bool sym, hipStream_t stream);
 
 // C[i*ldc + j] = sum_{t<K} (A(t,i) - muA[i]) B[t*ldb + j] with an FP64, uncentred B (FP64 MFMA).
 int gram_tn_f64b(const float* A, int64_t lda, const int64_t* mapA, const double* muA, int64_t M,

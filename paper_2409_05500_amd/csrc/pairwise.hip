@@ -21,6 +21,7 @@
 #include "pairwise.hpp"
 #include "pairwise_dev.hpp"
 #include "profile.hpp"
+#include "sliced.hpp"
 
 namespace vl {
 
@@ -114,9 +115,10 @@ __global__ void score_kernel(const double* __restrict__ Hx, const double* __rest
 // samples (4 steps of 2 samples per lane), chunks a multiple of 128.  Measured at one launch
 // per fit: m = 400 (n = 10^4) within 1% of the best chunk count, m = 1000 (n = 5 10^4) within
 // 0.5%, m = 100 (n = 5000) within 4% (a floor of 2048 samples per chunk was 49% slower there).
-PairwisePlan plan_pairwise(int64_t n_eff, int64_t m, bool compensated) {
+PairwisePlan plan_pairwise(int64_t n_eff, int64_t m, bool compensated, bool sliced) {
   PairwisePlan p;
   p.comp = compensated;
+  p.sliced = sliced;
   p.m = m;
   p.n_eff = n_eff;
   p.nt = (int)ceil_div(m, kT);
@@ -143,6 +145,10 @@ size_t pairwise_ws_bytes(const PairwisePlan& p, void* base, PairwiseWs* out) {
   char* region = base ? static_cast<char*>(base) + c.used : nullptr;
   Carver a(region);                              // stage 1
   w.scratch = a.take<double>(scratch_doubles(p));
+  if (p.sliced) {
+    w.slices = a.take<int8_t>(slice_bytes(p.m, p.n_eff));
+    w.ex = a.take<int32_t>(p.m);
+  }
   Carver b(region);                              // stages 2-5
   w.Xs = b.take<float>(p.m_pad * p.n_pad);
   w.coef = b.take<float2>(p.m_pad * p.m_pad);
@@ -163,6 +169,10 @@ size_t pairwise_ws_bytes(const PairwisePlan& p, void* base, PairwiseWs* out) {
 size_t scratch_doubles(const PairwisePlan& p) {
   size_t a = (size_t)colmean_splits(p.n_eff) * p.m;
   size_t b = (size_t)gram_splits(p.m, p.m, p.n_eff) * p.m * p.m;
+  if (p.sliced) {
+    a *= 3;     // column ranges for the slice exponents
+    b = std::max(b, (size_t)slice_gram_splits(p.m, p.m, p.n_eff, true) * p.m * p.m);
+  }
   return a > b ? a : b;
 }
 
@@ -214,14 +224,28 @@ int run_pairwise(const PairwisePlan& p, const PairwiseWs& w, const float* E, int
   double* cov = Cov ? Cov : w.cov;
   {
     ProfileScope ps("pairwise_cov", stream);
-    int rc = colmeans(E, lde, nullptr, m, n_eff, w.mu, w.scratch, st, stream);
+    int rc = colmeans(E, lde, nullptr, m, n_eff, w.mu, w.scratch, st, stream, nullptr, 0, 0,
+                      p.sliced ? w.ex : nullptr);
     if (rc) return rc;
-    // covariance: exact products and FP64 sums (plain FP32 mode: FP32 MFMA throughout)
-    const bool fp32 = (prec & ~VL_PAIRWISE_COMPENSATED) == VL_PREC_FP32;
-    rc = gram_tn(E, lde, nullptr, w.mu, m, E, lde, nullptr, w.mu, m, n_eff,
-                 fp32 ? GramMode::kFp32 : GramMode::kFp64, 1.0 / (double)n_eff,
-                 cov, m, w.scratch, stream, true);
-    if (rc) return rc;
+    if (p.sliced) {
+      // the covariance from int8 slices of E's centred columns
+      rc = slice_columns(E, lde, m, 1, 0, n_eff, w.mu, w.ex, w.slices, stream);
+      if (rc) return rc;
+      SliceOp D;
+      D.D = w.slices;
+      D.rows = m;
+      D.plane = m * slice_ldk(n_eff);
+      D.e = w.ex;
+      rc = slice_gram(D, m, D, m, n_eff, 1.0 / (double)n_eff, cov, m, w.scratch, stream, true);
+      if (rc) return rc;
+    } else {
+      // covariance: exact products and FP64 sums (plain FP32 mode: FP32 MFMA throughout)
+      const bool fp32 = (prec & ~VL_PAIRWISE_COMPENSATED) == VL_PREC_FP32;
+      rc = gram_tn(E, lde, nullptr, w.mu, m, E, lde, nullptr, w.mu, m, n_eff,
+                   fp32 ? GramMode::kFp32 : GramMode::kFp64, 1.0 / (double)n_eff, cov, m,
+                   w.scratch, stream, true);
+      if (rc) return rc;
+    }
   }
   {
     ProfileScope ps("pairwise_prep", stream);

@@ -6,6 +6,7 @@ namespace vl {
 
 struct PairwisePlan {
   bool comp = false;      // compensated moment sums, FP64 partials
+  bool sliced = false;    // covariance from int8 slices (VL_PREC_SLICED)
   int64_t m = 0, n_eff = 0;
   int nt = 0;             // micro-tiles per side (4 variables each)
   int64_t m_pad = 0;      // nt * 4
@@ -29,9 +30,12 @@ struct PairwiseWs {
   double* partB64 = nullptr;
   double* momx = nullptr;     // 2 m: E[log cosh x_i], E[x_i exp(-x_i^2/2)]
   int32_t* clist = nullptr;   // 2 tiles + 1: near-collinear tile flags, count, list
+  int8_t* slices = nullptr;   // sliced covariance: slice planes of E's columns (stage 1)
+  int32_t* ex = nullptr;      // m exponents
 };
 
-PairwisePlan plan_pairwise(int64_t n_eff, int64_t m, bool compensated = false);
+PairwisePlan plan_pairwise(int64_t n_eff, int64_t m, bool compensated = false,
+                           bool sliced = false);
 size_t scratch_doubles(const PairwisePlan& p);
 // Total workspace bytes; with base != nullptr also fills *out with the carved pointers.
 size_t pairwise_ws_bytes(const PairwisePlan& p, void* base, PairwiseWs* out);

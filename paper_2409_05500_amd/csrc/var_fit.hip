@@ -21,6 +21,7 @@
 #include "gram.hpp"
 #include "linalg.hpp"
 #include "var_fit.hpp"
+#include "sliced.hpp"
 #include "var_dev.hpp"
 #include "profile.hpp"
 
@@ -179,8 +180,9 @@ __global__ __launch_bounds__(256) void var_post_kernel(const double* __restrict_
   if (lane == 0) intercept[i] = mu[i] - s;
 }
 
-VarPlan plan_var(int64_t n, int64_t m, int p) {
+VarPlan plan_var(int64_t n, int64_t m, int p, bool sliced) {
   VarPlan v;
+  v.sliced = sliced;
   v.n = n;
   v.m = m;
   v.p = p;
@@ -205,7 +207,7 @@ size_t var_ws_bytes(const VarPlan& v, void* base, VarWs* out) {
   w.E64 = c.take<double>(v.n_eff * v.m);
   w.F = c.take<double>(v.m * nc);
   w.mu0 = c.take<double>(nc);
-  size_t s1 = (size_t)colmean_splits(v.n_eff) * nc;
+  size_t s1 = (size_t)colmean_splits(v.n_eff) * nc * (v.sliced ? 3 : 1);
   size_t s2 = (size_t)gram_splits(v.m, nc, v.n_eff) * v.m * nc;      // lag products
   size_t s3 = (size_t)gram_splits(v.dz, v.m, v.n_eff) * v.dz * v.m;   // R, refinement Gram
   size_t s4 = (size_t)gram_splits(v.dz, v.dz, v.n_eff) * v.dz * v.dz; // direct G
@@ -213,13 +215,41 @@ size_t var_ws_bytes(const VarPlan& v, void* base, VarWs* out) {
   s = s > s3 ? s : s3;
   s = s > s4 ? s : s4;
   s = s > (size_t)(3 * kCheckBlocks) ? s : (size_t)(3 * kCheckBlocks);  // refinement check
+  if (v.sliced) s = std::max(s, (size_t)slice_gram_splits(v.m, nc, v.n_eff, false) * v.m * nc);
   w.scratch = c.take<double>(s);
+  if (v.sliced) {
+    w.slices = c.take<int8_t>(std::max(slice_bytes(nc, v.n_eff), slice_bytes(v.n_eff, v.dz)));
+    w.slicesC = c.take<int8_t>(slice_bytes(v.m, v.dz));
+    w.ex = c.take<int32_t>(nc);
+    w.ez = c.take<int32_t>(v.n_eff);
+    w.ec = c.take<int32_t>(v.m);
+  }
   if (out) *out = w;
   return c.used;
 }
 
 static int var_residual(const VarPlan& v, const VarWs& w, const float* X, int64_t ldx, float* E,
                         int64_t lde, bool fp64, hipStream_t stream) {
+  if (v.sliced) {
+    // E = Yc - Zc Coef from the slices of the design rows and of the coefficient columns
+    const int64_t kpad = slice_ldk(v.dz);
+    int rc = slice_design_rows(X, ldx, w.colmap, w.mu, v.m, v.dz, v.n_eff, w.slices, w.ez,
+                               stream);
+    if (rc) return rc;
+    rc = slice_matrix_columns(w.Coef, v.dz, v.m, w.slicesC, w.ec, stream);
+    if (rc) return rc;
+    SliceOp A, B;
+    A.D = w.slices;
+    A.rows = v.n_eff;
+    A.plane = v.n_eff * kpad;
+    A.e = w.ez;
+    B.D = w.slicesC;
+    B.rows = v.m;
+    B.plane = v.m * kpad;
+    B.e = w.ec;
+    return slice_residual<float>(A, v.n_eff, B, v.m, v.dz, X, ldx, w.colmap, w.mu, E, lde,
+                                 stream);
+  }
   if (fp64) {
     launch_residual_f64w<float>(X, ldx, w.colmap, w.mu, v.m, v.p, v.n_eff, w.Coef, E, lde,
                                 stream);
@@ -294,10 +324,28 @@ static int var_normal_equations(const VarPlan& v, const VarWs& w, const float* X
     lag_colmap_kernel<<<(unsigned)ceil_div(nc, 256), 256, 0, stream>>>(m, v.p, ldx, w.colmap);
     VL_LAUNCH_CHECK();
     // MIXED also needs the lag-0 means once per lag block (mu0), written by the same pass
-    const bool fp64 = gmode == GramMode::kFp64;
+    // (sliced: with each lag-embedded column's range exponent about its lag-0 mean)
+    const bool fp64 = gmode == GramMode::kFp64 && !v.sliced;
     rc = colmeans(X, ldx, w.colmap, nc, n_eff, w.mu, w.scratch, st, stream,
-                  fp64 ? w.mu0 : nullptr, m, v.p + 1);
+                  fp64 ? w.mu0 : nullptr, m, v.p + 1, v.sliced ? w.ex : nullptr, m);
     if (rc) return rc;
+    if (v.sliced) {
+      // the same lag products F from int8 slices of the series centred by the lag-0 means
+      // (w.mu[0 .. m))
+      rc = slice_columns(X, ldx, m, v.p + 1, v.p, n_eff, w.mu, w.ex, w.slices, stream);
+      if (rc) return rc;
+      SliceOp D;
+      D.D = w.slices;
+      D.rows = nc;
+      D.plane = nc * slice_ldk(n_eff);
+      D.e = w.ex;
+      rc = slice_gram(D, m, D, nc, n_eff, 1.0, w.F, nc, w.scratch, stream);
+      if (rc) return rc;
+      var_assemble_kernel<<<(unsigned)ceil_div(dz * dz + dz * m, 256), 256, 0, stream>>>(
+          X, ldx, w.F, w.mu, m, v.p, v.n, w.G, w.Tmp);
+      VL_LAUNCH_CHECK();
+      return VL_OK;
+    }
     if (fp64) {
       rc = gram_tn(X, ldx, w.colmap, w.mu, m, X, ldx, w.colmap, w.mu0, nc, n_eff, gmode, 1.0,
                    w.F, nc, w.scratch, stream);

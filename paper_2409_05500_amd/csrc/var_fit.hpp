@@ -7,6 +7,7 @@ namespace vl {
 struct VarPlan {
   int64_t n = 0, m = 0, n_eff = 0, dz = 0;
   int p = 0;
+  bool sliced = false;        // int8-slice products (VL_PREC_SLICED): slice buffers in the ws
 };
 
 struct VarWs {
@@ -23,6 +24,13 @@ struct VarWs {
   double* F = nullptr;        // m x m (p+1) lag products F_h (see var_normal_equations)
   double* mu0 = nullptr;      // m (p+1): the lag-0 means repeated for every lag block
   double* scratch = nullptr;  // split-K partials
+  // VL_PREC_SLICED only: slice planes of the lag-embedded columns (the lag products), then of
+  // the design rows and the coefficient columns (the residual), sharing one region
+  int8_t* slices = nullptr;
+  int8_t* slicesC = nullptr;  // coefficient columns (m rows of dz)
+  int32_t* ex = nullptr;      // m (p+1): exponent per lag-embedded column
+  int32_t* ez = nullptr;      // n_eff: exponent per design row
+  int32_t* ec = nullptr;      // m: exponent per coefficient column
 };
 
 // Lag-order selection workspace: the VAR workspace of the p_max plan, then m x m buffers.
@@ -34,7 +42,7 @@ struct LagWs {
   double* chol = nullptr;   // factorisation scratch (m)
 };
 
-VarPlan plan_var(int64_t n, int64_t m, int p);
+VarPlan plan_var(int64_t n, int64_t m, int p, bool sliced = false);
 size_t var_ws_bytes(const VarPlan& v, void* base, VarWs* out);
 int run_var(const VarPlan& v, const VarWs& w, const float* X, int64_t ldx, int prec, double* M,
             double* intercept, float* E, int64_t lde, int32_t* st, hipStream_t stream);

@@ -280,8 +280,16 @@ def test_certified_order_host_checks(L):
               None) == L.VL_ERR_INVALID_ARG
     assert co(FAKE, 100, 4, 4, FAKE, 1e-6, FAKE, FAKE, None, None, FAKE, 64, FAKE,
               None) == L.VL_ERR_WORKSPACE
-    # precision enum: the refined FP32 mode is accepted, an unknown one refused
+    # precision enum: the refined FP32 and the int8-slice modes are accepted, an unknown one
+    # refused
     assert lib.pairwise_stats(FAKE, 100, 4, 4, 3, FAKE, FAKE, FAKE, None, FAKE, 16, FAKE,
                               None) == L.VL_ERR_WORKSPACE
-    assert lib.pairwise_stats(FAKE, 100, 4, 4, 4, FAKE, FAKE, FAKE, None, FAKE, big, FAKE,
+    assert lib.pairwise_stats(FAKE, 100, 4, 4, 4, FAKE, FAKE, FAKE, None, FAKE, 16, FAKE,
+                              None) == L.VL_ERR_WORKSPACE
+    assert lib.pairwise_stats(FAKE, 100, 4, 4, 5, FAKE, FAKE, FAKE, None, FAKE, big, FAKE,
                               None) == L.VL_ERR_INVALID_ARG
+    # the sliced modes' workspace holds the slice planes: six bytes per sample and column
+    assert lib.pairwise_stats_workspace_bytes(10000, 400, 4) >= \
+        lib.pairwise_stats_workspace_bytes(10000, 400, 1)
+    assert lib.varlingam_fit_var_workspace_bytes(10000, 400, 2, 4) >= \
+        lib.varlingam_fit_var_workspace_bytes(10000, 400, 2, 1) + 6 * 1200 * 9998

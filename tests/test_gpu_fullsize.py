@@ -4,9 +4,9 @@ benchmark's series), seeds 0-2, against the FP64 oracle's own fit of the same fl
 * order: walked with parity.order_violations on the oracle's score matrix (the GPU's pick must
   be within 1e-9 of the oracle's minimum over the GPU's current candidate set);
 * B0 / B_tau: against the oracle's B for the same order (the oracle's order when the two
-  agree, else the oracle's estimator run on the GPU's order), 1e-5 relative in the mixed mode
-  and in FP32 with one FP64 refinement step, 1e-3 with the BF16 Gram; plain FP32 is held to
-  parity.B_TOL_PLAIN and its error printed;
+  agree, else the oracle's estimator run on the GPU's order), 1e-5 relative in the mixed mode,
+  in FP32 with one FP64 refinement step and with the int8-slice products, 1e-3 with the BF16
+  Gram; plain FP32 is held to parity.B_TOL_PLAIN and its error printed;
 * S: max |S - S_ref| within the pairwise bound TOL_S of the small-size tests (6e-6).
 """
 import numpy as np
@@ -20,7 +20,7 @@ pytestmark = pytest.mark.gpu
 
 TOL_S = 6e-6
 B_TOL = {"mixed": PA.B_TOL_FP32, "bf16": PA.B_TOL_BF16, "fp32": PA.B_TOL_PLAIN,
-         "fp32_refined": PA.B_TOL_FP32}
+         "fp32_refined": PA.B_TOL_FP32, "sliced": PA.B_TOL_FP32}
 
 
 @pytest.fixture(scope="module")
@@ -36,7 +36,7 @@ def test_fit_benchmark_workload_end_to_end(api, fullsize_oracle, seed):
     print(f"full-size fit m400_n10000_p2_t4 seed {seed}: waiting for the oracle", flush=True)
     ref = fullsize_oracle("m400_n10000_p2_t4", seed)
     X = torch.from_numpy(ref["X32"]).to("cuda:0")
-    for prec in ("mixed", "bf16", "fp32", "fp32_refined"):
+    for prec in ("mixed", "sliced", "bf16", "fp32", "fp32_refined"):
         print(f"  {prec}", flush=True)
         g = api.fit(X, 2, prec)
         order = g.order.cpu().numpy()
