@@ -107,7 +107,7 @@ __global__ void colmean_final_kernel(const double* __restrict__ part, int64_t nc
                                      int64_t K, double* __restrict__ mean,
                                      double* __restrict__ rep, int64_t rep_m,
                                      int64_t rep_blocks, int32_t* __restrict__ range_exp,
-                                     int64_t centre_m) {
+                                     int64_t centre_m, int32_t* __restrict__ range_exp_own) {
   int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncol) return;
   const double v = sum_splits_at(part, splits, ncol, c) / (double)K;
@@ -139,12 +139,14 @@ __global__ void colmean_final_kernel(const double* __restrict__ part, int64_t nc
       mx = fmax(mx, part[2 * sn + (int64_t)z * ncol + c]);
     }
     range_exp[c] = exponent_of(fmax(mx - mu0, mu0 - mn));
+    if (range_exp_own) range_exp_own[c] = exponent_of(fmax(mx - v, v - mn));
   }
 }
 
 int colmeans(const float* A, int64_t lda, const int64_t* colmap, int64_t ncol, int64_t K,
              double* mean, double* scratch, int32_t* st, hipStream_t stream, double* rep,
-             int64_t rep_m, int64_t rep_blocks, int32_t* range_exp, int64_t centre_m) {
+             int64_t rep_m, int64_t rep_blocks, int32_t* range_exp, int64_t centre_m,
+             int32_t* range_exp_own) {
   const int splits = colmean_splits(K);
   const int64_t rows = ceil_div(K, splits);
   dim3 grid((unsigned)ceil_div(ncol, 64), (unsigned)splits);
@@ -157,7 +159,7 @@ int colmeans(const float* A, int64_t lda, const int64_t* colmap, int64_t ncol, i
   VL_LAUNCH_CHECK();
   colmean_final_kernel<<<(unsigned)ceil_div(ncol, 256), 256, 0, stream>>>(
       scratch, ncol, splits, K, mean, rep, rep_m, rep_blocks, range_exp,
-      centre_m > 0 ? centre_m : ncol);
+      centre_m > 0 ? centre_m : ncol, range_exp_own);
   VL_LAUNCH_CHECK();
   return VL_OK;
 }

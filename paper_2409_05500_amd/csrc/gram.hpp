@@ -13,11 +13,13 @@ inline int colmean_splits(int64_t K) {
 // mean[c] = (1/K) sum_{t<K} A[map(c) + t*lda]  (FP64);  raises VL_ERR_NONFINITE on NaN/Inf.
 // With rep: rep[h * rep_m + c] = mean[c] for c < rep_m and h < rep_blocks as well.
 // With range_exp: range_exp[c] = e with |A(t, c) - mean[c mod centre_m]| < 2^e for every t < K
-// (from the column's range; centre_m = 0: ncol), and scratch holds 3 splits ncol doubles.
+// (from the column's range; centre_m = 0: ncol), and scratch holds 3 splits ncol doubles;
+// range_exp_own (with range_exp only): the same about the column's own mean.
 int colmeans(const float* A, int64_t lda, const int64_t* colmap, int64_t ncol, int64_t K,
              double* mean, double* scratch, int32_t* st, hipStream_t stream,
              double* rep = nullptr, int64_t rep_m = 0, int64_t rep_blocks = 0,
-             int32_t* range_exp = nullptr, int64_t centre_m = 0);
+             int32_t* range_exp = nullptr, int64_t centre_m = 0,
+             int32_t* range_exp_own = nullptr);
 
 // Split-K factor of gram_tn(); scratch must hold gram_splits(M,N,K) * M * N doubles.  About
 // 1024 workgroups (four per CU): with M == N the tiles counted are the lower triangle's, which

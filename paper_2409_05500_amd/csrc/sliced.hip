@@ -52,12 +52,24 @@ __global__ __launch_bounds__(256) void slc_cols_kernel(const float* __restrict__
   const bool vj = j < m;
   const double c = vj ? mu[j] : 0.0;
   const int ej = vj ? e[(int64_t)h * m + j] : 0;
-  for (int r = ty; r < 64; r += 4) {
-    const int64_t t = tb + r;
-    int d[kSlices] = {0, 0, 0, 0, 0, 0};
-    if (vj && t < K) digits6(ldexp((double)X[(t0 + t - h) * ldx + j] - c, -ej), d);
+  // thread (j, ty): samples 16 ty + [0, 16) in groups of four, each group's digits packed into
+  // one 32-bit LDS store per slice
 #pragma unroll
-    for (int s = 0; s < kSlices; ++s) sd[s][tx][r] = (int8_t)d[s];
+  for (int g4 = 0; g4 < 4; ++g4) {
+    const int r0 = 16 * ty + 4 * g4;
+    int d[4][kSlices];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t t = tb + r0 + q;
+#pragma unroll
+      for (int s = 0; s < kSlices; ++s) d[q][s] = 0;
+      if (vj && t < K) digits6(ldexp((double)X[(t0 + t - h) * ldx + j] - c, -ej), d[q]);
+    }
+#pragma unroll
+    for (int s = 0; s < kSlices; ++s)
+      *reinterpret_cast<uint32_t*>(&sd[s][tx][r0]) =
+          (uint32_t)(uint8_t)d[0][s] | ((uint32_t)(uint8_t)d[1][s] << 8) |
+          ((uint32_t)(uint8_t)d[2][s] << 16) | ((uint32_t)(uint8_t)d[3][s] << 24);
   }
   __syncthreads();
   for (int it = threadIdx.x; it < kSlices * 64 * 4; it += 256) {
@@ -79,8 +91,9 @@ int slice_columns(const float* X, int64_t ldx, int64_t m, int L, int64_t t0, int
 }
 
 // ------------------------------------------------------------------------------------------
-// Row slices: one wave per row, the row's exponent from a wave maximum, then four consecutive
-// K entries a lane, their digits packed into one 32-bit store per slice.
+// Design slices with a scale per design column: z_k(t) 2^-f[k], every value below 1 (f from the
+// column's range about its mean), no exponent per row.  Block: one K block of 32 columns x 8
+// samples; thread (k, t) writes its digit bytes at consecutive addresses along k.
 // ------------------------------------------------------------------------------------------
 __device__ __forceinline__ void store_digits4(int8_t* __restrict__ D, int64_t plane,
                                               int64_t off, const int (&d)[4][kSlices]) {
@@ -92,47 +105,38 @@ __device__ __forceinline__ void store_digits4(int8_t* __restrict__ D, int64_t pl
   }
 }
 
-__global__ __launch_bounds__(256) void slc_rows_kernel(const float* __restrict__ X, int64_t ldx,
-                                                       const int64_t* __restrict__ colmap,
-                                                       const double* __restrict__ mu, int64_t m,
-                                                       int64_t dz, int64_t n_eff,
-                                                       int8_t* __restrict__ D, int64_t kpad,
-                                                       int64_t plane, int32_t* __restrict__ e) {
-  const int lane = threadIdx.x & 63;
-  const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+__global__ __launch_bounds__(256) void slc_design_kernel(const float* __restrict__ X, int64_t ldx,
+                                                         const int64_t* __restrict__ colmap,
+                                                         const double* __restrict__ mu,
+                                                         const int32_t* __restrict__ f,
+                                                         int64_t m, int64_t dz, int64_t n_eff,
+                                                         int8_t* __restrict__ D,
+                                                         int64_t plane) {
+  const int kk = threadIdx.x & 31;
+  const int64_t k = (int64_t)blockIdx.x * 32 + kk;
+  const int64_t t = (int64_t)blockIdx.y * 8 + (threadIdx.x >> 5);
   if (t >= n_eff) return;
-  const int64_t* mapZ = colmap + m;
-  const double* muZ = mu + m;
-  double mx = 0.0;
-  for (int64_t k = lane; k < dz; k += 64)
-    mx = fmax(mx, fabs((double)X[mapZ[k] + t * ldx] - muZ[k]));
-  const int ex = exponent_of(wave_max_d(mx));
-  if (lane == 0) e[t] = ex;
-  for (int64_t k4 = 4 * (int64_t)lane; k4 < kpad; k4 += 256) {
-    int d[4][kSlices];
+  int d[kSlices] = {0, 0, 0, 0, 0, 0};
+  if (k < dz) digits6(ldexp((double)X[colmap[m + k] + t * ldx] - mu[m + k], -f[k]), d);
+  int8_t* dst = D + (int64_t)blockIdx.x * n_eff * 32 + t * 32 + kk;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t k = k4 + q;
-#pragma unroll
-      for (int s = 0; s < kSlices; ++s) d[q][s] = 0;
-      if (k < dz) digits6(ldexp((double)X[mapZ[k] + t * ldx] - muZ[k], -ex), d[q]);
-    }
-    store_digits4(D, plane, (k4 >> 5) * n_eff * 32 + t * 32 + (k4 & 31), d);
-  }
+  for (int s = 0; s < kSlices; ++s) dst[s * plane] = (int8_t)d[s];
 }
 
-int slice_design_rows(const float* X, int64_t ldx, const int64_t* colmap, const double* mu,
-                      int64_t m, int64_t dz, int64_t n_eff, int8_t* D, int32_t* e,
-                      hipStream_t stream) {
+int slice_design(const float* X, int64_t ldx, const int64_t* colmap, const double* mu,
+                 const int32_t* f, int64_t m, int64_t dz, int64_t n_eff, int8_t* D,
+                 hipStream_t stream) {
   const int64_t kpad = slice_ldk(dz);
-  slc_rows_kernel<<<(unsigned)ceil_div(n_eff, 4), 256, 0, stream>>>(
-      X, ldx, colmap, mu, m, dz, n_eff, D, kpad, n_eff * kpad, e);
+  dim3 g((unsigned)(kpad / 32), (unsigned)ceil_div(n_eff, 8));
+  slc_design_kernel<<<g, 256, 0, stream>>>(X, ldx, colmap, mu, f, m, dz, n_eff, D, n_eff * kpad);
   VL_LAUNCH_CHECK();
   return VL_OK;
 }
 
-// Columns of a row-major FP64 K x N matrix: one wave per column.
+// Columns of a row-major FP64 K x N matrix, entry k scaled by 2^f[k] (f == nullptr: none): one
+// wave per column.
 __global__ __launch_bounds__(256) void slc_matcols_kernel(const double* __restrict__ C,
+                                                          const int32_t* __restrict__ f,
                                                           int64_t K, int64_t N,
                                                           int8_t* __restrict__ D, int64_t kpad,
                                                           int64_t plane,
@@ -140,8 +144,9 @@ __global__ __launch_bounds__(256) void slc_matcols_kernel(const double* __restri
   const int lane = threadIdx.x & 63;
   const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (j >= N) return;
+  auto val = [&](int64_t k) { return f ? ldexp(C[k * N + j], f[k]) : C[k * N + j]; };
   double mx = 0.0;
-  for (int64_t k = lane; k < K; k += 64) mx = fmax(mx, fabs(C[k * N + j]));
+  for (int64_t k = lane; k < K; k += 64) mx = fmax(mx, fabs(val(k)));
   const int ex = exponent_of(wave_max_d(mx));
   if (lane == 0) e[j] = ex;
   for (int64_t k4 = 4 * (int64_t)lane; k4 < kpad; k4 += 256) {
@@ -151,17 +156,17 @@ __global__ __launch_bounds__(256) void slc_matcols_kernel(const double* __restri
       const int64_t k = k4 + q;
 #pragma unroll
       for (int s = 0; s < kSlices; ++s) d[q][s] = 0;
-      if (k < K) digits6(ldexp(C[k * N + j], -ex), d[q]);
+      if (k < K) digits6(ldexp(val(k), -ex), d[q]);
     }
     store_digits4(D, plane, (k4 >> 5) * N * 32 + j * 32 + (k4 & 31), d);
   }
 }
 
-int slice_matrix_columns(const double* C, int64_t K, int64_t N, int8_t* D, int32_t* e,
-                         hipStream_t stream) {
+int slice_matrix_columns(const double* C, const int32_t* f, int64_t K, int64_t N, int8_t* D,
+                         int32_t* e, hipStream_t stream) {
   const int64_t kpad = slice_ldk(K);
-  slc_matcols_kernel<<<(unsigned)ceil_div(N, 4), 256, 0, stream>>>(C, K, N, D, kpad, N * kpad,
-                                                                  e);
+  slc_matcols_kernel<<<(unsigned)ceil_div(N, 4), 256, 0, stream>>>(C, f, K, N, D, kpad,
+                                                                  N * kpad, e);
   VL_LAUNCH_CHECK();
   return VL_OK;
 }
@@ -247,7 +252,7 @@ __device__ __forceinline__ double slice_value(const v16i (&acc)[kSlices], int q,
 }
 
 __device__ __forceinline__ int row_exponent(const SliceOp& S, int64_t r) {
-  return S.e[S.e_period ? r % S.e_period : r];
+  return S.e ? S.e[S.e_period ? r % S.e_period : r] : 0;
 }
 
 // Workgroups are taken in an order that gives each XCD (block id mod 8) a contiguous range of

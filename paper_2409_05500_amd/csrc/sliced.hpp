@@ -23,7 +23,7 @@ struct SliceOp {
   const int8_t* D = nullptr;
   int64_t rows = 0;                // R
   int64_t plane = 0;               // bytes per plane
-  const int32_t* e = nullptr;      // exponent of row r: e[r mod e_period] (e[r] if 0)
+  const int32_t* e = nullptr;      // exponent of row r: e[r mod e_period] (e[r] if 0); null: 0
   int64_t e_period = 0;
 };
 
@@ -34,17 +34,19 @@ struct SliceOp {
 int slice_columns(const float* X, int64_t ldx, int64_t m, int L, int64_t t0, int64_t K,
                   const double* mu, const int32_t* e, int8_t* D, hipStream_t stream);
 
-// Slices of the rows of the VAR design: row t holds z_k(t) = X[colmap[m + k] + t ldx] -
-// mu[m + k] for k < dz, each row with its own exponent (written to e[t]).
+// Slices of the rows of the VAR design, each design column k scaled by 2^-f[k] (every value
+// below 1 in magnitude, so the rows need no exponent of their own): row t holds
+// z_k(t) 2^-f[k], z_k(t) = X[colmap[m + k] + t ldx] - mu[m + k], k < dz.
 // D: slice_bytes(n_eff, dz) bytes.
-int slice_design_rows(const float* X, int64_t ldx, const int64_t* colmap, const double* mu,
-                      int64_t m, int64_t dz, int64_t n_eff, int8_t* D, int32_t* e,
-                      hipStream_t stream);
+int slice_design(const float* X, int64_t ldx, const int64_t* colmap, const double* mu,
+                 const int32_t* f, int64_t m, int64_t dz, int64_t n_eff, int8_t* D,
+                 hipStream_t stream);
 
-// Slices of the columns of a row-major FP64 K x N matrix: row j holds C[k N + j], k < K.
-// D: slice_bytes(N, K) bytes.
-int slice_matrix_columns(const double* C, int64_t K, int64_t N, int8_t* D, int32_t* e,
-                         hipStream_t stream);
+// Slices of the columns of a row-major FP64 K x N matrix, entry k scaled by 2^f[k] (f nullable):
+// row j holds C[k N + j] 2^f[k], k < K, with its exponent in e[j].  D: slice_bytes(N, K) bytes.
+// With the design slices above, sum_k z_k(t) C_kj = sum_k (z_k(t) 2^-f[k]) (C_kj 2^f[k]).
+int slice_matrix_columns(const double* C, const int32_t* f, int64_t K, int64_t N, int8_t* D,
+                         int32_t* e, hipStream_t stream);
 
 // Split-K factor and partial size of slice_gram (splits * M * N doubles).
 int slice_gram_splits(int64_t M, int64_t N, int64_t K, bool sym);

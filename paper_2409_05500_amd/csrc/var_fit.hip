@@ -221,7 +221,7 @@ size_t var_ws_bytes(const VarPlan& v, void* base, VarWs* out) {
     w.slices = c.take<int8_t>(std::max(slice_bytes(nc, v.n_eff), slice_bytes(v.n_eff, v.dz)));
     w.slicesC = c.take<int8_t>(slice_bytes(v.m, v.dz));
     w.ex = c.take<int32_t>(nc);
-    w.ez = c.take<int32_t>(v.n_eff);
+    w.ez = c.take<int32_t>(nc);
     w.ec = c.take<int32_t>(v.m);
   }
   if (out) *out = w;
@@ -233,16 +233,15 @@ static int var_residual(const VarPlan& v, const VarWs& w, const float* X, int64_
   if (v.sliced) {
     // E = Yc - Zc Coef from the slices of the design rows and of the coefficient columns
     const int64_t kpad = slice_ldk(v.dz);
-    int rc = slice_design_rows(X, ldx, w.colmap, w.mu, v.m, v.dz, v.n_eff, w.slices, w.ez,
-                               stream);
+    const int32_t* f = w.ez + v.m;      // design column k: lag-embedded column m + k
+    int rc = slice_design(X, ldx, w.colmap, w.mu, f, v.m, v.dz, v.n_eff, w.slices, stream);
     if (rc) return rc;
-    rc = slice_matrix_columns(w.Coef, v.dz, v.m, w.slicesC, w.ec, stream);
+    rc = slice_matrix_columns(w.Coef, f, v.dz, v.m, w.slicesC, w.ec, stream);
     if (rc) return rc;
     SliceOp A, B;
     A.D = w.slices;
     A.rows = v.n_eff;
     A.plane = v.n_eff * kpad;
-    A.e = w.ez;
     B.D = w.slicesC;
     B.rows = v.m;
     B.plane = v.m * kpad;
@@ -327,7 +326,8 @@ static int var_normal_equations(const VarPlan& v, const VarWs& w, const float* X
     // (sliced: with each lag-embedded column's range exponent about its lag-0 mean)
     const bool fp64 = gmode == GramMode::kFp64 && !v.sliced;
     rc = colmeans(X, ldx, w.colmap, nc, n_eff, w.mu, w.scratch, st, stream,
-                  fp64 ? w.mu0 : nullptr, m, v.p + 1, v.sliced ? w.ex : nullptr, m);
+                  fp64 ? w.mu0 : nullptr, m, v.p + 1, v.sliced ? w.ex : nullptr, m,
+                  v.sliced ? w.ez : nullptr);
     if (rc) return rc;
     if (v.sliced) {
       // the same lag products F from int8 slices of the series centred by the lag-0 means

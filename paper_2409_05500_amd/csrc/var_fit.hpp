@@ -29,7 +29,7 @@ struct VarWs {
   int8_t* slices = nullptr;
   int8_t* slicesC = nullptr;  // coefficient columns (m rows of dz)
   int32_t* ex = nullptr;      // m (p+1): exponent per lag-embedded column
-  int32_t* ez = nullptr;      // n_eff: exponent per design row
+  int32_t* ez = nullptr;      // m (p+1): exponent per lag-embedded column about its own mean
   int32_t* ec = nullptr;      // m: exponent per coefficient column
 };
 
