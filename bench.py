@@ -38,6 +38,7 @@ MEASURED_TRAFFIC = {
     # FETCH_SIZE 35164.7 KiB x 2, WRITE_SIZE 8546.2 KiB x 1 per dispatch (18 dispatches)
     "39a8eef9fcc8ebb7e1bc804bd862522873d06c7fcea76aa0e8cda18e188e874f": 80768661,
 }
+HEADLINE_PREC = "sliced"
 STAGES = ("var_gram", "var_solve", "var_residual", "var_refine", "pairwise_cov",
           "pairwise_prep", "pairwise_moments", "pairwise_combine", "order", "estimate_b")
 BATCH_STAGES = ("batch_var", "batch_pairwise", "batch_moments", "batch_order_b")
@@ -540,7 +541,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    fit = api.Fitter(n, m, p, "mixed", dev)
+    # the headline: the fastest form that meets the FP64-grade accuracy bar (the int8-slice
+    # products, SLICED: the same config-2 parity tests as MIXED)
+    fit = api.Fitter(n, m, p, HEADLINE_PREC, dev)
     for _ in range(args.warmup):
         fit.run(X)
     fit.check()
@@ -573,19 +576,19 @@ def main():
     fp32r_s = time_steps(f32r, X, args.steps, torch)
     f32r.check()
 
-    # the int8-slice products (Ozaki scheme) in place of MIXED's FP64-MFMA ones, and its stages
-    fs = api.Fitter(n, m, p, "sliced", dev)
+    # MIXED (the FP64-MFMA products) on the same input, and its stages
+    fm = api.Fitter(n, m, p, "mixed", dev)
     for _ in range(args.warmup):
-        fs.run(X)
-    sliced_s = time_steps(fs, X, args.steps, torch)
-    fs.check()
+        fm.run(X)
+    mixed_s = time_steps(fm, X, args.steps, torch)
+    fm.check()
     _lib.profile_enable("*")
-    time_steps(fs, X, max(3, args.steps // 4), torch)
-    sliced_stage_ms = {}
+    time_steps(fm, X, max(3, args.steps // 4), torch)
+    mixed_stage_ms = {}
     for st in STAGES:
         ms, cnt = _lib.profile_read(st)
         if cnt:
-            sliced_stage_ms[st] = round(ms / cnt, 4)
+            mixed_stage_ms[st] = round(ms / cnt, 4)
     _lib.profile_enable(None)
 
     # the BF16-Gram form with FP64 refinement, its VAR stages, and its distance from MIXED
@@ -617,13 +620,13 @@ def main():
     def b_rel(a, b):
         return float((a - b).abs().max() / max(float(b.abs().max()), 1e-2))
     def dist(o):
-        return {"B0_rel": b_rel(o.B0, fit.B0), "B_lags_rel": b_rel(o.B_lags, fit.B_lags),
-                "same_order": bool(torch.equal(o.order, fit.order))}
+        return {"B0_rel": b_rel(o.B0, fm.B0), "B_lags_rel": b_rel(o.B_lags, fm.B_lags),
+                "same_order": bool(torch.equal(o.order, fm.order))}
     bf16_dev = dist(bf)
     modes_vs_mixed = {"fp32": dist(f32), "fp32_refined": dist(f32r), "bf16": bf16_dev,
-                      "sliced": dist(fs),
+                      "sliced": dist(fit),
                       "mixed_compensated": dict(dist(fc), S_max_abs_diff=float(
-                          (fc.S - fit.S).abs().max()))}
+                          (fc.S - fm.S).abs().max()))}
 
     # measured issue rates of this part (the roofline denominators' check)
     rates = api.probe_rates(dev)
@@ -645,7 +648,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": wl.name, "m": m, "n": n, "p": p, "noise": "student-t(4)",
-                   "precision": "mixed", "seed": args.seed},
+                   "precision": HEADLINE_PREC, "seed": args.seed},
         "roofline": {"kernel": "pairwise_moments_kernel", "bound": "alu",
                      "achieved": achieved / 1e12, "peak": TRANS_PEAK / 1e12,
                      "unit": "Ttrans/s", "frac": achieved / TRANS_PEAK,
@@ -660,13 +663,13 @@ def main():
         "pairwise_kernel_ms": k_s * 1e3,
         "pairwise_kernel_sample_evals_per_s": evals / k_s,
         "sample_evals_per_step": evals,
-        "fit_ms_mixed": step_s * 1e3,
+        "fit_ms_sliced": step_s * 1e3,
+        "fit_ms_mixed": mixed_s * 1e3,
         "fit_ms_fp32": fp32_s * 1e3,
         "fit_ms_fp32_refined": fp32r_s * 1e3,
         "fit_ms_bf16": bf16_s * 1e3,
         "fit_ms_mixed_compensated": comp_s * 1e3,
-        "fit_ms_sliced": sliced_s * 1e3,
-        "sliced_stage_ms": sliced_stage_ms,
+        "mixed_stage_ms": mixed_stage_ms,
         "pairwise_kernel_ms_compensated": cms / ccount,
         "bf16_stage_ms": bf16_stage_ms,
         "bf16_vs_mixed": bf16_dev,

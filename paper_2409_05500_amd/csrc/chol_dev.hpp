@@ -333,12 +333,19 @@ __device__ inline void store_y(const double (*Y)[kTL], const CholArgs& a, int64_
   }
 }
 
+// Entry threadIdx.x of block row b's original diagonal (1 past the matrix), the pivot floor's
+// reference; loaded by the critical tile's workgroup together with its operand tiles.
+__device__ inline double diag0_entry(const CholArgs& a, int64_t b) {
+  const int64_t i = b * kNb + threadIdx.x;
+  const bool ok = threadIdx.x < kNb && i < a.n;
+  return mask_f64(a.diag0[ok ? i : 0], ok) + (ok ? 0.0 : 1.0);
+}
+
 // The critical tile's epilogue: S = the updated diagonal block (identity-padded) is factored;
-// Y_b goes to the workspace.
+// Y_b goes to the workspace.  d0v: diag0_entry(a, b).
 __device__ inline void factor_diag_store(double (*S)[kTL], double (*Y)[kTL], double* buf,
-                                         double* D0, const CholArgs& a, int64_t b) {
-  const int64_t kb = blk_rows(a.n, b);
-  if (threadIdx.x < kNb) D0[threadIdx.x] = threadIdx.x < kb ? a.diag0[b * kNb + threadIdx.x] : 1.0;
+                                         double* D0, const CholArgs& a, int64_t b, double d0v) {
+  if (threadIdx.x < kNb) D0[threadIdx.x] = d0v;
   block_factor_inv(S, Y, buf, D0, a.st);
   store_y(Y, a, 0 + b);
 }
@@ -353,6 +360,8 @@ __device__ __attribute__((always_inline)) inline void chol_prologue_block(const 
   const int kb = (int)blk_rows(a.n, 0);
   double v[16];
   tile_fetch(v, a.A, a.lda, kb, kb);
+  const bool dk = (int)threadIdx.x < kb;
+  const double d0v = mask_f64(a.A[(dk ? threadIdx.x : 0) * (a.lda + 1)], dk) + (dk ? 0.0 : 1.0);
   for (int64_t i0 = 0; i0 < a.n; i0 += 4 * 256) {
     double dg[4];
 #pragma unroll
@@ -371,7 +380,7 @@ __device__ __attribute__((always_inline)) inline void chol_prologue_block(const 
     const int e = threadIdx.x + 256 * u, r = e >> 6, q = e & 63;
     S[r][q] = (r < kb && q < kb) ? v[u] : (r == q ? 1.0 : 0.0);
   }
-  if (threadIdx.x < kNb) D0[threadIdx.x] = threadIdx.x < kb ? a.A[threadIdx.x * (a.lda + 1)] : 1.0;
+  if (threadIdx.x < kNb) D0[threadIdx.x] = d0v;
   block_factor_inv(S, Y, buf, D0, a.st);
   store_y(Y, a, 0);
 }
@@ -450,6 +459,8 @@ __device__ __attribute__((always_inline)) inline void chol_step_item(const CholA
     // all global loads of the item are issued before the first product; cur follows the layout
     // of the item's last product (lower blocks for a diagonal tile)
     double cur[16], nxt[16];
+    const bool crit = diag && i == k + 1;
+    const double d0v = crit ? diag0_entry(a, k + 1) : 1.0;
     {
       double pa[16], py[16];
       if (diag) {
@@ -483,13 +494,13 @@ __device__ __attribute__((always_inline)) inline void chol_step_item(const CholA
 #pragma unroll
       for (int u = 0; u < 3; ++u) lo[u] = f64x4{0.0, 0.0, 0.0, 0.0};
       mm64_lower(X, lo);
-      if (i == k + 1) {
+      if (crit) {
         // the critical tile: updated block into X (identity-padded), then factor and invert
         __syncthreads();
         lower_each([&](int u, int r, int q) {
           X[r][q] = (r < ri && q < ri) ? cur[u] - lo[u >> 2][u & 3] : (r == q ? 1.0 : 0.0);
         });
-        factor_diag_store(X, Z, buf, D0, a, k + 1);
+        factor_diag_store(X, Z, buf, D0, a, k + 1, d0v);
         return;
       }
       lower_each([&](int u, int r, int q) {

@@ -50,12 +50,13 @@ __device__ __attribute__((always_inline)) inline double pivot_floor(double d0) {
 
 // ------------------------------------------------------------------------------------------
 // 16 x 16 leaf, one wave, registers only: lane r (r = lane % 16; the four 16-lane rows of the
-// wave hold the same data) keeps row r of the leaf in a[].  Column C: the pivot comes from lane
-// C, every lane scales its entry, l_r = a[C] / sqrt(d), and subtracts l_r l_q from its entries
-// q > C.  Entries right of the diagonal are updated too and never read.  The inverse: lane j
-// computes column j of the leaf's L^{-1} by forward substitution, reading the rows of L from the
-// lanes that hold them.  Values move between lanes by DPP row broadcasts (row_newbcast: every
-// lane of a 16-lane row receives lane n of that row).
+// wave hold the same data) keeps row r of the leaf in a[] and, in y[], the column r of the
+// leaf's inverse as the forward substitution L y = e_r runs column by column.  Column C: the
+// pivot comes from lane C; every lane forms l_r = a_r[C] / sqrt(d) and the final entry
+// Y[C][r] = y_C / sqrt(d); then for each later column Q the one broadcast l_Q = L[Q][C] serves
+// both the elimination, a_r[Q] -= l_r l_Q, and the substitution, y_Q -= l_Q Y[C][r].  Entries
+// right of the diagonal are updated too and never read.  Values move between lanes by DPP row
+// broadcasts (row_newbcast: every lane of a 16-lane row receives lane n of that row).
 // ------------------------------------------------------------------------------------------
 constexpr int kLeaf = 16;
 
@@ -68,14 +69,20 @@ __device__ __attribute__((always_inline)) inline double row_bcast(double v) {
 }
 
 template <int C, int Q>
-__device__ __attribute__((always_inline)) inline void leaf_update(double (&a)[kLeaf], double l) {
-  if constexpr (Q > C) a[Q] = fma(-l, row_bcast<Q>(l), a[Q]);
+__device__ __attribute__((always_inline)) inline void leaf_update(double (&a)[kLeaf],
+                                                                  double (&y)[kLeaf], double l,
+                                                                  double yc) {
+  if constexpr (Q > C) {
+    const double lq = row_bcast<Q>(l);   // L[Q][C]
+    a[Q] = fma(-l, lq, a[Q]);
+    y[Q] = fma(-lq, yc, y[Q]);
+  }
 }
 
 template <int C, int... Qs>
 __device__ __attribute__((always_inline)) inline void leaf_column(
-    std::integer_sequence<int, Qs...>, double (&a)[kLeaf], int r, double floor_own,
-    double& isd_own, bool& bad_any) {
+    std::integer_sequence<int, Qs...>, double (&a)[kLeaf], double (&y)[kLeaf], double floor_own,
+    bool& bad_any) {
   const double d_raw = row_bcast<C>(a[C]);
   const double fl = row_bcast<C>(floor_own);
   bad_any |= !(d_raw > fl) || !isfinite(d_raw);
@@ -84,64 +91,35 @@ __device__ __attribute__((always_inline)) inline void leaf_column(
   // leaf's values only need to stay finite)
   const SqrtPair sp = sqrt_pair_f64(d);
   const double l = (2.0 * a[C]) * sp.h;
-  a[C] = l;
-  if (r == C) isd_own = 2.0 * sp.h;
-  (leaf_update<C, Qs>(a, l), ...);
-}
-
-template <int RR, int Q>
-__device__ __attribute__((always_inline)) inline void leaf_inverse_term(
-    double& s0, double& s1, const double (&a)[kLeaf], const double (&y)[kLeaf]) {
-  if constexpr (Q < RR) {
-    const double lq = row_bcast<RR>(a[Q]);        // L[RR][Q]
-    if constexpr ((Q & 1) != 0) s1 = fma(lq, y[Q], s1);
-    else s0 = fma(lq, y[Q], s0);
-  }
-}
-
-template <int RR, int... Qs>
-__device__ __attribute__((always_inline)) inline void leaf_inverse_row(
-    std::integer_sequence<int, Qs...>, double (&y)[kLeaf], const double (&a)[kLeaf], int j,
-    double isd_own) {
-  double s0 = 0.0, s1 = 0.0;
-  (leaf_inverse_term<RR, Qs>(s0, s1, a, y), ...);
-  const double id = row_bcast<RR>(isd_own);
-  y[RR] = j == RR ? id : (j < RR ? -id * (s0 + s1) : 0.0);
+  const double yc = y[C] * (2.0 * sp.h);
+  y[C] = yc;
+  (leaf_update<C, Qs>(a, y, l, yc), ...);
 }
 
 template <int... Cs>
 __device__ __attribute__((always_inline)) inline void leaf_factor(
-    std::integer_sequence<int, Cs...>, double (&a)[kLeaf], int r, double floor_own,
-    double& isd_own, bool& bad_any) {
-  (leaf_column<Cs>(std::make_integer_sequence<int, kLeaf>{}, a, r, floor_own, isd_own, bad_any),
-   ...);
+    std::integer_sequence<int, Cs...>, double (&a)[kLeaf], double (&y)[kLeaf], double floor_own,
+    bool& bad_any) {
+  (leaf_column<Cs>(std::make_integer_sequence<int, kLeaf>{}, a, y, floor_own, bad_any), ...);
 }
 
-template <int... Rs>
-__device__ __attribute__((always_inline)) inline void leaf_inverse(
-    std::integer_sequence<int, Rs...>, double (&y)[kLeaf], const double (&a)[kLeaf], int j,
-    double isd_own) {
-  (leaf_inverse_row<Rs>(std::make_integer_sequence<int, kLeaf>{}, y, a, j, isd_own), ...);
-}
-
-// The leaf at (b, b): its L into S (lower part; the part right of the diagonal is scratch) and
-// its inverse into the same block of Y.  Called by one whole wave.
-__device__ __attribute__((always_inline)) inline void leaf_factor_inv(double (*S)[kLd],
+// The leaf at (b, b): its inverse into the same block of Y (zeros above the diagonal included).
+// S is read, not written: the callers need only the inverse of a diagonal leaf.  Called by one
+// whole wave.
+__device__ __attribute__((always_inline)) inline void leaf_factor_inv(const double (*S)[kLd],
                                                                        double (*Y)[kLd],
                                                                        const double* D0, int b,
                                                                        bool& bad_any) {
   const int lane = threadIdx.x & 63, r = lane & 15;
-  double a[kLeaf];
+  double a[kLeaf], y[kLeaf];
 #pragma unroll
-  for (int q = 0; q < kLeaf; ++q) a[q] = S[b + r][b + q];
+  for (int q = 0; q < kLeaf; ++q) {
+    a[q] = S[b + r][b + q];
+    y[q] = q == r ? 1.0 : 0.0;
+  }
   const double floor_own = pivot_floor(D0[b + r]);
-  double isd_own = 1.0;
-  leaf_factor(std::make_integer_sequence<int, kLeaf>{}, a, r, floor_own, isd_own, bad_any);
-  double y[kLeaf];
-  leaf_inverse(std::make_integer_sequence<int, kLeaf>{}, y, a, r, isd_own);
+  leaf_factor(std::make_integer_sequence<int, kLeaf>{}, a, y, floor_own, bad_any);
   if (lane < kLeaf) {
-#pragma unroll
-    for (int q = 0; q < kLeaf; ++q) S[b + r][b + q] = a[q];
 #pragma unroll
     for (int rr = 0; rr < kLeaf; ++rr) Y[b + rr][b + r] = y[rr];
   }
@@ -187,9 +165,9 @@ __device__ __attribute__((always_inline)) inline void inv_block(double (*S)[kLd]
 }
 
 // Factor and invert the 64 x 64 block already in S (LDS; rows / columns >= kb hold the identity)
-// with D0 (LDS) the diagonal before any elimination.  On return the lower triangle of S holds
-// L11 and Y holds L11^{-1} (strict upper triangle zero); buf is kFactorBuf doubles of LDS
-// scratch.  Raises VL_ERR_SINGULAR on a rejected pivot.  Starts and ends with a workgroup
+// with D0 (LDS) the diagonal before any elimination.  On return Y holds L11^{-1} (strict upper
+// triangle zero) and the blocks of S below the diagonal leaves hold those of L11 (the leaves
+// themselves keep the updated input); buf is kFactorBuf doubles of LDS scratch.  Raises VL_ERR_SINGULAR on a rejected pivot.  Starts and ends with a workgroup
 // barrier.  Blocked by 16-column leaves (right-looking), 16 x 16 block products on MFMA; after
 // leaf s:
 //   panel (wave per block row):  L_is = A_is L_ss^{-T} for the block rows i > s
