@@ -162,7 +162,7 @@ template <bool kTP, bool kTQ>
 __device__ inline void mm64(const double (*P)[kTL], const double (*Q)[kTL], f64x4 (&acc)[2][2]) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wi = w >> 1, wj = w & 1, lr = lane & 15, lk = lane >> 4;
-#pragma unroll 4
+#pragma unroll
   for (int kk = 0; kk < kNb; kk += 4) {
     double a[2], b[2];
 #pragma unroll
@@ -254,7 +254,7 @@ __device__ inline void mm64_lower(const double (*P)[kTL], f64x4 (&acc)[3]) {
   int n = 0;
 #pragma unroll
   for (int b = 0; b < 3; ++b) n = lower_blocks(w, b, bi[b], bj[b]);
-#pragma unroll 4
+#pragma unroll
   for (int kk = 0; kk < kNb; kk += 4) {
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
@@ -323,7 +323,7 @@ __host__ __device__ inline StepItems step_items(int64_t nb, int64_t k, int64_t c
   return s;
 }
 
-// Y_b (zeros above the diagonal) to the workspace
+// Y_b (zeros above the diagonal; the LDS tile's upper part is not read) to the workspace
 __device__ inline void store_y(const double (*Y)[kTL], const CholArgs& a, int64_t b) {
   double* Yo = a.Yb + b * kNb * kNb;
 #pragma unroll
@@ -341,13 +341,31 @@ __device__ inline double diag0_entry(const CholArgs& a, int64_t b) {
   return mask_f64(a.diag0[ok ? i : 0], ok) + (ok ? 0.0 : 1.0);
 }
 
-// The critical tile's epilogue: S = the updated diagonal block (identity-padded) is factored;
-// Y_b goes to the workspace.  d0v: diag0_entry(a, b).
-__device__ inline void factor_diag_store(double (*S)[kTL], double (*Y)[kTL], double* buf,
-                                         double* D0, const CholArgs& a, int64_t b, double d0v) {
-  if (threadIdx.x < kNb) D0[threadIdx.x] = d0v;
-  block_factor_inv(S, Y, buf, D0, a.st);
-  store_y(Y, a, 0 + b);
+// The critical tile's lower 16 x 16 blocks of L L^T, in row order (0,0) (1,0) (1,1) (2,0) ...
+// (3,3): wave 0 takes block 0 alone (leaf 0 of the factorisation follows at once), waves 1..3
+// take three each.  Returns the number of blocks of wave w; block b of the wave is (bi, bj).
+__device__ inline int crit_blocks(int w, int b, int& bi, int& bj) {
+  const int f = w == 0 ? 0 : 3 * (w - 1) + b + 1;
+  bi = f >= 6 ? 3 : (f >= 3 ? 2 : (f >= 1 ? 1 : 0));
+  bj = f - bi * (bi + 1) / 2;
+  return w == 0 ? 1 : 3;
+}
+
+// f(slot, row, column) for the (up to 12) positions a lane holds in the critical tile's blocks:
+// block b, register r of the 16 x 16 product -> slot 4 b + r
+template <class F>
+__device__ inline void crit_each(F f) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    int bi, bj;
+    const int n = crit_blocks(w, b, bi, bj);
+    if (b < n) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        f(4 * b + r, 16 * bi + (lane >> 4) + 4 * r, 16 * bj + (lane & 15));
+    }
+  }
 }
 
 // Step 0's diagonal block: the original diagonal is saved for the pivot test, block 0 is
@@ -463,7 +481,12 @@ __device__ __attribute__((always_inline)) inline void chol_step_item(const CholA
     const double d0v = crit ? diag0_entry(a, k + 1) : 1.0;
     {
       double pa[16], py[16];
-      if (diag) {
+      if (crit) {
+        crit_each([&](int u, int r, int q) {
+          const bool ok = r < ri && q < cols;
+          cur[u] = out[(int64_t)(ok ? r : 0) * ldo + (ok ? q : 0)];
+        });
+      } else if (diag) {
         lower_each([&](int u, int r, int q) {
           const bool ok = r < ri && q < cols;
           cur[u] = out[(int64_t)(ok ? r : 0) * ldo + (ok ? q : 0)];
@@ -480,12 +503,67 @@ __device__ __attribute__((always_inline)) inline void chol_step_item(const CholA
       if (src2) tile_fetch(nxt, src2, ld2, (int)rows2, (int)cols2);
       tile_put(X, pa);
       tile_put(Z, py);
+      if (crit && threadIdx.x < kNb) D0[threadIdx.x] = d0v;
     }
     __syncthreads();
     f64x4 l1[4];
     tri_zero(l1);
     mm64_tri(X, Z, l1);                              // L_ik
     __syncthreads();
+    if (crit) {
+      // The critical tile: S = A_ii - L_ik L_ik^T (identity-padded) goes to Z block by block,
+      // (0,0) first: wave 0 factors leaf 0 of S while waves 1..3 form the other nine blocks.
+      // L_ik stays in X until every block is formed; Y (the factor's inverse) then takes X.
+      tri_each(l1, [&](int r, int q, double v) { X[r][q] = v; });
+      __syncthreads();
+      const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+      // register rr of a block product: row 16 bi + lane / 16 + 4 rr, column 16 bj + lane % 16
+      auto put_s = [&](int b, int bi, int bj, const f64x4_t& p) {
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int r = 16 * bi + (lane >> 4) + 4 * rr, q = 16 * bj + (lane & 15);
+          Z[r][q] = (r < ri && q < ri) ? cur[4 * b + rr] - p[rr] : (r == q ? 1.0 : 0.0);
+        }
+      };
+      if (w == 0) {
+        // block (0,0): four partial sums over the K quarters (independent MFMA chains)
+        f64x4_t p[4];
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) {
+          p[kc] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+          mfma_blk16<true>(&X[0][16 * kc], kTL, &X[0][16 * kc], kTL, p[kc]);
+        }
+        put_s(0, 0, 0, (p[0] + p[1]) + (p[2] + p[3]));
+      } else {
+        // three blocks, their MFMA chains interleaved
+        int bi[3], bj[3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) crit_blocks(w, b, bi[b], bj[b]);
+        f64x4_t p[3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) p[b] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+        const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+        for (int kk = 0; kk < kNb; kk += 4) {
+#pragma unroll
+          for (int b = 0; b < 3; ++b)
+            p[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(X[16 * bi[b] + li][kk + lk],
+                                                         X[16 * bj[b] + li][kk + lk], p[b], 0,
+                                                         0, 0);
+        }
+#pragma unroll
+        for (int b = 0; b < 3; ++b) put_s(b, bi[b], bj[b], p[b]);
+      }
+      double y0[kLeaf];
+      bool bad_any = false;
+      if (w == 0) leaf_factor_regs(Z, D0, 0, bad_any, y0);   // reads only its own block
+      __syncthreads();
+      if (w == 0) leaf_store_y(X, 0, y0);
+      __syncthreads();
+      block_factor_rest(Z, X, buf, D0, a.st, bad_any);
+      store_y(X, a, k + 1);
+      return;
+    }
     if (diag) {
       // L_ik L_ik^T, lower blocks only
       tri_each(l1, [&](int r, int q, double v) { X[r][q] = v; });
@@ -494,15 +572,6 @@ __device__ __attribute__((always_inline)) inline void chol_step_item(const CholA
 #pragma unroll
       for (int u = 0; u < 3; ++u) lo[u] = f64x4{0.0, 0.0, 0.0, 0.0};
       mm64_lower(X, lo);
-      if (crit) {
-        // the critical tile: updated block into X (identity-padded), then factor and invert
-        __syncthreads();
-        lower_each([&](int u, int r, int q) {
-          X[r][q] = (r < ri && q < ri) ? cur[u] - lo[u >> 2][u & 3] : (r == q ? 1.0 : 0.0);
-        });
-        factor_diag_store(X, Z, buf, D0, a, k + 1, d0v);
-        return;
-      }
       lower_each([&](int u, int r, int q) {
         if (r < ri && q < cols) out[(int64_t)r * ldo + q] = cur[u] - lo[u >> 2][u & 3];
       });

@@ -103,15 +103,15 @@ __device__ __attribute__((always_inline)) inline void leaf_factor(
   (leaf_column<Cs>(std::make_integer_sequence<int, kLeaf>{}, a, y, floor_own, bad_any), ...);
 }
 
-// The leaf at (b, b): its inverse into the same block of Y (zeros above the diagonal included).
-// S is read, not written: the callers need only the inverse of a diagonal leaf.  Called by one
-// whole wave.
-__device__ __attribute__((always_inline)) inline void leaf_factor_inv(const double (*S)[kLd],
-                                                                       double (*Y)[kLd],
-                                                                       const double* D0, int b,
-                                                                       bool& bad_any) {
-  const int lane = threadIdx.x & 63, r = lane & 15;
-  double a[kLeaf], y[kLeaf];
+// The leaf at (b, b) of S: on return y[rr] = Y[b + rr][b + r] (r = lane % 16) of its inverse,
+// zeros above the diagonal included.  S is read, not written: the callers need only the
+// inverse of a diagonal leaf.  Called by one whole wave.
+__device__ __attribute__((always_inline)) inline void leaf_factor_regs(const double (*S)[kLd],
+                                                                        const double* D0, int b,
+                                                                        bool& bad_any,
+                                                                        double (&y)[kLeaf]) {
+  const int r = threadIdx.x & 15;
+  double a[kLeaf];
 #pragma unroll
   for (int q = 0; q < kLeaf; ++q) {
     a[q] = S[b + r][b + q];
@@ -119,10 +119,25 @@ __device__ __attribute__((always_inline)) inline void leaf_factor_inv(const doub
   }
   const double floor_own = pivot_floor(D0[b + r]);
   leaf_factor(std::make_integer_sequence<int, kLeaf>{}, a, y, floor_own, bad_any);
+}
+
+__device__ __attribute__((always_inline)) inline void leaf_store_y(double (*Y)[kLd], int b,
+                                                                    const double (&y)[kLeaf]) {
+  const int lane = threadIdx.x & 63;
   if (lane < kLeaf) {
 #pragma unroll
-    for (int rr = 0; rr < kLeaf; ++rr) Y[b + rr][b + r] = y[rr];
+    for (int rr = 0; rr < kLeaf; ++rr) Y[b + rr][b + lane] = y[rr];
   }
+}
+
+// The leaf at (b, b): its inverse into the same block of Y.
+__device__ __attribute__((always_inline)) inline void leaf_factor_inv(const double (*S)[kLd],
+                                                                       double (*Y)[kLd],
+                                                                       const double* D0, int b,
+                                                                       bool& bad_any) {
+  double y[kLeaf];
+  leaf_factor_regs(S, D0, b, bad_any, y);
+  leaf_store_y(Y, b, y);
 }
 
 typedef double f64x4_t __attribute__((ext_vector_type(4)));
@@ -165,11 +180,13 @@ __device__ __attribute__((always_inline)) inline void inv_block(double (*S)[kLd]
 }
 
 // Factor and invert the 64 x 64 block already in S (LDS; rows / columns >= kb hold the identity)
-// with D0 (LDS) the diagonal before any elimination.  On return Y holds L11^{-1} (strict upper
-// triangle zero) and the blocks of S below the diagonal leaves hold those of L11 (the leaves
-// themselves keep the updated input); buf is kFactorBuf doubles of LDS scratch.  Raises VL_ERR_SINGULAR on a rejected pivot.  Starts and ends with a workgroup
-// barrier.  Blocked by 16-column leaves (right-looking), 16 x 16 block products on MFMA; after
-// leaf s:
+// with D0 (LDS) the diagonal before any elimination.  On return Y holds L11^{-1} in its diagonal
+// 16 x 16 blocks (zeros above their diagonals included) and in the blocks below them; the blocks
+// above are neither written nor read.  The blocks of S below the diagonal leaves hold those of
+// L11 (the leaves themselves keep the updated input); buf is kFactorBuf doubles of LDS
+// scratch.  Raises
+// VL_ERR_SINGULAR on a rejected pivot.  Starts and ends with a workgroup barrier.  Blocked by
+// 16-column leaves (right-looking), 16 x 16 block products on MFMA; after leaf s:
 //   panel (wave per block row):  L_is = A_is L_ss^{-T} for the block rows i > s
 //   then wave 0 alone updates the next diagonal block, A_{s+1,s+1} -= L_{s+1,s} L_{s+1,s}^T,
 //   and factors leaf s + 1 at once, while waves 1.. apply the rest of the trailing update
@@ -178,18 +195,18 @@ __device__ __attribute__((always_inline)) inline void inv_block(double (*S)[kLd]
 //   < s).  The last row of L^{-1} follows the last leaf.
 constexpr int kFactorBuf = 3 * kLeaf * kLeaf;
 
-__device__ __attribute__((always_inline)) inline void block_factor_inv(double (*S)[kLd],
-                                                                        double (*Y)[kLd],
-                                                                        double* buf,
-                                                                        const double* D0,
-                                                                        int32_t* st) {
+//
+// block_factor_rest is the part after leaf 0: it starts once Y's block (0, 0) holds the leaf's
+// inverse and S holds the input (a workgroup barrier after those writes); bad_any carries the
+// pivot test of leaf 0.
+__device__ __attribute__((always_inline)) inline void block_factor_rest(double (*S)[kLd],
+                                                                         double (*Y)[kLd],
+                                                                         double* buf,
+                                                                         const double* D0,
+                                                                         int32_t* st,
+                                                                         bool bad_any) {
   const int tid = threadIdx.x, w = tid >> 6;
   constexpr int kB = kNb / kLeaf;  // 4 block rows
-  for (int e = tid; e < kNb * kNb; e += 256) Y[e >> 6][e & 63] = 0.0;
-  __syncthreads();
-  bool bad_any = false;
-  if (w == 0) leaf_factor_inv(S, Y, D0, 0, bad_any);
-  __syncthreads();
   for (int sb = 0; sb < kB - 1; ++sb) {
     const int b = sb * kLeaf;
     // panel: wave w takes block row sb + 1 + w (reads and writes only its own block)
@@ -232,6 +249,18 @@ __device__ __attribute__((always_inline)) inline void block_factor_inv(double (*
   if (w < kB - 1) inv_block(S, Y, buf + w * kLeaf * kLeaf, kB - 1, w);
   __syncthreads();
   if (bad_any) raise_status(st, VL_ERR_SINGULAR);
+}
+
+__device__ __attribute__((always_inline)) inline void block_factor_inv(double (*S)[kLd],
+                                                                        double (*Y)[kLd],
+                                                                        double* buf,
+                                                                        const double* D0,
+                                                                        int32_t* st) {
+  __syncthreads();
+  bool bad_any = false;
+  if ((threadIdx.x >> 6) == 0) leaf_factor_inv(S, Y, D0, 0, bad_any);
+  __syncthreads();
+  block_factor_rest(S, Y, buf, D0, st, bad_any);
 }
 
 }  // namespace vl
