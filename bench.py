@@ -35,8 +35,8 @@ TRANS_PER_EVAL = 3
 # exactly: x1).  Keyed by the SHA-256 of the kernel sources the counters were taken with
 # (kernel_source_digest); any other source reports null.
 MEASURED_TRAFFIC = {
-    # FETCH_SIZE 35164.7 KiB x 2, WRITE_SIZE 8546.2 KiB x 1 per dispatch (18 dispatches)
-    "39a8eef9fcc8ebb7e1bc804bd862522873d06c7fcea76aa0e8cda18e188e874f": 80768661,
+    # FETCH_SIZE 35619.3 KiB x 2, WRITE_SIZE 8534.9 KiB x 1 per dispatch (24 dispatches)
+    "9c3f5650953d15594460fd06170797ec504d0b1f40359f4630bfa99cb262d0e9": 81688064,
 }
 HEADLINE_PREC = "sliced"
 STAGES = ("var_gram", "var_solve", "var_residual", "var_refine", "pairwise_cov",
