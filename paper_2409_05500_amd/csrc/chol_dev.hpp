@@ -47,40 +47,60 @@ __device__ __attribute__((always_inline)) inline void gemm_f64_block(
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = f64x4g{0.0, 0.0, 0.0, 0.0};
-  // operands of the next 16-wide K slice are loaded while the current one is multiplied
+  // operands of the next 16-wide K slice are loaded while the current one is multiplied; the
+  // padding is masked when a slice is used, not when it is loaded (masking a loaded value
+  // waits for it, which would leave no load in flight across the products)
   double a[4][2], b[4][2], an[4][2], bn[4][2];
   auto load = [&](int64_t k0, double (&pa)[4][2], double (&pb)[4][2]) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int64_t k = k0 + 4 * s + lk;
-      const bool vk = k < we;
-      const int64_t kc = vk ? k : (K > 0 ? K - 1 : 0);
+      const int64_t kc = k < we ? k : (K > 0 ? K - 1 : 0);
 #pragma unroll
       for (int x = 0; x < 2; ++x) {
-        const double av = transA ? A[kc * lda + ra[x]] : A[ra[x] * lda + kc];
-        const double bv = transB ? Bm[cb[x] * ldb + kc] : Bm[kc * ldb + cb[x]];
-        pa[s][x] = mask_f64(av, vk && vr[x]);
-        pb[s][x] = mask_f64(bv, vk && vc[x]);
+        pa[s][x] = transA ? A[kc * lda + ra[x]] : A[ra[x] * lda + kc];
+        pb[s][x] = transB ? Bm[cb[x] * ldb + kc] : Bm[kc * ldb + cb[x]];
       }
     }
   };
-  if (wb < we) load(wb, a, b);
-  for (int64_t k0 = wb; k0 < we; k0 += 16) {
-    if (k0 + 16 < we) load(k0 + 16, an, bn);
+  auto mask = [&](int64_t k0, double (&pa)[4][2], double (&pb)[4][2]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const bool vk = k0 + 4 * s + lk < we;
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        pa[s][x] = mask_f64(pa[s][x], vk && vr[x]);
+        pb[s][x] = mask_f64(pb[s][x], vk && vc[x]);
+      }
+    }
+  };
+  auto mul = [&](const double (&pa)[4][2], const double (&pb)[4][2]) {
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y)
-          acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s][x], b[s][y], acc[x][y], 0, 0, 0);
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int x = 0; x < 2; ++x) {
-        a[s][x] = an[s][x];
-        b[s][x] = bn[s][x];
-      }
+          acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[s][x], pb[s][y], acc[x][y], 0, 0, 0);
+  };
+  // two slices per trip, the buffers alternating (a copy of a buffer still being loaded would
+  // wait for it); the next slice is loaded unconditionally (clamped addresses, masked on use)
+  // so that the wait before a slice's use leaves the following slice's loads in flight
+  // (the scheduling barriers keep each slice's loads ahead of the previous slice's products)
+  if (wb < we) {
+    load(wb, a, b);
+    for (int64_t k0 = wb;; k0 += 32) {
+      load(k0 + 16, an, bn);
+      __builtin_amdgcn_sched_barrier(0);
+      mask(k0, a, b);
+      mul(a, b);
+      if (k0 + 16 >= we) break;
+      load(k0 + 32, a, b);
+      __builtin_amdgcn_sched_barrier(0);
+      mask(k0 + 16, an, bn);
+      mul(an, bn);
+      if (k0 + 32 >= we) break;
+    }
   }
   // result element (x, y, r) of this lane: row x*16 + lk + 4r, column y*16 + li of the block
   if (w > 0) {
