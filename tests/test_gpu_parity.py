@@ -193,7 +193,7 @@ def test_order_nonfinite_raises(api, dev):
     assert ei.value.code == VL_ERR_NONFINITE
 
 
-@pytest.mark.parametrize("m", [30, 100])
+@pytest.mark.parametrize("m", [30, 100, 300])
 def test_order_nonfinite_rows_still_give_a_permutation(api, dev, m):
     """Rows 10..19 of S hold -inf, so their M is +inf like the removed entries: the status is
     VL_ERR_NONFINITE, and the order must still be a permutation (no removed variable picked
@@ -210,10 +210,33 @@ def test_order_nonfinite_rows_still_give_a_permutation(api, dev, m):
     assert sorted(order.cpu().numpy().tolist()) == list(range(m))
 
 
-def test_order_ties_lowest_index(api, dev):
-    order, margin = api.approx_order(_dev(np.zeros((5, 5)), dev))
-    assert order.cpu().numpy().tolist() == [0, 1, 2, 3, 4]
+@pytest.mark.parametrize("m", [5, 130, 300, 700])
+def test_order_ties_lowest_index(api, dev, m):
+    """Every M equal at every step: the lowest index wins, also once the live entries have been
+    packed into fewer slots per lane (m > 64)."""
+    order, margin = api.approx_order(_dev(np.zeros((m, m)), dev))
+    assert order.cpu().numpy().tolist() == list(range(m))
     assert np.all(margin.cpu().numpy()[:-1] == 0.0)
+
+
+@pytest.mark.parametrize("h", [40, 150, 260])
+def test_order_duplicated_variables_ties(api, dev, h):
+    """Variables 2i and 2i+1 have identical rows and columns of S (their pair scores 0), so their
+    M stay exactly equal through every update: each pair is taken lower index first, in the
+    oracle's order, across the stages of fewer slots per lane."""
+    rng = np.random.default_rng(h)
+    A = rng.normal(size=(h, h))
+    A = A - A.T
+    S = np.kron(A, np.ones((2, 2)))
+    for i in range(h):
+        S[2 * i, 2 * i + 1] = S[2 * i + 1, 2 * i] = 0.0
+    order, margin = api.approx_order(_dev(S, dev))
+    oo, _ = O.approx_order(S)
+    got = order.cpu().numpy()
+    assert np.array_equal(got, oo)
+    pos = np.empty(2 * h, int)
+    pos[got] = np.arange(2 * h)
+    assert np.all(pos[0::2] < pos[1::2])
 
 
 # ------------------------------------------------------------------------------------------
