@@ -391,7 +391,8 @@ int varlingam_edge_frequency(const int32_t* orders, const double* B0s, const dou
 /* kept if the fit gets at least 1% faster); then it rebinds.  Choices are cached per       */
 /* device, precision and bucket in the process and in a text file: $VL_TUNE_CACHE (empty:  */
 /* no file), else $XDG_CACHE_HOME/varlingam/batch_tune.txt, else                            */
-/* $HOME/.cache/varlingam/batch_tune.txt; buckets found there are not timed again.          */
+/* $HOME/.cache/varlingam/batch_tune.txt, named anew at each call (the process's copy is   */
+/* read again when a call names another file); buckets found there are not timed again.    */
 /* Calls on one batch must not overlap.  varlingam_batch_chunk_len() returns the length of  */
 /* the bucket with the most problems, varlingam_batch_chunk_len_of() that of one problem    */
 /* (0 for a bad index).                                                                     */

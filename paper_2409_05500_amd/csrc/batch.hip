@@ -740,10 +740,12 @@ int launch_fit(const vl_batch* B, void* ws, int32_t* st, hipStream_t s) {
 // the process and in a text file (one "key chunk" line per bucket), read before tuning and
 // rewritten after it through a temporary file and a rename.  The file is
 // $VL_TUNE_CACHE if that is set (an empty value turns the file off), else
-// $XDG_CACHE_HOME/varlingam/batch_tune.txt, else $HOME/.cache/varlingam/batch_tune.txt.
-// File errors only cost a re-tune.
+// $XDG_CACHE_HOME/varlingam/batch_tune.txt, else $HOME/.cache/varlingam/batch_tune.txt,
+// taken at each call: the process's copy is that of the file named by the last call, and is
+// read afresh when a call names another file.  File errors only cost a re-tune.
 std::mutex g_tune_mu;
 std::map<std::string, int> g_tune_cache;
+std::string g_tune_path;
 bool g_tune_loaded = false;
 
 std::string tune_file() {
@@ -899,8 +901,10 @@ int varlingam_batch_autotune(vl_batch* B, void* ws, size_t ws_bytes, int32_t* de
   std::vector<int> todo;
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
-    if (!g_tune_loaded) {
+    if (!g_tune_loaded || path != g_tune_path) {
+      g_tune_cache.clear();
       tune_read(path, g_tune_cache);
+      g_tune_path = path;
       g_tune_loaded = true;
     }
     for (int k : occupied) {
