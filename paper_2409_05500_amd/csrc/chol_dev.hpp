@@ -26,6 +26,23 @@ __device__ __attribute__((always_inline)) inline void gemm_f64_block(
   __shared__ double part[3][32 * 32];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
   if (lower_only && j0 > i0 + 31) return;
+  // the beta term's inputs of wave 0's outputs, loaded before the products so that their
+  // latency is hidden (clamped in-bounds addresses; only in-range elements use them)
+  double cin[2][2][4];
+  const bool use_c0 = beta != 0.0;
+  if (use_c0 && w == 0) {
+    const double* src = C0 ? C0 : C;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t gi = i0 + x * 16 + lk + 4 * r, gj = j0 + y * 16 + li;
+          const bool ok = gi < M && gj < N;
+          cin[x][y][r] = src[(ok ? gi : 0) * ldc + (ok ? gj : 0)];
+        }
+  }
   int64_t kb = 0, ke = K;
   if (tri == 2) kb = i0 < K ? i0 : K;
   if (tri == 1) ke = i0 + 32 < K ? i0 + 32 : K;
@@ -124,11 +141,8 @@ __device__ __attribute__((always_inline)) inline void gemm_f64_block(
           const double v = ((acc[x][y][r] + part[0][rr * 32 + cc]) + part[1][rr * 32 + cc]) +
                            part[2][rr * 32 + cc];
           const int64_t gi = i0 + rr, gj = j0 + cc;
-          if (gi < M && gj < N && (!lower_only || gj <= gi)) {
-            double* c = C + gi * ldc + gj;
-            const double c0 = beta == 0.0 ? 0.0 : (C0 ? C0[gi * ldc + gj] : *c);
-            *c = beta * c0 + alpha * v;
-          }
+          if (gi < M && gj < N && (!lower_only || gj <= gi))
+            C[gi * ldc + gj] = beta * (use_c0 ? cin[x][y][r] : 0.0) + alpha * v;
         }
   }
 }
