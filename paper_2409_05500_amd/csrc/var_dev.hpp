@@ -24,6 +24,10 @@ __device__ inline void var_residual_tile_f32(
   const int64_t* mapZ = colmap + m;
   const double* muZ = mu + m;
   f32x16 acc = {};
+  // the output column's offset and mean, read before the products
+  const int64_t jo = j0 + wj * 32 + (lane & 31);
+  const int64_t offy = colmap[jo < m ? jo : 0];
+  const float muy = (float)mu[jo < m ? jo : 0];
   for (int64_t k0 = 0; k0 < dz; k0 += 32) {
     {
       const int kk = tid & 31, tt = tid >> 5;
@@ -65,14 +69,18 @@ __device__ inline void var_residual_tile_f32(
     }
     __syncthreads();
   }
+  // Y at this lane's outputs: every load issued before the first store (clamped addresses;
+  // a load under each store's bounds test would wait for each in turn)
+  float yin[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int64_t t = t0 + wi * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-    const int64_t j = j0 + wj * 32 + (lane & 31);
-    if (t < n_eff && j < m) {
-      const float y = X[colmap[j] + t * ldx] - (float)mu[j];
-      E[t * lde + j] = y - acc[r];
-    }
+    yin[r] = X[offy + (t < n_eff ? t : n_eff - 1) * ldx];
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int64_t t = t0 + wi * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    if (t < n_eff && jo < m) E[t * lde + jo] = (yin[r] - muy) - acc[r];
   }
 }
 
@@ -248,19 +256,32 @@ __device__ inline void var_residual_tile_f64w(
     }
     __syncthreads();
   }
+  // Y at this lane's outputs: every load issued before the first store (clamped addresses)
+  float yin[XB][2][4];
 #pragma unroll
-  for (int x = 0; x < XB; ++x)
+  for (int y = 0; y < 2; ++y) {
+    const int64_t j = j0 + wj * 32 + y * 16 + li;
+    const int64_t offy = colmap[j < m ? j : 0];
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
+    for (int x = 0; x < XB; ++x)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t t = t0 + wi * (RT / 2) + x * 16 + lk + 4 * r;     // f64 D layout
-        const int64_t j = j0 + wj * 32 + y * 16 + li;
-        if (t < n_eff && j < m) {
-          const double yv = (double)X[colmap[j] + t * ldx] - mu[j];
-          E[t * lde + j] = (TOut)(yv - acc[x][y][r]);
-        }
+        yin[x][y][r] = X[offy + (t < n_eff ? t : n_eff - 1) * ldx];
       }
+  }
+#pragma unroll
+  for (int y = 0; y < 2; ++y) {
+    const int64_t j = j0 + wj * 32 + y * 16 + li;
+    const double muy = mu[j < m ? j : 0];
+#pragma unroll
+    for (int x = 0; x < XB; ++x)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t t = t0 + wi * (RT / 2) + x * 16 + lk + 4 * r;
+        if (t < n_eff && j < m) E[t * lde + j] = (TOut)(((double)yin[x][y][r] - muy) - acc[x][y][r]);
+      }
+  }
 }
 
 }  // namespace vl
