@@ -295,16 +295,24 @@ void slc_gram_kernel(
   const int wi = wave >> 1, wj = wave & 1, h = lane >> 5, l32 = lane & 31;
   const int64_t kbeg = z * kchunk;
   const int64_t kend = std::min(Kpad, kbeg + kchunk);
+  const int64_t col = j0 + wj * 32 + l32;
+  const int ec = row_exponent(B, col < N ? col : 0);   // read before the products
   v16i acc[kSlices];
   slice_mma<2, 2>(A, i0, B, j0, kbeg, kend, acc);
   double* Pz = P + z * M * N;
-  const int64_t col = j0 + wj * 32 + l32;
   if (col >= N) return;
-  const int ec = row_exponent(B, col);
+  // the row exponents, all read before the first store (clamped rows: a read under each
+  // store's bounds test would wait for each in turn)
+  int ea[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int64_t row = i0 + wi * 32 + 8 * (q >> 2) + 4 * h + (q & 3);
-    if (row < M) Pz[row * N + col] = slice_value(acc, q, row_exponent(A, row) + ec);
+    ea[q] = row_exponent(A, row < M ? row : 0);
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int64_t row = i0 + wi * 32 + 8 * (q >> 2) + 4 * h + (q & 3);
+    if (row < M) Pz[row * N + col] = slice_value(acc, q, ea[q] + ec);
   }
 }
 
@@ -369,13 +377,22 @@ void slc_residual_kernel(
   const int ec = row_exponent(B, j);
   const double muj = mu[j];
   const int64_t cj = colmap[j];
+  // Y and the row exponents (0 for the design's slices, whose rows carry none) at this lane's
+  // outputs: every load issued before the first store (clamped rows)
+  float yin[16];
+  int ea[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int64_t t = i0 + wi * 32 + 8 * (q >> 2) + 4 * h + (q & 3);
-    if (t < n_eff) {
-      const double y = (double)X[cj + t * ldx] - muj;
-      E[t * lde + j] = (TOut)(y - slice_value(acc, q, row_exponent(A, t) + ec));
-    }
+    const int64_t tc = t < n_eff ? t : n_eff - 1;
+    yin[q] = X[cj + tc * ldx];
+    ea[q] = row_exponent(A, tc);
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int64_t t = i0 + wi * 32 + 8 * (q >> 2) + 4 * h + (q & 3);
+    if (t < n_eff)
+      E[t * lde + j] = (TOut)(((double)yin[q] - muj) - slice_value(acc, q, ea[q] + ec));
   }
 }
 
