@@ -47,16 +47,17 @@ __device__ inline void gram_tile_f32(
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc64[r] = 0.0;
 
-  // register prefetch of the next stage overlaps its loads with this stage's MFMAs
+  // register prefetch of the next stage overlaps its loads with this stage's MFMAs: the raw
+  // values are held, and centred and masked when they are stored to LDS (an operation on a
+  // loaded value right after its load would wait for it before the MFMAs)
   float ra[kGK / 4], rb[kGK / 4];
   auto load = [&](int64_t k0) {
 #pragma unroll
     for (int r = 0; r < kGK / 4; ++r) {
       const int64_t t = k0 + rg + 4 * r;
-      const bool in = t < ke;
-      const int64_t tc = in ? t : ke - 1;         // clamped, in bounds; padding masked below
-      ra[r] = mask_f32(pa[tc * lda] - ma, va && in);
-      rb[r] = mask_f32(pb[tc * ldb] - mb, vb && in);
+      const int64_t tc = t < ke ? t : ke - 1;     // clamped, in bounds; padding masked below
+      ra[r] = pa[tc * lda];
+      rb[r] = pb[tc * ldb];
     }
   };
   load(kb);
@@ -64,8 +65,9 @@ __device__ inline void gram_tile_f32(
   for (int64_t k0 = kb; k0 < ke; k0 += kGK, ++stage) {
 #pragma unroll
     for (int r = 0; r < kGK / 4; ++r) {
-      As[(rg + 4 * r) * kGLd + cc] = ra[r];
-      Bs[(rg + 4 * r) * kGLd + cc] = rb[r];
+      const bool in = k0 + rg + 4 * r < ke;
+      As[(rg + 4 * r) * kGLd + cc] = mask_f32(ra[r] - ma, va && in);
+      Bs[(rg + 4 * r) * kGLd + cc] = mask_f32(rb[r] - mb, vb && in);
     }
     __syncthreads();
     if (k0 + kGK < ke) load(k0 + kGK);
