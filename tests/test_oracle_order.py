@@ -34,6 +34,24 @@ def test_ties_go_to_lowest_index_and_margin_zero():
     assert np.all(margin[:-1] == 0.0)
 
 
+def test_duplicated_variables_tie_at_every_pair():
+    """Variables 2i and 2i+1 with identical rows and columns of S (their pair scores 0) keep equal
+    M at every step while both are candidates, so the lowest-index rule takes 2i first and the
+    step that takes it has margin exactly 0."""
+    h = 30
+    rng = np.random.default_rng(7)
+    A = rng.normal(size=(h, h))
+    A = A - A.T
+    S = np.kron(A, np.ones((2, 2)))
+    for i in range(h):
+        S[2 * i, 2 * i + 1] = S[2 * i + 1, 2 * i] = 0.0
+    order, margin = O.approx_order(S)
+    pos = np.empty(2 * h, int)
+    pos[order] = np.arange(2 * h)
+    assert np.all(pos[0::2] < pos[1::2])
+    assert np.all(margin[pos[0::2]] == 0.0)
+
+
 def test_pure_python_loop_form_small():
     """Alg. 1 written as explicit loops over U (tiny m), compared element by element."""
     rng = np.random.default_rng(4)
